@@ -1,0 +1,196 @@
+/*
+ * mctune.h -- C ABI of the MI355X explicit-state auto-tuning checker.
+ *
+ * The method (Garanina, Staroletov, Gorlatch, "Auto-Tuning High-Performance Programs
+ * Using Model Checking in Promela"): a timed model of an OpenCL kernel on an abstract
+ * platform picks its tuning parameters nondeterministically (Sec. 4, Step 1, the
+ * `main` process of Listing 3); the over-time property G(FIN -> time > T) (Sec. 4,
+ * Step 2) fails exactly when some run terminates with time <= T; the least such T
+ * (Sec. 2, Fig. 1 and Step 3) and the parameter values on a counterexample path
+ * (Step 4) are the tuning result.  This library answers those queries by exhaustive
+ * explicit-state exploration on the GPU.
+ *
+ * Model (one descriptor = one kernel, one platform, a list of configurations):
+ *   state       (cfg, clock, pending, rem[0..m-1]); rem_i = cycles left in the
+ *               workgroup on compute unit i, 0 = idle; a distinguished root.
+ *   SELECT(c)   root -> (c, 0, n_c, 0,..,0) for every configuration c.
+ *   DISPATCH(i) pending > 0 and rem_i = 0: rem_i := d_c, pending -= 1; no time passes
+ *               (host/device/unit hand-off of Listings 4-6).  One successor per free
+ *               unit.
+ *   ADVANCE     only when no DISPATCH is enabled and a unit is busy: the clock moves
+ *               to the next operation end of any busy unit (the clock process of
+ *               Listing 9 ticks when every active PE has reported its unit of work,
+ *               Listing 8).
+ *   terminal    pending = 0 and all units idle (FIN, Listing 4); its clock is the
+ *               model time of the run.
+ *   Operation lists per workgroup (global loads at Lg, local steps at Ll, barriers
+ *   at Lb -- free by default, as the barrier process of Listing 7 never advances
+ *   time -- compute at Lc):
+ *     MC_KIND_REDUCTION (WG, TS):        n = G/WG; ceil(G/(WG*TS)) x Lg,
+ *                                        log2(WG) x Ll, 1 x Lb, TS x Lc.
+ *     MC_KIND_MATMUL (WGx, WGy, TS, VW): n = (M/WGx)(N/(WGy*VW)); 2K x Lg,
+ *                                        K(1+VW) x Ll, 2K/TS x Lb, K*VW x Lc.
+ *   d_c is the workgroup duration; E_c the distinct cumulative operation end times.
+ *
+ * Conventions.  Every call returns an int: MC_OK (0) or a negative MC_E_* code; no
+ * call aborts and no C++ exception crosses the ABI.  Device pointers are plain
+ * hipMalloc'd (or torch-allocated) device addresses; host pointers are ordinary host
+ * memory.  A model handle is not thread-safe; separate handles on separate streams
+ * may run concurrently.  Query calls are synchronous with respect to the host: they
+ * enqueue on the handle's stream and wait for it.
+ */
+#ifndef MCTUNE_H
+#define MCTUNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------------- */
+#define MC_OK 0
+#define MC_E_INVAL (-1)      /* invalid descriptor, option or argument */
+#define MC_E_NOMEM (-2)      /* workspace smaller than mc_workspace_bytes() */
+#define MC_E_DEVICE (-3)     /* a HIP runtime call failed */
+#define MC_E_TABLE_FULL (-4) /* visited-set capacity exceeded (reload with more slots) */
+#define MC_E_BUFFER (-5)     /* output buffer too small; the needed size is returned */
+#define MC_E_STATE (-6)      /* no query has produced what was asked for */
+#define MC_E_OVERFLOW (-7)   /* a frontier or a packed field exceeded its bound */
+#define MC_E_ADMIT (-8)      /* a query can never fit the engine's memory budget */
+#define MC_E_NOTFOUND (-9)   /* no such ticket / state */
+
+/* ---- model descriptor ---------------------------------------------------------- */
+#define MC_KIND_REDUCTION 0u
+#define MC_KIND_MATMUL 1u
+
+#define MC_MAX_CU 8u         /* compute units per model */
+
+typedef struct mc_desc {
+    uint32_t kind;           /* MC_KIND_REDUCTION or MC_KIND_MATMUL */
+    uint32_t n_cu;           /* m, 1..MC_MAX_CU */
+    uint32_t size[3];        /* reduction: {G, 0, 0}; matmul: {M, N, K} */
+    uint32_t lat_global;     /* Lg >= 1 */
+    uint32_t lat_local;      /* Ll >= 1 */
+    uint32_t lat_compute;    /* Lc >= 1 */
+    uint32_t lat_barrier;    /* Lb >= 0 */
+    uint32_t n_cfg;          /* number of configurations, >= 1 */
+    const uint32_t *params;  /* host pointer, n_cfg rows of 4: reduction (WG, TS, 0, 0),
+                                matmul (WGx, WGy, TS, VW); VW = 0 means 1.  Powers of
+                                two; sizes must divide as the operation lists require. */
+} mc_desc;
+
+/* ---- options ------------------------------------------------------------------- */
+#define MC_ENGINE_SUPERSTEP 0u /* persistent kernel, one configuration's subgraph per
+                                  workgroup, zero-time closures and lock-step runs
+                                  expanded in one super-step */
+#define MC_ENGINE_LEVEL 1u     /* plain level-synchronous BFS, one launch per level */
+
+typedef struct mc_opts {
+    uint32_t engine;         /* MC_ENGINE_* */
+    uint32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = default) */
+    uint32_t log2_slots;     /* visited-set capacity 2^log2_slots (0 = from load_factor) */
+    float load_factor;       /* target states/slots when sizing (0 = 0.5) */
+    uint32_t grid;           /* persistent workgroups (0 = automatic) */
+    uint32_t reserved[3];
+} mc_opts;
+
+/* ---- statistics of the last query ---------------------------------------------- */
+typedef struct mc_stats {
+    uint64_t states;         /* unique states (root included); count_T for mc_check */
+    uint64_t levels;         /* BFS levels = deepest state's depth + 1 */
+    uint64_t terminals;      /* unique terminal states */
+    uint64_t edges;          /* successor generations performed (engine-specific) */
+    uint64_t dups;           /* inserts that found the state present (engine-specific) */
+    uint64_t probes;         /* hash-slot probes (engine-specific) */
+    uint64_t launches;       /* kernel launches of the exploration */
+    uint64_t explore_ns;     /* GPU time of the exploration kernels (HIP events) */
+    uint64_t total_ns;       /* host wall time of the query call */
+    uint64_t clear_ns;       /* GPU time clearing the visited set */
+} mc_stats;
+
+typedef struct mc_model_info {
+    uint32_t n_cu, n_cfg;
+    uint32_t key_words;      /* packed key width in 64-bit words: 1, 2 or 4 */
+    uint32_t key_bits;       /* bits actually used */
+    uint64_t slots;          /* visited-set capacity */
+    uint64_t slot_bytes;     /* bytes per visited-set slot */
+    uint64_t bound_states;   /* reachable-state count the workspace was sized for */
+    uint64_t max_depth;      /* longest path length (sizes the trace buffer) */
+} mc_model_info;
+
+typedef struct mc_model mc_model;
+
+/* Bytes of device workspace a model needs (visited set, frontiers, tables, counters).
+ * The visited set is sized from the exact reachable-state count of the lock-step
+ * round structure and the load factor.  Pure host computation.
+ * MC_E_INVAL: invalid descriptor (sizes not powers of two or not divisible, empty
+ * domain, latencies out of range, packed state wider than 256 bits, clock above 2^32). */
+int mc_workspace_bytes(const mc_desc *d, const mc_opts *o, size_t *bytes);
+
+/* Reachable-state count of the model (root included), its longest path, and the packed
+ * key width, without touching the GPU. */
+int mc_describe(const mc_desc *d, uint64_t *states, uint64_t *max_depth, uint32_t *key_words);
+
+/* Load a model: validates, derives per-configuration tables, uploads them into
+ * the caller's workspace and binds the stream.  dev_ws: device memory of ws_bytes
+ * bytes owned by the caller, kept alive until mc_model_free.  stream: hipStream_t
+ * (NULL = default stream).  The library owns *out.
+ * MC_E_NOMEM if ws_bytes < mc_workspace_bytes(); MC_E_DEVICE wraps a HIP error. */
+int mc_model_load(const mc_desc *d, const mc_opts *o, void *dev_ws, size_t ws_bytes,
+                  void *stream, mc_model **out);
+
+int mc_model_free(mc_model *h);
+int mc_model_info_get(const mc_model *h, mc_model_info *info);
+
+/* min_time (Sec. 2 steps 3-4 in one pass; the single-run optimum of Sec. 8): explore
+ * every reachable state, reduce the terminal clocks per configuration, return
+ * T_min and the configurations attaining it in ascending order.  argmin may be NULL
+ * with cap 0 to query *n_argmin; MC_E_BUFFER if cap < *n_argmin (the rest is valid).
+ * st may be NULL. */
+int mc_min_time(mc_model *h, uint32_t *t_min, uint32_t *argmin, size_t cap,
+                size_t *n_argmin, mc_stats *st);
+
+/* check(T): exhaustive exploration of the states with clock <= T (the clock never
+ * decreases along a transition, so pruning at T is exact).  *violated = 1 iff some
+ * terminal has clock <= T, i.e. G(FIN -> time > T) fails (Sec. 4, Step 2).
+ * st->states = count of states with clock <= T. */
+int mc_check(mc_model *h, uint32_t T, int *violated, mc_stats *st);
+
+/* Per-configuration least terminal clock of the last query (UINT32_MAX = none reached
+ * under its threshold).  tc: host array of cap >= n_cfg entries. */
+int mc_terminal_clocks(const mc_model *h, uint32_t *tc, size_t cap);
+
+/* Counterexample of the last query (Sec. 4, Step 4): the path root -> ... -> terminal
+ * of the smallest configuration attaining T_min (after mc_min_time) or of the smallest
+ * configuration with a terminal clock <= T (after a violated mc_check).  Rows of
+ * (3 + n_cu) uint32 values: cfg (UINT32_MAX for the root), clock, pending,
+ * rem_0..rem_{m-1}; root first.  rows may be NULL with cap 0 to query *len.
+ * MC_E_STATE if no query ran or the last check held; MC_E_BUFFER if cap < *len. */
+int mc_trace(mc_model *h, uint32_t *rows, size_t cap, size_t *len);
+
+/* One seeded random run to termination (simulation mode, Sec. 2 and Step 3): uniform
+ * choice among the successors at every step, choices drawn from splitmix64 of
+ * (seed, step).  Returns the terminal clock and the configuration selected. */
+int mc_simulate(mc_model *h, uint64_t seed, uint32_t *t_end, uint32_t *cfg);
+
+/* The search of Sec. 2 (Fig. 1) and Step 3: T_ini from mc_simulate(seed), then integer
+ * bisection keeping check(lo) holding and check(hi) failing, lo = 0.  Returns T_min,
+ * the number of check calls, and leaves the trace of the last failing check. */
+int mc_tune_bisect(mc_model *h, uint64_t seed, uint32_t *t_min, uint32_t *n_checks,
+                   mc_stats *st);
+
+/* Select the exploration engine used by later queries (MC_ENGINE_*); both engines
+ * compute identical results. */
+int mc_set_engine(mc_model *h, uint32_t engine);
+
+/* Parameters of configuration cfg (4 values, as in the descriptor). */
+int mc_config(const mc_model *h, uint32_t cfg, uint32_t *params4);
+
+const char *mc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCTUNE_H */

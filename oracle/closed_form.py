@@ -51,13 +51,14 @@ def end_times(oplist) -> list[int]:
     return out
 
 
-def per_config(model: dict) -> list[dict]:
+def per_config(model: dict, with_E: bool = True) -> list[dict]:
     m = model["m"]
     res = []
     for row in model["params"]:
         n, ol = ops(model, row)
-        E = end_times(ol)
-        b, d = len(E), E[-1]
+        E = end_times(ol) if with_E else None
+        b = sum(cnt for cnt, lat in ol if lat > 0)
+        d = sum(cnt * lat for cnt, lat in ol)
         q, p = divmod(n, m)
         rounds = -(-n // m)
         count = 1 + q * ((1 << m) - 1 + b)
@@ -68,8 +69,8 @@ def per_config(model: dict) -> list[dict]:
     return res
 
 
-def summary(model: dict) -> dict:
-    pc = per_config(model)
+def summary(model: dict, with_E: bool = True) -> dict:
+    pc = per_config(model, with_E)
     tcs = [c["tc"] for c in pc]
     t_min = min(tcs)
     return {"reachable": 1 + sum(c["count"] for c in pc),

@@ -1,0 +1,256 @@
+"""Python binding of libmctune, the MI355X explicit-state auto-tuning checker.
+
+Argument marshalling only: every step of the exploration runs in the HIP kernels of
+``csrc/``.  PyTorch provides the device workspace and the stream.  The C names
+(``mc_*``) are exposed one-to-one; ``Model`` bundles a loaded model with its workspace.
+
+Importing the package never falls back to anything: if ``libmctune.so`` has not been
+built the import raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmctune.so")
+
+MC_OK = 0
+MC_E_INVAL, MC_E_NOMEM, MC_E_DEVICE, MC_E_TABLE_FULL = -1, -2, -3, -4
+MC_E_BUFFER, MC_E_STATE, MC_E_OVERFLOW, MC_E_ADMIT, MC_E_NOTFOUND = -5, -6, -7, -8, -9
+MC_KIND_REDUCTION, MC_KIND_MATMUL = 0, 1
+MC_ENGINE_SUPERSTEP, MC_ENGINE_LEVEL = 0, 1
+MC_MAX_CU = 8
+ROOT = 0xFFFFFFFF
+NO_CLOCK = 0xFFFFFFFF
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2305_09130_amd/build.py "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class McDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("n_cu", ctypes.c_uint32),
+                ("size", ctypes.c_uint32 * 3), ("lat_global", ctypes.c_uint32),
+                ("lat_local", ctypes.c_uint32), ("lat_compute", ctypes.c_uint32),
+                ("lat_barrier", ctypes.c_uint32), ("n_cfg", ctypes.c_uint32),
+                ("params", _u32p)]
+
+
+class McOpts(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("log2_slots", ctypes.c_uint32), ("load_factor", ctypes.c_float),
+                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
+class McStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("states", "levels", "terminals", "edges", "dups", "probes", "launches",
+                 "explore_ns", "total_ns", "clear_ns")]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class McModelInfo(ctypes.Structure):
+    _fields_ = [("n_cu", ctypes.c_uint32), ("n_cfg", ctypes.c_uint32),
+                ("key_words", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
+                ("slots", ctypes.c_uint64), ("slot_bytes", ctypes.c_uint64),
+                ("bound_states", ctypes.c_uint64), ("max_depth", ctypes.c_uint64)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_SIGS = {
+    "mc_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "mc_describe": ([_P(McDesc), _u64p, _u64p, _u32p], ctypes.c_int),
+    "mc_workspace_bytes": ([_P(McDesc), _P(McOpts), _P(ctypes.c_size_t)], ctypes.c_int),
+    "mc_model_load": ([_P(McDesc), _P(McOpts), _vp, ctypes.c_size_t, _vp, _P(_vp)], ctypes.c_int),
+    "mc_model_free": ([_vp], ctypes.c_int),
+    "mc_model_info_get": ([_vp, _P(McModelInfo)], ctypes.c_int),
+    "mc_set_engine": ([_vp, ctypes.c_uint32], ctypes.c_int),
+    "mc_min_time": ([_vp, _u32p, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t), _P(McStats)],
+                    ctypes.c_int),
+    "mc_check": ([_vp, ctypes.c_uint32, _P(ctypes.c_int), _P(McStats)], ctypes.c_int),
+    "mc_terminal_clocks": ([_vp, _u32p, ctypes.c_size_t], ctypes.c_int),
+    "mc_trace": ([_vp, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t)], ctypes.c_int),
+    "mc_simulate": ([_vp, ctypes.c_uint64, _u32p, _u32p], ctypes.c_int),
+    "mc_tune_bisect": ([_vp, ctypes.c_uint64, _u32p, _u32p, _P(McStats)], ctypes.c_int),
+    "mc_config": ([_vp, ctypes.c_uint32, _u32p], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class McError(RuntimeError):
+    def __init__(self, where: str, code: int):
+        super().__init__(f"{where}: {mc_strerror(code)} ({code})")
+        self.code = code
+
+
+def mc_strerror(code: int) -> str:
+    return _lib.mc_strerror(code).decode()
+
+
+def _check(where: str, rc: int) -> None:
+    if rc != MC_OK:
+        raise McError(where, rc)
+
+
+def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
+    """McDesc of a model dict (see workloads); returns the params array to keep alive."""
+    params = np.ascontiguousarray(np.asarray(model["params"], dtype=np.uint32).reshape(-1, 4))
+    d = McDesc()
+    if model["kind"] == "reduction":
+        d.kind = MC_KIND_REDUCTION
+        d.size[0], d.size[1], d.size[2] = model["G"], 0, 0
+    else:
+        d.kind = MC_KIND_MATMUL
+        d.size[0], d.size[1], d.size[2] = model["M"], model["N"], model["K"]
+    d.n_cu = model["m"]
+    d.lat_global, d.lat_local = model["Lg"], model["Ll"]
+    d.lat_compute, d.lat_barrier = model["Lc"], model["Lb"]
+    d.n_cfg = params.shape[0]
+    d.params = params.ctypes.data_as(_u32p)
+    return d, params
+
+
+def make_opts(engine: int = MC_ENGINE_SUPERSTEP, block: int = 0, log2_slots: int = 0,
+              load_factor: float = 0.0, grid: int = 0) -> McOpts:
+    o = McOpts()
+    o.engine, o.block, o.log2_slots, o.load_factor, o.grid = engine, block, log2_slots, \
+        load_factor, grid
+    return o
+
+
+def mc_describe(model: dict) -> dict:
+    d, keep = make_desc(model)
+    s, dep, w = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
+    _check("mc_describe", _lib.mc_describe(ctypes.byref(d), ctypes.byref(s), ctypes.byref(dep),
+                                           ctypes.byref(w)))
+    return {"states": s.value, "max_depth": dep.value, "key_words": w.value}
+
+
+def state_count(model: dict) -> int | None:
+    """Reachable-state count of a model, or None if the library cannot represent it
+    (invalid sizes, clocks beyond 32 bits, keys beyond 256 bits)."""
+    try:
+        return mc_describe(model)["states"]
+    except McError:
+        return None
+
+
+def mc_workspace_bytes(model: dict, opts: McOpts | None = None) -> int:
+    d, keep = make_desc(model)
+    n = ctypes.c_size_t()
+    _check("mc_workspace_bytes",
+           _lib.mc_workspace_bytes(ctypes.byref(d), ctypes.byref(opts) if opts else None,
+                                   ctypes.byref(n)))
+    return n.value
+
+
+class Model:
+    """A model loaded on the GPU with its own workspace (a torch uint8 tensor)."""
+
+    def __init__(self, model: dict, engine: int = MC_ENGINE_SUPERSTEP, block: int = 0,
+                 log2_slots: int = 0, load_factor: float = 0.0, grid: int = 0,
+                 device: str = "cuda:0", stream=None):
+        import torch
+        self.model = model
+        self.m = model["m"]
+        self.n_cfg = len(model["params"])
+        self._desc, self._params = make_desc(model)
+        self._opts = make_opts(engine, block, log2_slots, load_factor, grid)
+        nbytes = mc_workspace_bytes(model, self._opts)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check("mc_model_load",
+               _lib.mc_model_load(ctypes.byref(self._desc), ctypes.byref(self._opts),
+                                  ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.last_stats: dict = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.mc_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def mc_model_info_get(self) -> dict:
+        info = McModelInfo()
+        _check("mc_model_info_get", _lib.mc_model_info_get(self._h, ctypes.byref(info)))
+        return {n: int(getattr(info, n)) for n, _ in info._fields_}
+
+    def mc_set_engine(self, engine: int) -> None:
+        _check("mc_set_engine", _lib.mc_set_engine(self._h, engine))
+
+    def mc_min_time(self) -> tuple[int, list[int]]:
+        t = ctypes.c_uint32()
+        n = ctypes.c_size_t()
+        st = McStats()
+        arg = np.zeros(self.n_cfg, dtype=np.uint32)
+        _check("mc_min_time", _lib.mc_min_time(self._h, ctypes.byref(t),
+                                               arg.ctypes.data_as(_u32p), arg.shape[0],
+                                               ctypes.byref(n), ctypes.byref(st)))
+        self.last_stats = st.as_dict()
+        return t.value, [int(v) for v in arg[:n.value]]
+
+    def mc_check(self, T: int) -> bool:
+        v = ctypes.c_int()
+        st = McStats()
+        _check("mc_check", _lib.mc_check(self._h, int(T), ctypes.byref(v), ctypes.byref(st)))
+        self.last_stats = st.as_dict()
+        return bool(v.value)
+
+    def mc_terminal_clocks(self) -> list[int | None]:
+        tc = np.zeros(self.n_cfg, dtype=np.uint32)
+        _check("mc_terminal_clocks",
+               _lib.mc_terminal_clocks(self._h, tc.ctypes.data_as(_u32p), tc.shape[0]))
+        return [None if int(v) == NO_CLOCK else int(v) for v in tc]
+
+    def mc_trace(self) -> np.ndarray:
+        n = ctypes.c_size_t()
+        _check("mc_trace", _lib.mc_trace(self._h, None, 0, ctypes.byref(n)))
+        rows = np.zeros((n.value, 3 + self.m), dtype=np.uint32)
+        _check("mc_trace", _lib.mc_trace(self._h, rows.ctypes.data_as(_u32p), n.value,
+                                         ctypes.byref(n)))
+        return rows
+
+    def mc_simulate(self, seed: int) -> tuple[int, int]:
+        t, c = ctypes.c_uint32(), ctypes.c_uint32()
+        _check("mc_simulate", _lib.mc_simulate(self._h, seed, ctypes.byref(t), ctypes.byref(c)))
+        return t.value, c.value
+
+    def mc_tune_bisect(self, seed: int) -> tuple[int, int]:
+        t, n = ctypes.c_uint32(), ctypes.c_uint32()
+        st = McStats()
+        _check("mc_tune_bisect", _lib.mc_tune_bisect(self._h, seed, ctypes.byref(t),
+                                                     ctypes.byref(n), ctypes.byref(st)))
+        self.last_stats = st.as_dict()
+        return t.value, n.value
+
+    def mc_config(self, cfg: int) -> list[int]:
+        p = np.zeros(4, dtype=np.uint32)
+        _check("mc_config", _lib.mc_config(self._h, cfg, p.ctypes.data_as(_u32p)))
+        return [int(v) for v in p]
+
+
+def exported_symbols() -> list[str]:
+    """Names declared in include/mctune.h (the ABI test checks they are exported)."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "mctune.h")
+    text = open(hdr).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(mc_\w+)\s*\(", text, re.M)))

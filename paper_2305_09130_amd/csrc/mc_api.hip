@@ -1,0 +1,594 @@
+// mc_api.hip -- the C ABI: workspace planning, model load, query drivers (min_time,
+// check(T), bisection), counterexample decoding and simulation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mctune.h"
+#include "mc_launch.h"
+#include "mc_model.h"
+
+using namespace mc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+struct WsPlan {
+  size_t ctrl = 0, tc = 0, cfgs = 0, order = 0, seeds = 0, front0 = 0, front1 = 0, trace = 0,
+         table = 0, total = 0;
+  uint64_t slots = 0;
+  uint32_t slot_bytes = 0;
+  uint64_t fcap = 0;
+  uint64_t trace_cap = 0;
+  size_t table_bytes = 0;
+};
+
+uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
+
+int plan_ws(const ModelHost& mh, const mc_opts& o, WsPlan* p) {
+  uint64_t slots;
+  if (o.log2_slots) {
+    if (o.log2_slots < 4 || o.log2_slots > 31) return MC_E_INVAL;
+    slots = 1ull << o.log2_slots;
+  } else {
+    const double lf = (o.load_factor > 0.f && o.load_factor < 1.f) ? o.load_factor : 0.5;
+    slots = next_pow2((uint64_t)((double)mh.states / lf) + 1);
+    slots = std::max<uint64_t>(slots, 1024);
+    if (slots > (1ull << 31)) return MC_E_INVAL;
+  }
+  const uint32_t W = mh.W;
+  const size_t entry = 8ull * W + 8ull;
+  size_t off = 0;
+  p->ctrl = off;   off = align_up(off + sizeof(Ctrl));
+  p->tc = off;     off = align_up(off + 4ull * mh.n_cfg);
+  p->cfgs = off;   off = align_up(off + sizeof(CfgRec) * mh.n_cfg);
+  p->order = off;  off = align_up(off + 4ull * mh.n_cfg);
+  p->seeds = off;  off = align_up(off + sizeof(Seed) * mh.n_cfg);
+  p->fcap = mh.frontier_bound + 64;
+  p->front0 = off; off = align_up(off + entry * p->fcap);
+  p->front1 = off; off = align_up(off + entry * p->fcap);
+  p->trace_cap = mh.max_depth + 2;
+  p->trace = off;  off = align_up(off + 8ull * W * p->trace_cap);
+  p->slots = slots;
+  p->slot_bytes = slot_bytes_for(W);
+  p->table = off;
+  p->table_bytes = (size_t)slots * p->slot_bytes;
+  off = align_up(off + p->table_bytes);
+  p->total = off;
+  return MC_OK;
+}
+
+mc_opts default_opts(const mc_opts* o) {
+  mc_opts r;
+  std::memset(&r, 0, sizeof(r));
+  if (o) r = *o;
+  if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 256;
+  if (r.engine > MC_ENGINE_LEVEL) r.engine = MC_ENGINE_SUPERSTEP;
+  return r;
+}
+
+void host_encode(const Layout& L, const uint32_t* fields, uint64_t* words) {
+  for (int j = 0; j < 4; ++j) words[j] = 0;
+  for (int f = 0; f < 3 + L.m; ++f) words[L.word[f]] |= (uint64_t)fields[f] << L.shift[f];
+}
+
+void host_decode(const Layout& L, const uint64_t* words, uint32_t* fields) {
+  for (int f = 0; f < 3 + L.m; ++f)
+    fields[f] = (uint32_t)((words[L.word[f]] >> L.shift[f]) & ((1ull << L.width[f]) - 1ull));
+}
+
+int dev_err(unsigned int e) {
+  switch (e) {
+    case 0: return MC_OK;
+    case kDevErrTableFull: return MC_E_TABLE_FULL;
+    case kDevErrOverflow: return MC_E_OVERFLOW;
+    default: return MC_E_DEVICE;
+  }
+}
+
+#define HIPCHK(x)                      \
+  do {                                 \
+    hipError_t e_ = (x);               \
+    if (e_ != hipSuccess) {            \
+      (void)hipGetLastError();         \
+      return MC_E_DEVICE;              \
+    }                                  \
+  } while (0)
+
+}  // namespace
+
+enum { kQueryNone = 0, kQueryMin = 1, kQueryCheck = 2 };
+
+struct mc_model {
+  ModelHost mh;
+  mc_opts opts{};
+  WsPlan plan;
+  hipStream_t stream = nullptr;
+  unsigned char* ws = nullptr;
+  Ctrl* ctrl = nullptr;
+  uint32_t* tc = nullptr;
+  CfgRec* cfgs = nullptr;
+  uint32_t* order = nullptr;
+  Seed* seeds = nullptr;
+  unsigned char* front[2] = {nullptr, nullptr};
+  unsigned long long* trace_buf = nullptr;
+  unsigned char* table = nullptr;
+  Ctrl* hctrl = nullptr;  // pinned host copy
+  uint32_t* hpoll = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool dirty = true;
+  int last = kQueryNone;
+  uint32_t last_T = 0;
+  int last_violated = 0;
+  std::vector<uint32_t> tc_host;
+  bool trace_ready = false;
+  std::vector<uint32_t> trace_rows;
+};
+
+namespace {
+
+QueryArgs make_args(mc_model* h, bool prune, uint32_t T) {
+  QueryArgs q;
+  q.ctrl = h->ctrl;
+  q.tc = h->tc;
+  q.cfgs = h->cfgs;
+  q.table = h->table;
+  q.mask = h->plan.slots - 1;
+  q.L = h->mh.layout;
+  q.n_cfg = h->mh.n_cfg;
+  q.prune = prune ? 1u : 0u;
+  q.T = T;
+  q.max_clock = h->mh.max_clock;
+  return q;
+}
+
+template <int W>
+int explore_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
+  hipStream_t s = h->stream;
+  HIPCHK(launch_seed<W>(s, q, h->seeds, h->front[0]));
+  *launches = 1;
+  if (h->opts.engine == MC_ENGINE_SUPERSTEP) {
+    SuperArgs sa;
+    sa.q = q;
+    sa.order = h->order;
+    sa.seeds = h->seeds;
+    sa.n_parts = h->mh.n_cfg;
+    uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->mh.n_cfg, 4096u);
+    HIPCHK(launch_super<W>(s, grid, h->opts.block, sa));
+    *launches += 1;
+    return MC_OK;
+  }
+  // plain level-synchronous BFS: one launch per level; the frontier size lives on the
+  // device, the host polls it once per batch of launches
+  const uint64_t fcap = h->plan.fcap;
+  uint32_t grid = (uint32_t)std::min<uint64_t>((fcap + kLevelBlock - 1) / kLevelBlock, 256);
+  grid = std::max<uint32_t>(grid, 1);
+  LevelArgs la;
+  la.q = q;
+  la.fcap = (uint32_t)fcap;
+  const uint64_t limit = h->mh.max_depth + 64;
+  const uint32_t batch = 64;
+  uint64_t L = 0;
+  for (;;) {
+    for (uint32_t b = 0; b < batch; ++b, ++L) {
+      la.in_idx = (uint32_t)(L % 3);
+      la.out_idx = (uint32_t)((L + 1) % 3);
+      la.clr_idx = (uint32_t)((L + 2) % 3);
+      HIPCHK(launch_level<W>(s, grid, la, h->front[L % 2], h->front[(L + 1) % 2]));
+    }
+    *launches += batch;
+    HIPCHK(hipMemcpyAsync(h->hpoll, &h->ctrl->fcount[L % 3], 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->hpoll + 1, &h->ctrl->error, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h->hpoll[0] == 0 || h->hpoll[1] != 0) break;
+    if (L > limit) return MC_E_OVERFLOW;
+  }
+  return MC_OK;
+}
+
+int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = h->stream;
+  h->trace_ready = false;
+  h->last = kQueryNone;
+  bool cleared = false;
+  if (h->dirty) {
+    HIPCHK(hipEventRecord(h->ev[0], s));
+    HIPCHK(launch_clear(s, h->table, h->plan.table_bytes));
+    HIPCHK(hipEventRecord(h->ev[1], s));
+    cleared = true;
+  }
+  HIPCHK(launch_reset(s, h->ctrl, h->tc, h->mh.n_cfg));
+  const QueryArgs q = make_args(h, prune, T);
+  HIPCHK(hipEventRecord(h->ev[2], s));
+  uint64_t launches = 0;
+  int rc;
+  switch (h->mh.W) {
+    case 1: rc = explore_w<1>(h, q, &launches); break;
+    case 2: rc = explore_w<2>(h, q, &launches); break;
+    default: rc = explore_w<4>(h, q, &launches); break;
+  }
+  h->dirty = true;
+  if (rc != MC_OK) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  }
+  HIPCHK(hipEventRecord(h->ev[3], s));
+  HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(h->tc_host.data(), h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int derr = dev_err(h->hctrl->error);
+  if (derr != MC_OK) return derr;
+  float ms_explore = 0.f, ms_clear = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms_explore, h->ev[2], h->ev[3]));
+  if (cleared) HIPCHK(hipEventElapsedTime(&ms_clear, h->ev[0], h->ev[1]));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->states = h->hctrl->states;
+    st->levels = h->hctrl->max_depth + 1;
+    st->terminals = h->hctrl->terminals;
+    st->edges = h->hctrl->edges;
+    st->dups = h->hctrl->dups;
+    st->probes = h->hctrl->probes;
+    st->launches = launches;
+    st->explore_ns = (uint64_t)(ms_explore * 1e6);
+    st->clear_ns = (uint64_t)(ms_clear * 1e6);
+    st->total_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                       std::chrono::steady_clock::now() - t0)
+                       .count();
+  }
+  return MC_OK;
+}
+
+template <int W>
+int trace_w(mc_model* h, uint32_t cfg, uint32_t clock) {
+  hipStream_t s = h->stream;
+  uint32_t fields[kFields] = {0};
+  fields[kFCfg] = cfg;
+  fields[kFClock] = clock;
+  uint64_t words[4];
+  host_encode(h->mh.layout, fields, words);
+  const QueryArgs q = make_args(h, false, 0);
+  HIPCHK(launch_find<W>(s, q, reinterpret_cast<const unsigned long long*>(words)));
+  HIPCHK(launch_chase<W>(s, q, h->trace_buf, (uint32_t)h->plan.trace_cap));
+  HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h->hctrl->target_slot == kParentNone) return MC_E_STATE;
+  if (h->hctrl->error == kDevErrTrace) return MC_E_DEVICE;
+  const uint32_t n = h->hctrl->trace_len;
+  std::vector<uint64_t> keys((size_t)n * W);
+  if (n)
+    HIPCHK(hipMemcpyAsync(keys.data(), h->trace_buf, 8ull * W * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const uint32_t m = h->mh.m, S = 3 + m;
+  h->trace_rows.assign((size_t)n * S, 0);
+  for (uint32_t i = 0; i < n; ++i) {
+    uint64_t w[4] = {0, 0, 0, 0};
+    for (int j = 0; j < W; ++j) w[j] = keys[(size_t)(n - 1 - i) * W + j];
+    uint32_t f[kFields];
+    host_decode(h->mh.layout, w, f);
+    uint32_t* row = &h->trace_rows[(size_t)i * S];
+    row[0] = f[kFCfg] == h->mh.n_cfg ? 0xFFFFFFFFu : f[kFCfg];
+    row[1] = f[kFClock];
+    row[2] = f[kFPending];
+    for (uint32_t u = 0; u < m; ++u) row[3 + u] = f[kFRem + u];
+  }
+  h->trace_ready = true;
+  return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mc_strerror(int code) {
+  switch (code) {
+    case MC_OK: return "ok";
+    case MC_E_INVAL: return "invalid descriptor, option or argument";
+    case MC_E_NOMEM: return "workspace too small";
+    case MC_E_DEVICE: return "HIP runtime error";
+    case MC_E_TABLE_FULL: return "visited-set capacity exceeded";
+    case MC_E_BUFFER: return "output buffer too small";
+    case MC_E_STATE: return "no query result for this request";
+    case MC_E_OVERFLOW: return "frontier or packed field overflow";
+    case MC_E_ADMIT: return "query cannot fit the memory budget";
+    case MC_E_NOTFOUND: return "not found";
+    default: return "unknown error";
+  }
+}
+
+int mc_describe(const mc_desc* d, uint64_t* states, uint64_t* max_depth, uint32_t* key_words) {
+  try {
+    ModelHost mh;
+    std::string err;
+    const int rc = build_model(d, &mh, &err);
+    if (rc) return rc;
+    if (states) *states = mh.states;
+    if (max_depth) *max_depth = mh.max_depth;
+    if (key_words) *key_words = mh.W;
+    return MC_OK;
+  } catch (...) {
+    return MC_E_INVAL;
+  }
+}
+
+int mc_workspace_bytes(const mc_desc* d, const mc_opts* o, size_t* bytes) {
+  if (!bytes) return MC_E_INVAL;
+  try {
+    ModelHost mh;
+    std::string err;
+    int rc = build_model(d, &mh, &err);
+    if (rc) return rc;
+    WsPlan p;
+    rc = plan_ws(mh, default_opts(o), &p);
+    if (rc) return rc;
+    *bytes = p.total;
+    return MC_OK;
+  } catch (...) {
+    return MC_E_INVAL;
+  }
+}
+
+int mc_model_free(mc_model* h) {
+  if (!h) return MC_E_INVAL;
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->hctrl) (void)hipHostFree(h->hctrl);
+  if (h->hpoll) (void)hipHostFree(h->hpoll);
+  delete h;
+  return MC_OK;
+}
+
+int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes, void* stream,
+                  mc_model** out) {
+  if (!out || !dev_ws) return MC_E_INVAL;
+  *out = nullptr;
+  mc_model* h = nullptr;
+  try {
+    h = new mc_model();
+    std::string err;
+    int rc = build_model(d, &h->mh, &err);
+    if (rc) {
+      delete h;
+      return rc;
+    }
+    h->opts = default_opts(o);
+    rc = plan_ws(h->mh, h->opts, &h->plan);
+    if (rc) {
+      delete h;
+      return rc;
+    }
+    if (ws_bytes < h->plan.total) {
+      delete h;
+      return MC_E_NOMEM;
+    }
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    h->ws = reinterpret_cast<unsigned char*>(dev_ws);
+    h->ctrl = reinterpret_cast<Ctrl*>(h->ws + h->plan.ctrl);
+    h->tc = reinterpret_cast<uint32_t*>(h->ws + h->plan.tc);
+    h->cfgs = reinterpret_cast<CfgRec*>(h->ws + h->plan.cfgs);
+    h->order = reinterpret_cast<uint32_t*>(h->ws + h->plan.order);
+    h->seeds = reinterpret_cast<Seed*>(h->ws + h->plan.seeds);
+    h->front[0] = h->ws + h->plan.front0;
+    h->front[1] = h->ws + h->plan.front1;
+    h->trace_buf = reinterpret_cast<unsigned long long*>(h->ws + h->plan.trace);
+    h->table = h->ws + h->plan.table;
+    h->tc_host.assign(h->mh.n_cfg, kNoClock);
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->hctrl), sizeof(Ctrl), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 64, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      mc_model_free(h);
+      return MC_E_DEVICE;
+    }
+    for (auto& e : h->ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        mc_model_free(h);
+        return MC_E_DEVICE;
+      }
+    }
+    // partitions, largest subgraph first
+    std::vector<uint32_t> order(h->mh.n_cfg);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      return h->mh.cfg_states[a] > h->mh.cfg_states[b];
+    });
+    hipStream_t s = h->stream;
+    if (hipMemcpyAsync(h->cfgs, h->mh.cfgs.data(), sizeof(CfgRec) * h->mh.n_cfg,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->order, order.data(), 4ull * h->mh.n_cfg, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipGetLastError();
+      mc_model_free(h);
+      return MC_E_DEVICE;
+    }
+    h->dirty = true;
+    *out = h;
+    return MC_OK;
+  } catch (const std::bad_alloc&) {
+    if (h) mc_model_free(h);
+    return MC_E_NOMEM;
+  } catch (...) {
+    if (h) mc_model_free(h);
+    return MC_E_INVAL;
+  }
+}
+
+int mc_model_info_get(const mc_model* h, mc_model_info* info) {
+  if (!h || !info) return MC_E_INVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->n_cu = h->mh.m;
+  info->n_cfg = h->mh.n_cfg;
+  info->key_words = h->mh.W;
+  info->key_bits = h->mh.layout.used_bits;
+  info->slots = h->plan.slots;
+  info->slot_bytes = h->plan.slot_bytes;
+  info->bound_states = h->mh.states;
+  info->max_depth = h->mh.max_depth;
+  return MC_OK;
+}
+
+int mc_set_engine(mc_model* h, uint32_t engine) {
+  if (!h || engine > MC_ENGINE_LEVEL) return MC_E_INVAL;
+  h->opts.engine = engine;
+  return MC_OK;
+}
+
+int mc_min_time(mc_model* h, uint32_t* t_min, uint32_t* argmin, size_t cap, size_t* n_argmin,
+                mc_stats* st) {
+  if (!h || !t_min || !n_argmin) return MC_E_INVAL;
+  try {
+    const int rc = run_query(h, false, 0, st);
+    if (rc) return rc;
+    uint32_t best = kNoClock;
+    for (uint32_t v : h->tc_host) best = std::min(best, v);
+    if (best == kNoClock) return MC_E_STATE;
+    size_t n = 0;
+    for (uint32_t c = 0; c < h->mh.n_cfg; ++c) {
+      if (h->tc_host[c] != best) continue;
+      if (argmin && n < cap) argmin[n] = c;
+      ++n;
+    }
+    *t_min = best;
+    *n_argmin = n;
+    h->last = kQueryMin;
+    h->last_T = best;
+    return n > cap && argmin ? MC_E_BUFFER : MC_OK;
+  } catch (...) {
+    return MC_E_DEVICE;
+  }
+}
+
+int mc_check(mc_model* h, uint32_t T, int* violated, mc_stats* st) {
+  if (!h || !violated) return MC_E_INVAL;
+  try {
+    const int rc = run_query(h, true, T, st);
+    if (rc) return rc;
+    *violated = h->hctrl->violated ? 1 : 0;
+    h->last = kQueryCheck;
+    h->last_T = T;
+    h->last_violated = *violated;
+    return MC_OK;
+  } catch (...) {
+    return MC_E_DEVICE;
+  }
+}
+
+int mc_terminal_clocks(const mc_model* h, uint32_t* tc, size_t cap) {
+  if (!h || !tc) return MC_E_INVAL;
+  if (h->last == kQueryNone) return MC_E_STATE;
+  if (cap < h->mh.n_cfg) return MC_E_BUFFER;
+  std::memcpy(tc, h->tc_host.data(), 4ull * h->mh.n_cfg);
+  return MC_OK;
+}
+
+int mc_trace(mc_model* h, uint32_t* rows, size_t cap, size_t* len) {
+  if (!h || !len) return MC_E_INVAL;
+  try {
+    if (!h->trace_ready) {
+      if (h->last == kQueryNone) return MC_E_STATE;
+      if (h->last == kQueryCheck && !h->last_violated) return MC_E_STATE;
+      uint32_t cfg = kNoClock;
+      for (uint32_t c = 0; c < h->mh.n_cfg; ++c) {
+        if (h->tc_host[c] == kNoClock) continue;
+        if (h->last == kQueryMin && h->tc_host[c] != h->last_T) continue;
+        if (h->last == kQueryCheck && h->tc_host[c] > h->last_T) continue;
+        cfg = c;
+        break;
+      }
+      if (cfg == kNoClock) return MC_E_STATE;
+      int rc;
+      switch (h->mh.W) {
+        case 1: rc = trace_w<1>(h, cfg, h->tc_host[cfg]); break;
+        case 2: rc = trace_w<2>(h, cfg, h->tc_host[cfg]); break;
+        default: rc = trace_w<4>(h, cfg, h->tc_host[cfg]); break;
+      }
+      if (rc) return rc;
+    }
+    const size_t S = 3 + h->mh.m;
+    const size_t n = h->trace_rows.size() / S;
+    *len = n;
+    if (!rows) return cap ? MC_E_INVAL : MC_OK;
+    if (cap < n) return MC_E_BUFFER;
+    std::memcpy(rows, h->trace_rows.data(), 4ull * h->trace_rows.size());
+    return MC_OK;
+  } catch (...) {
+    return MC_E_DEVICE;
+  }
+}
+
+int mc_simulate(mc_model* h, uint64_t seed, uint32_t* t_end, uint32_t* cfg) {
+  if (!h || !t_end || !cfg) return MC_E_INVAL;
+  hipStream_t s = h->stream;
+  const QueryArgs q = make_args(h, false, 0);
+  HIPCHK(launch_simulate(s, q, seed));
+  HIPCHK(hipMemcpyAsync(h->hpoll, &h->ctrl->sim_t, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *t_end = h->hpoll[0];
+  *cfg = h->hpoll[1];
+  return MC_OK;
+}
+
+int mc_tune_bisect(mc_model* h, uint64_t seed, uint32_t* t_min, uint32_t* n_checks, mc_stats* st) {
+  if (!h || !t_min || !n_checks) return MC_E_INVAL;
+  uint32_t t_ini = 0, c0 = 0;
+  int rc = mc_simulate(h, seed, &t_ini, &c0);
+  if (rc) return rc;
+  mc_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  mc_stats one;
+  // check(lo) holds (clock >= 1 at every terminal), check(hi) fails (the simulated run)
+  uint32_t lo = 0, hi = t_ini, n = 0;
+  int last_violated = -1;
+  while (hi - lo > 1) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    int v = 0;
+    rc = mc_check(h, mid, &v, &one);
+    if (rc) return rc;
+    ++n;
+    acc.explore_ns += one.explore_ns;
+    acc.clear_ns += one.clear_ns;
+    acc.launches += one.launches;
+    acc.states += one.states;
+    if (v) hi = mid;
+    else lo = mid;
+    last_violated = v;
+  }
+  if (last_violated != 1) {  // leave the counterexample of check(T_min) behind
+    int v = 0;
+    rc = mc_check(h, hi, &v, &one);
+    if (rc) return rc;
+    acc.explore_ns += one.explore_ns;
+    acc.clear_ns += one.clear_ns;
+    acc.launches += one.launches;
+    if (!v) return MC_E_STATE;
+  }
+  *t_min = hi;
+  *n_checks = n;
+  if (st) *st = acc;
+  return MC_OK;
+}
+
+int mc_config(const mc_model* h, uint32_t cfg, uint32_t* params4) {
+  if (!h || !params4 || cfg >= h->mh.n_cfg) return MC_E_INVAL;
+  std::memcpy(params4, &h->mh.params[4ull * cfg], 16);
+  return MC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// mc_device.h -- device-side building blocks of the explorer: packed keys, operation
+// tables, the lock-free visited set and wavefront compaction helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mc_model.h"
+
+namespace mc {
+
+// Device counters of one query (one per model; zeroed before every query).
+struct Ctrl {
+  unsigned long long states;     // states claimed in the visited set (root included)
+  unsigned long long terminals;  // terminal states claimed
+  unsigned long long edges;      // successor generations
+  unsigned long long dups;       // inserts that found the state present
+  unsigned long long probes;     // slots probed
+  unsigned long long max_depth;  // deepest claimed state
+  unsigned int error;            // kDevErr* (first error wins)
+  unsigned int violated;         // some terminal with clock <= T
+  unsigned int queue_head;       // next partition of the persistent engine
+  unsigned int levels;           // level-engine launches with a non-empty frontier
+  unsigned int fcount[3];        // level-engine frontier sizes (rotating)
+  unsigned int root_slot;
+  unsigned int trace_len;
+  unsigned int target_slot;
+  unsigned int sim_t, sim_cfg;
+  unsigned int pad[16];
+};
+static_assert(sizeof(Ctrl) == 160, "Ctrl layout");
+
+constexpr unsigned int kDevErrTableFull = 1;
+constexpr unsigned int kDevErrOverflow = 2;
+constexpr unsigned int kDevErrPublish = 3;
+constexpr unsigned int kDevErrTrace = 4;
+
+constexpr uint32_t kMaxProbeIters = 1u << 16;
+
+template <int W>
+struct SlotBytes;
+template <>
+struct SlotBytes<1> { static constexpr uint32_t v = 16; };
+template <>
+struct SlotBytes<2> { static constexpr uint32_t v = 32; };
+template <>
+struct SlotBytes<4> { static constexpr uint32_t v = 64; };
+
+template <int W>
+struct Key {
+  unsigned long long w[W];
+};
+
+// A queued state: key, its visited-set slot and its depth (path length from the root).
+template <int W>
+struct Entry {
+  unsigned long long k[W];
+  uint32_t slot;
+  uint32_t depth;
+};
+
+struct Seed {
+  unsigned long long k[4];
+  uint32_t slot;
+  uint32_t depth;
+  uint32_t pad[2];
+};
+static_assert(sizeof(Seed) == 48, "Seed layout");
+
+struct St {
+  uint32_t cfg, pending, clock;
+  uint32_t rem[kMaxCU];
+};
+
+// ---- packed keys ----------------------------------------------------------------
+
+template <int W>
+__device__ __forceinline__ unsigned long long key_word(const Key<W>& k, int i) {
+  unsigned long long r = k.w[0];
+#pragma unroll
+  for (int j = 1; j < W; ++j) r = (i == j) ? k.w[j] : r;
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t key_get(const Key<W>& k, const Layout& L, int f) {
+  const unsigned long long v = key_word<W>(k, L.word[f]) >> L.shift[f];
+  return (uint32_t)(v & ((1ull << L.width[f]) - 1ull));
+}
+
+template <int W>
+__device__ __forceinline__ void key_put(Key<W>& k, const Layout& L, int f, uint32_t v) {
+  const unsigned long long x = (unsigned long long)v << L.shift[f];
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (L.word[f] == j) k.w[j] |= x;
+}
+
+template <int W>
+__device__ __forceinline__ St decode(const Key<W>& k, const Layout& L) {
+  St s;
+  s.cfg = key_get<W>(k, L, kFCfg);
+  s.pending = key_get<W>(k, L, kFPending);
+  s.clock = key_get<W>(k, L, kFClock);
+#pragma unroll
+  for (int i = 0; i < kMaxCU; ++i) s.rem[i] = (i < L.m) ? key_get<W>(k, L, kFRem + i) : 0u;
+  return s;
+}
+
+template <int W>
+__device__ __forceinline__ Key<W> encode(const St& s, const Layout& L) {
+  Key<W> k;
+#pragma unroll
+  for (int j = 0; j < W; ++j) k.w[j] = 0ull;
+  key_put<W>(k, L, kFCfg, s.cfg);
+  key_put<W>(k, L, kFPending, s.pending);
+  key_put<W>(k, L, kFClock, s.clock);
+#pragma unroll
+  for (int i = 0; i < kMaxCU; ++i)
+    if (i < L.m) key_put<W>(k, L, kFRem + i, s.rem[i]);
+  return k;
+}
+
+__device__ __forceinline__ unsigned long long fmix64(unsigned long long x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+template <int W>
+__device__ __forceinline__ unsigned long long key_hash(const Key<W>& k) {
+  unsigned long long h = fmix64(k.w[0] + 0x9e3779b97f4a7c15ull);
+#pragma unroll
+  for (int j = 1; j < W; ++j) h = fmix64(h ^ (k.w[j] + 0x632be59bd9b4e019ull * j));
+  return h;
+}
+
+__device__ __forceinline__ bool is_terminal(const St& s, int m) {
+  if (s.pending) return false;
+  bool idle = true;
+#pragma unroll
+  for (int i = 0; i < kMaxCU; ++i) idle &= (i >= m) || (s.rem[i] == 0u);
+  return idle;
+}
+
+// ---- operation ends of one workgroup (phases of CfgRec) ----------------------------
+
+// number of operation ends at times <= e, for 0 <= e
+__device__ __forceinline__ uint32_t ends_upto(const CfgRec& r, uint32_t e) {
+  if (e >= r.d) return r.b;
+  uint32_t res = r.b;
+  bool found = false;
+#pragma unroll
+  for (int j = kMaxPhases - 1; j >= 0; --j) {
+    if (j < (int)r.nph && e >= r.t0[j] && !found) {
+      res = r.i0[j] + (e - r.t0[j]) / r.lat[j];
+      found = true;
+    }
+  }
+  return res;
+}
+
+// time of the k-th operation end (0-based), k < b
+__device__ __forceinline__ uint32_t end_at(const CfgRec& r, uint32_t k) {
+  uint32_t res = r.d;
+  bool found = false;
+#pragma unroll
+  for (int j = 0; j < kMaxPhases; ++j) {
+    if (j < (int)r.nph && !found && k < r.i0[j] + r.cnt[j]) {
+      res = r.t0[j] + (k - r.i0[j] + 1u) * r.lat[j];
+      found = true;
+    }
+  }
+  return res;
+}
+
+// One ADVANCE step: the clock moves to the next operation end of any busy unit.
+__device__ __forceinline__ void advance_once(St& s, const CfgRec& r, int m) {
+  uint32_t delta = 0xFFFFFFFFu;
+#pragma unroll
+  for (int i = 0; i < kMaxCU; ++i) {
+    if (i < m && s.rem[i]) {
+      const uint32_t e = r.d - s.rem[i];
+      const uint32_t di = end_at(r, ends_upto(r, e)) - e;
+      delta = di < delta ? di : delta;
+    }
+  }
+  s.clock += delta;
+#pragma unroll
+  for (int i = 0; i < kMaxCU; ++i)
+    if (i < m && s.rem[i]) s.rem[i] -= delta;
+}
+
+// ---- visited set ----------------------------------------------------------------
+
+template <int W>
+__device__ __forceinline__ unsigned long long* slot_key(unsigned char* base, unsigned long long s) {
+  return reinterpret_cast<unsigned long long*>(base + s * SlotBytes<W>::v);
+}
+template <int W>
+__device__ __forceinline__ uint32_t* slot_parent(unsigned char* base, unsigned long long s) {
+  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W);
+}
+// publish word of a wide key: 0xFFFFFFFF until the claimer has written every key word
+template <int W>
+__device__ __forceinline__ uint32_t* slot_pub(unsigned char* base, unsigned long long s) {
+  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W + 4u);
+}
+constexpr uint32_t kPublished = 1u;
+
+constexpr int kScopeWG = __HIP_MEMORY_SCOPE_WORKGROUP;
+constexpr int kScopeAgent = __HIP_MEMORY_SCOPE_AGENT;
+
+enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
+
+// Open addressing with linear probing; a 64-bit compare-and-swap on key word 0 claims
+// a slot.  Wider keys are claimed on word 0, then the winner writes the other words and
+// publishes them (release) through the slot's publish word;
+// a lane that finds its own word 0 in a slot waits for the publish and compares the
+// rest.  Waiting never blocks inside an iteration: every lane of the wavefront runs
+// the same iteration loop, and a winner publishes in the iteration it won, so a
+// waiting lane cannot starve a winner of its own wavefront.  SCOPE is the widest set
+// of threads that may insert the same key: the workgroup in the super-step engine
+// (one configuration's subgraph per workgroup, configuration index in word 0), the
+// device in the level engine.
+template <int W, int SCOPE>
+__device__ __forceinline__ int table_insert(unsigned char* base, unsigned long long mask,
+                                            const Key<W>& k, uint32_t& slot_out,
+                                            uint32_t& probes) {
+  unsigned long long s = key_hash<W>(k) & mask;
+  bool waiting = false;
+  const unsigned long long iters = mask < kMaxProbeIters ? mask + 1ull : kMaxProbeIters;
+  for (unsigned long long it = 0; it < iters; ++it) {
+    unsigned long long* p = slot_key<W>(base, s);
+    if (!waiting) {
+      ++probes;
+      const unsigned long long old = atomicCAS(p, kEmptyWord, k.w[0]);
+      if (old == kEmptyWord) {
+        if (W > 1) {
+#pragma unroll
+          for (int j = 1; j < W; ++j) __hip_atomic_store(p + j, k.w[j], __ATOMIC_RELAXED, SCOPE);
+          __hip_atomic_store(slot_pub<W>(base, s), kPublished, __ATOMIC_RELEASE, SCOPE);
+        }
+        slot_out = (uint32_t)s;
+        return kInsNew;
+      }
+      if (old != k.w[0]) {
+        s = (s + 1) & mask;
+        continue;
+      }
+      if (W == 1) {
+        slot_out = (uint32_t)s;
+        return kInsDup;
+      }
+      waiting = true;
+    }
+    const uint32_t pub = __hip_atomic_load(slot_pub<W>(base, s), __ATOMIC_ACQUIRE, SCOPE);
+    if (pub != kPublished) continue;
+    bool eq = true;
+#pragma unroll
+    for (int j = 1; j < W; ++j) eq &= __hip_atomic_load(p + j, __ATOMIC_RELAXED, SCOPE) == k.w[j];
+    if (eq) {
+      slot_out = (uint32_t)s;
+      return kInsDup;
+    }
+    waiting = false;
+    s = (s + 1) & mask;
+  }
+  return kInsFail;
+}
+
+// Lookup only (after the exploration finished; plain loads).
+template <int W>
+__device__ __forceinline__ uint32_t table_find(unsigned char* base, unsigned long long mask,
+                                               const Key<W>& k) {
+  unsigned long long s = key_hash<W>(k) & mask;
+  for (unsigned long long it = 0; it <= mask; ++it) {
+    const unsigned long long* p = slot_key<W>(base, s);
+    if (p[0] == kEmptyWord) return kParentNone;
+    bool eq = true;
+#pragma unroll
+    for (int j = 0; j < W; ++j) eq &= p[j] == k.w[j];
+    if (eq) return (uint32_t)s;
+    s = (s + 1) & mask;
+  }
+  return kParentNone;
+}
+
+// ---- wavefront helpers ------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
+  const uint32_t l = lane_id();
+  return (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
+}
+
+// Wavefront-aggregated append: one atomic per wavefront; returns this lane's position
+// (valid only where pred).  Must be reached by every lane of the wavefront.
+__device__ __forceinline__ uint32_t wave_append(bool pred, unsigned int* counter) {
+  const unsigned long long mask = __ballot(pred);
+  if (!mask) return 0u;
+  const int leader = __ffsll((long long)mask) - 1;
+  uint32_t base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + lanes_below(mask);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(v, o);
+    v = x > v ? x : v;
+  }
+  return v;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014)
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace mc

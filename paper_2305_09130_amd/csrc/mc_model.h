@@ -1,0 +1,76 @@
+// mc_model.h -- host-side model logic shared by the library's host code and kernels:
+// descriptor validation, per-configuration operation tables, packed-key layout and
+// the exact sizes of the lock-step round structure used to size device memory.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mctune.h"
+
+namespace mc {
+
+constexpr int kMaxCU = (int)MC_MAX_CU;
+constexpr int kFields = 3 + kMaxCU;  // cfg, pending, clock, rem_0..rem_{m-1}
+constexpr int kFCfg = 0, kFPending = 1, kFClock = 2, kFRem = 3;
+constexpr int kMaxPhases = 4;
+
+constexpr uint32_t kParentNone = 0xFFFFFFFFu;  // no parent recorded (empty slot)
+constexpr uint32_t kParentRoot = 0xFFFFFFFEu;  // the root has no parent
+constexpr uint64_t kEmptyWord = ~0ull;         // empty slot (word 0)
+constexpr uint32_t kNoClock = 0xFFFFFFFFu;
+
+// Packed key layout.  Fields never straddle a 64-bit word; the configuration index
+// sits in the low bits of word 0 and all-ones never encodes a valid configuration,
+// so no valid key has word 0 equal to kEmptyWord.
+struct Layout {
+  uint8_t word[kFields];
+  uint8_t shift[kFields];
+  uint8_t width[kFields];
+  uint8_t m;
+  uint8_t W;  // key words: 1, 2 or 4
+  uint8_t used_bits;
+  uint8_t pad[2];
+};
+
+// One configuration: workgroup count, duration and the timed operation phases
+// (phases of zero latency add no operation end and are dropped).  Phase j ends
+// cnt[j] operations at t0[j] + k*lat[j], k = 1..cnt[j]; i0[j] = ends before phase j.
+struct CfgRec {
+  uint32_t n;      // workgroups
+  uint32_t d;      // workgroup duration = last operation end
+  uint32_t b;      // number of distinct operation ends
+  uint32_t nph;    // timed phases
+  uint32_t cnt[kMaxPhases];
+  uint32_t lat[kMaxPhases];
+  uint32_t t0[kMaxPhases];
+  uint32_t i0[kMaxPhases];
+  uint32_t tc;     // ceil(n/m) * d: clock of every terminal of this configuration
+  uint32_t pad[3];
+};
+static_assert(sizeof(CfgRec) == 96, "CfgRec layout");
+
+struct ModelHost {
+  mc_desc desc{};
+  std::vector<uint32_t> params;  // n_cfg * 4
+  std::vector<CfgRec> cfgs;
+  Layout layout{};
+  uint32_t m = 0, n_cfg = 0, W = 1;
+  uint64_t states = 0;           // exact reachable count, root included
+  uint64_t max_depth = 0;        // longest path (edges)
+  uint32_t max_clock = 0;
+  uint32_t max_n = 0, max_d = 0;
+  std::vector<uint64_t> cfg_states;  // reachable states per configuration subgraph
+  uint64_t frontier_bound = 0;   // widest BFS level
+};
+
+// Validates d and fills h.  Returns MC_OK or MC_E_INVAL with a message in err.
+int build_model(const mc_desc* d, ModelHost* h, std::string* err);
+
+uint64_t binom(uint32_t n, uint32_t k);
+uint32_t bit_length(uint64_t x);
+
+}  // namespace mc

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP explorer against the CPU oracle, through the C ABI.
+
+Bit-exact on every integer result: T_min, the argmin set, the per-configuration least
+terminal clocks, the reachable-state count (count_T under pruning), the number of BFS
+levels and the over-time verdict.  Traces are checked by replaying every step through
+the oracle's successor function (many paths are correct; validity is what is unique).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import closed_form as cf
+
+pytestmark = pytest.mark.gpu
+
+ENGINES = {"superstep": 0, "level": 1}
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2305_09130_amd as mc
+    return mc
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_cached(key):
+    model, T = key
+    return oracle.explore(_thaw(model), T=T)
+
+
+def _freeze(model):
+    return tuple(sorted((k, tuple(map(tuple, v)) if k == "params" else v)
+                        for k, v in model.items()))
+
+
+def _thaw(frozen):
+    d = dict(frozen)
+    d["params"] = [list(r) for r in d["params"]]
+    return d
+
+
+def ref(model, T=None):
+    return _oracle_cached((_freeze(model), T))
+
+
+def check_min_time(mc, g, model, r):
+    t_min, argmin = g.mc_min_time()
+    st = g.last_stats
+    assert (t_min, argmin) == (r["t_min"], r["argmin"])
+    assert st["states"] == r["reachable"]
+    assert st["levels"] == r["levels"]
+    assert st["terminals"] == r["terminals"]
+    assert g.mc_terminal_clocks() == r["tc"]
+    tr = g.mc_trace()
+    assert len(tr) == len(r["trace"])
+    oracle.check_trace(model, tr, target_clock=r["t_min"], cfgs=r["argmin"])
+    assert tr[-1][0] == min(r["argmin"])
+
+
+def check_threshold(mc, g, model, T):
+    r = ref(model, T)
+    v = g.mc_check(T)
+    st = g.last_stats
+    assert v == r["violated"], (T, v, r["violated"])
+    assert st["states"] == r["reachable"], (T, st["states"], r["reachable"])
+    assert g.mc_terminal_clocks() == r["tc"]
+    if v:
+        tr = g.mc_trace()
+        oracle.check_trace(model, tr, max_clock=T)
+        assert tr[-1][0] == r["trace_cfg"]
+    else:
+        with pytest.raises(mc.McError) as e:
+            g.mc_trace()
+        assert e.value.code == mc.MC_E_STATE
+
+
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_reduction_g256(mc, engine):
+    model = workloads.reduction_g256()
+    _say(f"reduction_g256 engine={engine}")
+    r = ref(model)
+    g = mc.Model(model, engine=ENGINES[engine])
+    check_min_time(mc, g, model, r)
+    for T in sorted({r["t_min"] - 2, r["t_min"] - 1, r["t_min"], r["t_min"] + 1,
+                     r["t_min"] + 2, 0, r["t_min"] // 2, 5000}):
+        _say(f"  check T={T}")
+        check_threshold(mc, g, model, T)
+    g.close()
+
+
+def _tiny_cases():
+    cases = workloads.tiny_models(101, 40, max_cu=8) + workloads.tiny_models(102, 24, max_cu=4)
+    return cases
+
+
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_tiny_sweep(mc, engine):
+    for i, model in enumerate(_tiny_cases()):
+        _say(f"tiny[{i}] engine={engine} {workloads.describe(model)}")
+        r = ref(model)
+        g = mc.Model(model, engine=ENGINES[engine])
+        check_min_time(mc, g, model, r)
+        for T in (r["t_min"] - 1, r["t_min"]):
+            check_threshold(mc, g, model, T)
+        g.close()
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_superstep_block_shapes(mc, block):
+    model = workloads.reduction_model(64, 4, [1, 2, 4, 8, 16], [1, 2, 4], 5, 2, Lb=1)
+    _say(f"block={block} {workloads.describe(model)}")
+    r = ref(model)
+    g = mc.Model(model, engine=0, block=block)
+    check_min_time(mc, g, model, r)
+    g.close()
+
+
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_matmul64(mc, engine):
+    model = workloads.matmul_64()
+    _say(f"matmul64 engine={engine}")
+    r = ref(model)
+    g = mc.Model(model, engine=ENGINES[engine])
+    check_min_time(mc, g, model, r)
+    if engine == "superstep":
+        for T in (r["t_min"] - 1, r["t_min"]):
+            _say(f"  check T={T}")
+            check_threshold(mc, g, model, T)
+    g.close()
+
+
+def test_matmul128_vw_full_size(mc):
+    """The large workload: closed forms (pinned to the oracle) give the counts, the
+    per-configuration clocks and the argmin; the trace is replayed through the oracle."""
+    model = workloads.matmul_128_vw()
+    _say("matmul128_vw superstep")
+    s = cf.summary(model, with_E=False)
+    g = mc.Model(model, engine=0, block=1024)
+    t_min, argmin = g.mc_min_time()
+    st = g.last_stats
+    assert (t_min, argmin) == (s["t_min"], s["argmin"])
+    assert st["states"] == s["reachable"] == 58006261
+    assert st["levels"] == s["levels"]
+    assert g.mc_terminal_clocks() == s["tc"]
+    tr = g.mc_trace()
+    assert len(tr) == s["trace_len"]
+    oracle.check_trace(model, tr, target_clock=s["t_min"], cfgs=s["argmin"])
+    g.close()
+
+
+def test_simulate_matches_oracle_walk(mc):
+    for model in [workloads.reduction_g256()] + _tiny_cases()[:20]:
+        g = mc.Model(model)
+        r = ref(model)
+        for seed in (0, 1, 7, 12345, 2**63 + 5):
+            t, c = g.mc_simulate(seed)
+            assert (t, c) == oracle.simulate(model, seed)
+            assert t == r["tc"][c]
+        g.close()
+
+
+def test_bisection(mc):
+    for model in [workloads.reduction_g256()] + _tiny_cases()[:10]:
+        _say(f"bisect {workloads.describe(model)}")
+        r = ref(model)
+        g = mc.Model(model)
+        for seed in (3, 11):
+            t_min, n = g.mc_tune_bisect(seed)
+            t_ini, _ = oracle.simulate(model, seed)
+            assert t_min == r["t_min"]
+            assert (t_min, n) == oracle.bisect_t_min(model, t_ini)
+            oracle.check_trace(model, g.mc_trace(), max_clock=t_min)
+        g.close()
+
+
+def test_table_full_is_reported_then_recovers(mc):
+    model = workloads.reduction_g256()
+    r = ref(model)
+    for engine in (0, 1):
+        _say(f"table-full engine={engine}")
+        g = mc.Model(model, engine=engine, log2_slots=12)
+        with pytest.raises(mc.McError) as e:
+            g.mc_min_time()
+        assert e.value.code == mc.MC_E_TABLE_FULL
+        g.close()
+        g = mc.Model(model, engine=engine, log2_slots=17)  # load factor 0.62
+        check_min_time(mc, g, model, r)
+        g.close()
+
+
+def test_repeated_queries_same_handle(mc):
+    model = workloads.reduction_model(128, 3, [1, 2, 4, 8], [1, 2, 4], 9, 3, Lb=0)
+    r = ref(model)
+    g = mc.Model(model)
+    for rep in range(3):
+        for engine in (0, 1):
+            g.mc_set_engine(engine)
+            check_min_time(mc, g, model, r)
+            check_threshold(mc, g, model, r["t_min"] - 1)
+    g.close()
+
+
+def test_single_unit_closed_form(mc):
+    model = workloads.reduction_model(64, 1, [1, 2, 4, 8, 16, 32, 64], [1, 2, 4, 8], 21, 3)
+    g = mc.Model(model)
+    g.mc_min_time()
+    assert g.last_stats["states"] == cf.single_cu_count(model)
+    g.close()
