@@ -108,6 +108,8 @@ typedef struct mc_stats {
     uint64_t explore_ns;     /* GPU time of the exploration kernels (HIP events) */
     uint64_t total_ns;       /* host wall time of the query call */
     uint64_t clear_ns;       /* GPU time clearing the visited set */
+    uint64_t engine_ns;      /* GPU time of the exploration engine's own launch(es),
+                                without the seed and result copies (HIP events) */
 } mc_stats;
 
 typedef struct mc_model_info {

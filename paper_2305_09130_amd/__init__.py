@@ -52,7 +52,7 @@ class McOpts(ctypes.Structure):
 class McStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("states", "levels", "terminals", "edges", "dups", "probes", "launches",
-                 "explore_ns", "total_ns", "clear_ns")]
+                 "explore_ns", "total_ns", "clear_ns", "engine_ns")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -162,7 +162,7 @@ class Model:
 
     def __init__(self, model: dict, engine: int = MC_ENGINE_SUPERSTEP, block: int = 0,
                  log2_slots: int = 0, load_factor: float = 0.0, grid: int = 0,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, workspace=None):
         import torch
         self.model = model
         self.m = model["m"]
@@ -171,7 +171,12 @@ class Model:
         self._opts = make_opts(engine, block, log2_slots, load_factor, grid)
         nbytes = mc_workspace_bytes(model, self._opts)
         self.device = torch.device(device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif workspace.numel() < nbytes or workspace.dtype != torch.uint8:
+            raise ValueError(f"workspace needs {nbytes} bytes of uint8")
+        self.workspace = workspace
+        nbytes = workspace.numel()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check("mc_model_load",

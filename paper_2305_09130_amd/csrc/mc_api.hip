@@ -129,7 +129,7 @@ struct mc_model {
   unsigned char* table = nullptr;
   Ctrl* hctrl = nullptr;  // pinned host copy
   uint32_t* hpoll = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool dirty = true;
   int last = kQueryNone;
   uint32_t last_T = 0;
@@ -157,10 +157,22 @@ QueryArgs make_args(mc_model* h, bool prune, uint32_t T) {
 }
 
 template <int W>
+int engine_w(mc_model* h, const QueryArgs& q, uint64_t* launches);
+
+template <int W>
 int explore_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   hipStream_t s = h->stream;
   HIPCHK(launch_seed<W>(s, q, h->seeds, h->front[0]));
   *launches = 1;
+  HIPCHK(hipEventRecord(h->ev[4], s));
+  const int rc = engine_w<W>(h, q, launches);
+  HIPCHK(hipEventRecord(h->ev[5], s));
+  return rc;
+}
+
+template <int W>
+int engine_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
+  hipStream_t s = h->stream;
   if (h->opts.engine == MC_ENGINE_SUPERSTEP) {
     SuperArgs sa;
     sa.q = q;
@@ -233,8 +245,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
   HIPCHK(hipStreamSynchronize(s));
   const int derr = dev_err(h->hctrl->error);
   if (derr != MC_OK) return derr;
-  float ms_explore = 0.f, ms_clear = 0.f;
+  float ms_explore = 0.f, ms_clear = 0.f, ms_engine = 0.f;
   HIPCHK(hipEventElapsedTime(&ms_explore, h->ev[2], h->ev[3]));
+  HIPCHK(hipEventElapsedTime(&ms_engine, h->ev[4], h->ev[5]));
   if (cleared) HIPCHK(hipEventElapsedTime(&ms_clear, h->ev[0], h->ev[1]));
   if (st) {
     std::memset(st, 0, sizeof(*st));
@@ -247,6 +260,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     st->launches = launches;
     st->explore_ns = (uint64_t)(ms_explore * 1e6);
     st->clear_ns = (uint64_t)(ms_clear * 1e6);
+    st->engine_ns = (uint64_t)(ms_engine * 1e6);
     st->total_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                        std::chrono::steady_clock::now() - t0)
                        .count();
@@ -564,6 +578,7 @@ int mc_tune_bisect(mc_model* h, uint64_t seed, uint32_t* t_min, uint32_t* n_chec
     ++n;
     acc.explore_ns += one.explore_ns;
     acc.clear_ns += one.clear_ns;
+    acc.engine_ns += one.engine_ns;
     acc.launches += one.launches;
     acc.states += one.states;
     if (v) hi = mid;
