@@ -93,7 +93,9 @@ typedef struct mc_opts {
     uint32_t log2_slots;     /* visited-set capacity 2^log2_slots (0 = from load_factor) */
     float load_factor;       /* target states/slots when sizing (0 = 0.5) */
     uint32_t grid;           /* persistent workgroups (0 = automatic) */
-    uint32_t reserved[3];
+    uint32_t batch_items;    /* super-step engine: states generated from one frontier state
+                                before waiting for the visited set (0 = 2 x block) */
+    uint32_t reserved[2];
 } mc_opts;
 
 /* ---- statistics of the last query ---------------------------------------------- */
@@ -110,6 +112,11 @@ typedef struct mc_stats {
     uint64_t clear_ns;       /* GPU time clearing the visited set */
     uint64_t engine_ns;      /* GPU time of the exploration engine's own launch(es),
                                 without the seed and result copies (HIP events) */
+    uint64_t supersteps;     /* super-steps of the persistent engine */
+    uint64_t batches;        /* insert batches of the persistent engine */
+    uint64_t max_probe;      /* longest probe sequence of one insert */
+    uint64_t critical_ns;    /* longest single-configuration exploration (device clock) */
+    uint64_t critical_cfg;   /* the configuration that took it */
 } mc_stats;
 
 typedef struct mc_model_info {
@@ -191,6 +198,45 @@ int mc_set_engine(mc_model *h, uint32_t engine);
 int mc_config(const mc_model *h, uint32_t cfg, uint32_t *params4);
 
 const char *mc_strerror(int code);
+
+/* ---- batched exploration: many models in one persistent launch ----------------- */
+/* The models of a batch are disjoint state graphs, and so are the configurations of a
+ * model after SELECT: every (model, configuration) subgraph becomes one partition of a
+ * single queue, largest first, consumed by one persistent launch.  Each model keeps its
+ * own visited set, carved from one arena in the caller's workspace. */
+typedef struct mc_batch mc_batch;
+
+typedef struct mc_batch_opts {
+    uint32_t block;          /* threads per workgroup: 256, 512, 1024 (0 = 512) */
+    uint32_t grid;           /* persistent workgroups (0 = automatic) */
+    float load_factor;       /* visited-set load factor (0 = 0.5) */
+    uint32_t chunk;          /* states generated per super-step before waiting for the
+                                visited set (0 = 2 x block) */
+    uint32_t use_graph;      /* 1: capture the query's launch sequence once in a hipGraph
+                                and replay it (needs a non-null stream: MC_E_INVAL) */
+    uint32_t reserved[3];
+} mc_batch_opts;
+
+/* Workspace bytes of a batch of n models (host array of n descriptors). */
+int mc_batch_workspace_bytes(const mc_desc *models, uint32_t n, const mc_batch_opts *o,
+                             size_t *bytes);
+/* Create a batch in the caller's device workspace on the given stream.  The library
+ * owns *out.  MC_E_NOMEM if ws_bytes is too small; MC_E_INVAL for any invalid model. */
+int mc_batch_create(const mc_desc *models, uint32_t n, const mc_batch_opts *o, void *dev_ws,
+                    size_t ws_bytes, void *stream, mc_batch **out);
+/* min_time of every model: t_min[i] and the reachable count states[i] (host arrays of
+ * n, either may be NULL); st aggregates the counters (explore_ns = the whole query on
+ * the GPU).  Per-model argmin sets come from mc_batch_terminal_clocks. */
+int mc_batch_min_time(mc_batch *b, uint32_t *t_min, uint64_t *states, mc_stats *st);
+/* Per-configuration least terminal clocks of one model of the last mc_batch_min_time. */
+int mc_batch_terminal_clocks(const mc_batch *b, uint32_t model, uint32_t *tc, size_t cap);
+int mc_batch_free(mc_batch *b);
+/* Autotuner: tries block in {256,512,1024} x load factor in {0.25,0.5,0.7} x chunk in
+ * {1,2,4} x block on the batch itself, in the caller's workspace (candidates that do not
+ * fit are skipped), and returns the fastest options and their GPU time (-1 when served
+ * from the per-process cache, keyed by the batch and the device architecture). */
+int mc_batch_autotune(const mc_desc *models, uint32_t n, void *dev_ws, size_t ws_bytes,
+                      void *stream, mc_batch_opts *best, float *best_ms);
 
 #ifdef __cplusplus
 }

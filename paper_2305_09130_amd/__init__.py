@@ -46,13 +46,15 @@ class McDesc(ctypes.Structure):
 class McOpts(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_uint32), ("block", ctypes.c_uint32),
                 ("log2_slots", ctypes.c_uint32), ("load_factor", ctypes.c_float),
-                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("grid", ctypes.c_uint32), ("batch_items", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class McStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("states", "levels", "terminals", "edges", "dups", "probes", "launches",
-                 "explore_ns", "total_ns", "clear_ns", "engine_ns")]
+                 "explore_ns", "total_ns", "clear_ns", "engine_ns", "supersteps",
+                 "batches", "max_probe", "critical_ns", "critical_cfg")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -63,6 +65,17 @@ class McModelInfo(ctypes.Structure):
                 ("key_words", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
                 ("slots", ctypes.c_uint64), ("slot_bytes", ctypes.c_uint64),
                 ("bound_states", ctypes.c_uint64), ("max_depth", ctypes.c_uint64)]
+
+
+class McBatchOpts(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("load_factor", ctypes.c_float), ("chunk", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+    def as_dict(self) -> dict:
+        return {"block": int(self.block), "grid": int(self.grid),
+                "load_factor": float(self.load_factor), "chunk": int(self.chunk),
+                "use_graph": int(self.use_graph)}
 
 
 _P = ctypes.POINTER
@@ -83,6 +96,15 @@ _SIGS = {
     "mc_simulate": ([_vp, ctypes.c_uint64, _u32p, _u32p], ctypes.c_int),
     "mc_tune_bisect": ([_vp, ctypes.c_uint64, _u32p, _u32p, _P(McStats)], ctypes.c_int),
     "mc_config": ([_vp, ctypes.c_uint32, _u32p], ctypes.c_int),
+    "mc_batch_workspace_bytes": ([_P(McDesc), ctypes.c_uint32, _P(McBatchOpts),
+                                  _P(ctypes.c_size_t)], ctypes.c_int),
+    "mc_batch_create": ([_P(McDesc), ctypes.c_uint32, _P(McBatchOpts), _vp, ctypes.c_size_t,
+                         _vp, _P(_vp)], ctypes.c_int),
+    "mc_batch_min_time": ([_vp, _u32p, _u64p, _P(McStats)], ctypes.c_int),
+    "mc_batch_terminal_clocks": ([_vp, ctypes.c_uint32, _u32p, ctypes.c_size_t], ctypes.c_int),
+    "mc_batch_free": ([_vp], ctypes.c_int),
+    "mc_batch_autotune": ([_P(McDesc), ctypes.c_uint32, _vp, ctypes.c_size_t, _vp,
+                           _P(McBatchOpts), _P(ctypes.c_float)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -124,10 +146,11 @@ def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
 
 
 def make_opts(engine: int = MC_ENGINE_SUPERSTEP, block: int = 0, log2_slots: int = 0,
-              load_factor: float = 0.0, grid: int = 0) -> McOpts:
+              load_factor: float = 0.0, grid: int = 0, batch_items: int = 0) -> McOpts:
     o = McOpts()
     o.engine, o.block, o.log2_slots, o.load_factor, o.grid = engine, block, log2_slots, \
         load_factor, grid
+    o.batch_items = batch_items
     return o
 
 
@@ -162,13 +185,13 @@ class Model:
 
     def __init__(self, model: dict, engine: int = MC_ENGINE_SUPERSTEP, block: int = 0,
                  log2_slots: int = 0, load_factor: float = 0.0, grid: int = 0,
-                 device: str = "cuda:0", stream=None, workspace=None):
+                 device: str = "cuda:0", stream=None, workspace=None, batch_items: int = 0):
         import torch
         self.model = model
         self.m = model["m"]
         self.n_cfg = len(model["params"])
         self._desc, self._params = make_desc(model)
-        self._opts = make_opts(engine, block, log2_slots, load_factor, grid)
+        self._opts = make_opts(engine, block, log2_slots, load_factor, grid, batch_items)
         nbytes = mc_workspace_bytes(model, self._opts)
         self.device = torch.device(device)
         if workspace is None:
@@ -251,6 +274,106 @@ class Model:
         p = np.zeros(4, dtype=np.uint32)
         _check("mc_config", _lib.mc_config(self._h, cfg, p.ctypes.data_as(_u32p)))
         return [int(v) for v in p]
+
+
+def _desc_array(models: list[dict]):
+    arr = (McDesc * len(models))()
+    keep = []
+    for i, m in enumerate(models):
+        d, p = make_desc(m)
+        arr[i] = d
+        keep.append(p)
+    return arr, keep
+
+
+def make_batch_opts(block: int = 0, grid: int = 0, load_factor: float = 0.0, chunk: int = 0,
+                    use_graph: bool = False) -> McBatchOpts:
+    o = McBatchOpts()
+    o.block, o.grid, o.load_factor, o.chunk = block, grid, load_factor, chunk
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+def mc_batch_workspace_bytes(models: list[dict], opts: McBatchOpts | None = None) -> int:
+    arr, keep = _desc_array(models)
+    n = ctypes.c_size_t()
+    _check("mc_batch_workspace_bytes",
+           _lib.mc_batch_workspace_bytes(arr, len(models), ctypes.byref(opts) if opts else None,
+                                         ctypes.byref(n)))
+    return n.value
+
+
+def mc_batch_autotune(models: list[dict], workspace, stream=None) -> tuple[McBatchOpts, float]:
+    """Fastest batch options for these models on this GPU (cached per process)."""
+    import torch
+    arr, keep = _desc_array(models)
+    st = stream if stream is not None else torch.cuda.current_stream(workspace.device)
+    best = McBatchOpts()
+    ms = ctypes.c_float()
+    _check("mc_batch_autotune",
+           _lib.mc_batch_autotune(arr, len(models), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel(), ctypes.c_void_p(st.cuda_stream),
+                                  ctypes.byref(best), ctypes.byref(ms)))
+    return best, ms.value
+
+
+class Batch:
+    """Many models explored together in one persistent launch (mc_batch_*)."""
+
+    def __init__(self, models: list[dict], opts: McBatchOpts | None = None,
+                 device: str = "cuda:0", stream=None, workspace=None):
+        import torch
+        self.models = models
+        self.n = len(models)
+        self._arr, self._keep = _desc_array(models)
+        self._opts = opts if opts is not None else McBatchOpts()
+        nbytes = mc_batch_workspace_bytes(models, self._opts)
+        self.device = torch.device(device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif workspace.numel() < nbytes:
+            raise ValueError(f"batch workspace needs {nbytes} bytes")
+        self.workspace = workspace
+        if stream is None:
+            # a graph needs a capturable stream of its own (default priority)
+            stream = (torch.cuda.Stream(self.device) if self._opts.use_graph
+                      else torch.cuda.current_stream(self.device))
+        self.stream = stream
+        if self._opts.use_graph:
+            # the workspace was allocated on the current stream: order it before ours
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        h = ctypes.c_void_p()
+        _check("mc_batch_create",
+               _lib.mc_batch_create(self._arr, self.n, ctypes.byref(self._opts),
+                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.last_stats: dict = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.mc_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def mc_batch_min_time(self) -> tuple[list[int], list[int]]:
+        t = np.zeros(self.n, dtype=np.uint32)
+        st_ = np.zeros(self.n, dtype=np.uint64)
+        st = McStats()
+        _check("mc_batch_min_time",
+               _lib.mc_batch_min_time(self._h, t.ctypes.data_as(_u32p),
+                                      st_.ctypes.data_as(_u64p), ctypes.byref(st)))
+        self.last_stats = st.as_dict()
+        return [int(v) for v in t], [int(v) for v in st_]
+
+    def mc_batch_terminal_clocks(self, i: int) -> list[int | None]:
+        nc = len(self.models[i]["params"])
+        tc = np.zeros(nc, dtype=np.uint32)
+        _check("mc_batch_terminal_clocks",
+               _lib.mc_batch_terminal_clocks(self._h, i, tc.ctypes.data_as(_u32p), nc))
+        return [None if int(v) == NO_CLOCK else int(v) for v in tc]
 
 
 def exported_symbols() -> list[str]:

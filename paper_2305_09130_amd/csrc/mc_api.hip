@@ -29,7 +29,7 @@ uint64_t next_pow2(uint64_t x) {
 
 struct WsPlan {
   size_t ctrl = 0, tc = 0, cfgs = 0, order = 0, seeds = 0, front0 = 0, front1 = 0, trace = 0,
-         table = 0, total = 0;
+         table = 0, total = 0, md = 0, head = 0;
   uint64_t slots = 0;
   uint32_t slot_bytes = 0;
   uint64_t fcap = 0;
@@ -56,7 +56,9 @@ int plan_ws(const ModelHost& mh, const mc_opts& o, WsPlan* p) {
   p->ctrl = off;   off = align_up(off + sizeof(Ctrl));
   p->tc = off;     off = align_up(off + 4ull * mh.n_cfg);
   p->cfgs = off;   off = align_up(off + sizeof(CfgRec) * mh.n_cfg);
-  p->order = off;  off = align_up(off + 4ull * mh.n_cfg);
+  p->order = off;  off = align_up(off + 8ull * mh.n_cfg);
+  p->md = off;     off = align_up(off + sizeof(ModelDev));
+  p->head = off;   off = align_up(off + 4);
   p->seeds = off;  off = align_up(off + sizeof(Seed) * mh.n_cfg);
   p->fcap = mh.frontier_bound + 64;
   p->front0 = off; off = align_up(off + entry * p->fcap);
@@ -122,7 +124,10 @@ struct mc_model {
   Ctrl* ctrl = nullptr;
   uint32_t* tc = nullptr;
   CfgRec* cfgs = nullptr;
-  uint32_t* order = nullptr;
+  uint2* parts = nullptr;
+  ModelDev* dmd = nullptr;
+  unsigned int* head = nullptr;
+  ModelDev* hmd = nullptr;  // pinned host staging of the device descriptor
   Seed* seeds = nullptr;
   unsigned char* front[2] = {nullptr, nullptr};
   unsigned long long* trace_buf = nullptr;
@@ -157,7 +162,7 @@ QueryArgs make_args(mc_model* h, bool prune, uint32_t T) {
 }
 
 template <int W>
-int engine_w(mc_model* h, const QueryArgs& q, uint64_t* launches);
+int level_loop(mc_model* h, const QueryArgs& q, uint64_t* launches);
 
 template <int W>
 int explore_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
@@ -165,25 +170,14 @@ int explore_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   HIPCHK(launch_seed<W>(s, q, h->seeds, h->front[0]));
   *launches = 1;
   HIPCHK(hipEventRecord(h->ev[4], s));
-  const int rc = engine_w<W>(h, q, launches);
+  const int rc = level_loop<W>(h, q, launches);
   HIPCHK(hipEventRecord(h->ev[5], s));
   return rc;
 }
 
 template <int W>
-int engine_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
+int level_loop(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   hipStream_t s = h->stream;
-  if (h->opts.engine == MC_ENGINE_SUPERSTEP) {
-    SuperArgs sa;
-    sa.q = q;
-    sa.order = h->order;
-    sa.seeds = h->seeds;
-    sa.n_parts = h->mh.n_cfg;
-    uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->mh.n_cfg, 4096u);
-    HIPCHK(launch_super<W>(s, grid, h->opts.block, sa));
-    *launches += 1;
-    return MC_OK;
-  }
   // plain level-synchronous BFS: one launch per level; the frontier size lives on the
   // device, the host polls it once per batch of launches
   const uint64_t fcap = h->plan.fcap;
@@ -224,15 +218,45 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     HIPCHK(hipEventRecord(h->ev[1], s));
     cleared = true;
   }
-  HIPCHK(launch_reset(s, h->ctrl, h->tc, h->mh.n_cfg));
   const QueryArgs q = make_args(h, prune, T);
-  HIPCHK(hipEventRecord(h->ev[2], s));
   uint64_t launches = 0;
-  int rc;
-  switch (h->mh.W) {
-    case 1: rc = explore_w<1>(h, q, &launches); break;
-    case 2: rc = explore_w<2>(h, q, &launches); break;
-    default: rc = explore_w<4>(h, q, &launches); break;
+  int rc = MC_OK;
+  if (h->opts.engine == MC_ENGINE_SUPERSTEP) {
+    ModelDev& md = *h->hmd;
+    md.ctrl = h->ctrl;
+    md.tc = h->tc;
+    md.cfgs = h->cfgs;
+    md.seeds = h->seeds;
+    md.table = h->table;
+    md.mask = h->plan.slots - 1;
+    md.L = h->mh.layout;
+    md.n_cfg = h->mh.n_cfg;
+    md.prune = prune ? 1u : 0u;
+    md.T = T;
+    md.max_clock = h->mh.max_clock;
+    HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_reset_models(s, h->dmd, 1, h->head));
+    HIPCHK(hipEventRecord(h->ev[2], s));
+    HIPCHK(launch_seed_models(s, h->dmd, 1));
+    HIPCHK(hipEventRecord(h->ev[4], s));
+    PartQueue pq;
+    pq.models = h->dmd;
+    pq.parts = h->parts;
+    pq.n_parts = h->mh.n_cfg;
+    pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * h->opts.block;
+    pq.head = h->head;
+    const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->mh.n_cfg, 4096u);
+    HIPCHK(launch_super(s, grid, h->opts.block, pq));
+    HIPCHK(hipEventRecord(h->ev[5], s));
+    launches = 2;
+  } else {
+    HIPCHK(launch_reset(s, h->ctrl, h->tc, h->mh.n_cfg));
+    HIPCHK(hipEventRecord(h->ev[2], s));
+    switch (h->mh.W) {
+      case 1: rc = explore_w<1>(h, q, &launches); break;
+      case 2: rc = explore_w<2>(h, q, &launches); break;
+      default: rc = explore_w<4>(h, q, &launches); break;
+    }
   }
   h->dirty = true;
   if (rc != MC_OK) {
@@ -261,6 +285,11 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     st->explore_ns = (uint64_t)(ms_explore * 1e6);
     st->clear_ns = (uint64_t)(ms_clear * 1e6);
     st->engine_ns = (uint64_t)(ms_engine * 1e6);
+    st->supersteps = h->hctrl->supersteps;
+    st->batches = h->hctrl->chunks;
+    st->max_probe = h->hctrl->max_probe;
+    st->critical_ns = h->hctrl->crit_ticks * 10ull;  // 100 MHz device clock
+    st->critical_cfg = h->hctrl->crit_part;
     st->total_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                        std::chrono::steady_clock::now() - t0)
                        .count();
@@ -363,6 +392,7 @@ int mc_model_free(mc_model* h) {
     if (e) (void)hipEventDestroy(e);
   if (h->hctrl) (void)hipHostFree(h->hctrl);
   if (h->hpoll) (void)hipHostFree(h->hpoll);
+  if (h->hmd) (void)hipHostFree(h->hmd);
   delete h;
   return MC_OK;
 }
@@ -395,7 +425,9 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     h->ctrl = reinterpret_cast<Ctrl*>(h->ws + h->plan.ctrl);
     h->tc = reinterpret_cast<uint32_t*>(h->ws + h->plan.tc);
     h->cfgs = reinterpret_cast<CfgRec*>(h->ws + h->plan.cfgs);
-    h->order = reinterpret_cast<uint32_t*>(h->ws + h->plan.order);
+    h->parts = reinterpret_cast<uint2*>(h->ws + h->plan.order);
+    h->dmd = reinterpret_cast<ModelDev*>(h->ws + h->plan.md);
+    h->head = reinterpret_cast<unsigned int*>(h->ws + h->plan.head);
     h->seeds = reinterpret_cast<Seed*>(h->ws + h->plan.seeds);
     h->front[0] = h->ws + h->plan.front0;
     h->front[1] = h->ws + h->plan.front1;
@@ -404,7 +436,9 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     h->tc_host.assign(h->mh.n_cfg, kNoClock);
     if (hipHostMalloc(reinterpret_cast<void**>(&h->hctrl), sizeof(Ctrl), hipHostMallocDefault) !=
             hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 64, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 64, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->hmd), sizeof(ModelDev), hipHostMallocDefault) !=
+            hipSuccess) {
       (void)hipGetLastError();
       mc_model_free(h);
       return MC_E_DEVICE;
@@ -422,10 +456,12 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
       return h->mh.cfg_states[a] > h->mh.cfg_states[b];
     });
+    std::vector<uint2> parts(h->mh.n_cfg);
+    for (uint32_t i = 0; i < h->mh.n_cfg; ++i) parts[i] = make_uint2(0u, order[i]);
     hipStream_t s = h->stream;
     if (hipMemcpyAsync(h->cfgs, h->mh.cfgs.data(), sizeof(CfgRec) * h->mh.n_cfg,
                        hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(h->order, order.data(), 4ull * h->mh.n_cfg, hipMemcpyHostToDevice, s) !=
+        hipMemcpyAsync(h->parts, parts.data(), 8ull * h->mh.n_cfg, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       (void)hipGetLastError();

@@ -1,0 +1,476 @@
+// mc_batch.hip -- many models explored in one persistent launch: arena layout, the
+// (model, configuration) partition queue, the autotuner and hipGraph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mctune.h"
+#include "mc_launch.h"
+#include "mc_model.h"
+
+using namespace mc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
+constexpr size_t kCtrlStride = 256;
+
+struct BatchPlan {
+  size_t ctrl = 0, tc = 0, cfgs = 0, seeds = 0, md = 0, parts = 0, head = 0, tables = 0;
+  size_t tables_bytes = 0, total = 0;
+  std::vector<size_t> tc_off, cfg_off, seed_off, table_off;
+  std::vector<uint64_t> slots;
+  uint64_t n_parts = 0;
+};
+
+mc_batch_opts default_bopts(const mc_batch_opts* o) {
+  mc_batch_opts r;
+  std::memset(&r, 0, sizeof(r));
+  if (o) r = *o;
+  if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 512;
+  if (!(r.load_factor > 0.f && r.load_factor < 1.f)) r.load_factor = 0.5f;
+  return r;
+}
+
+int plan_batch(const std::vector<ModelHost>& ms, const mc_batch_opts& o, BatchPlan* p) {
+  const size_t n = ms.size();
+  size_t off = 0;
+  p->ctrl = off;
+  off = align_up(off + kCtrlStride * n);
+  p->tc = off;
+  p->tc_off.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    p->tc_off[i] = off;
+    off += 4ull * ms[i].n_cfg;
+  }
+  off = align_up(off);
+  p->cfg_off.resize(n);
+  p->cfgs = off;
+  for (size_t i = 0; i < n; ++i) {
+    p->cfg_off[i] = off;
+    off += sizeof(CfgRec) * ms[i].n_cfg;
+  }
+  off = align_up(off);
+  p->seed_off.resize(n);
+  p->seeds = off;
+  for (size_t i = 0; i < n; ++i) {
+    p->seed_off[i] = off;
+    off += sizeof(Seed) * ms[i].n_cfg;
+  }
+  off = align_up(off);
+  p->md = off;
+  off = align_up(off + sizeof(ModelDev) * n);
+  p->n_parts = 0;
+  for (const auto& m : ms) p->n_parts += m.n_cfg;
+  p->parts = off;
+  off = align_up(off + 8ull * p->n_parts);
+  p->head = off;
+  off = align_up(off + 4);
+  p->tables = off;
+  p->table_off.resize(n);
+  p->slots.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    uint64_t slots = next_pow2((uint64_t)((double)ms[i].states / o.load_factor) + 1);
+    slots = std::max<uint64_t>(slots, 1024);
+    if (slots > (1ull << 31)) return MC_E_INVAL;
+    p->slots[i] = slots;
+    p->table_off[i] = off;
+    off = align_up(off + slots * slot_bytes_for(ms[i].W));
+  }
+  p->tables_bytes = off - p->tables;
+  p->total = off;
+  return MC_OK;
+}
+
+int build_models(const mc_desc* models, uint32_t n, std::vector<ModelHost>* ms) {
+  if (!models || n == 0) return MC_E_INVAL;
+  ms->resize(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    std::string err;
+    const int rc = build_model(&models[i], &(*ms)[i], &err);
+    if (rc) return rc;
+  }
+  return MC_OK;
+}
+
+#define HIPCHK(x)              \
+  do {                         \
+    hipError_t e_ = (x);       \
+    if (e_ != hipSuccess) {    \
+      (void)hipGetLastError(); \
+      return MC_E_DEVICE;      \
+    }                          \
+  } while (0)
+
+}  // namespace
+
+struct mc_batch {
+  std::vector<ModelHost> ms;
+  mc_batch_opts opts{};
+  BatchPlan plan;
+  hipStream_t stream = nullptr;
+  unsigned char* ws = nullptr;
+  ModelDev* dmd = nullptr;
+  uint2* parts = nullptr;
+  unsigned int* head = nullptr;
+  unsigned char* hctrl = nullptr;  // pinned: n * kCtrlStride
+  uint32_t* htc = nullptr;         // pinned: all clocks
+  size_t tc_words = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ran = false;
+  uint32_t grid = 0;
+};
+
+namespace {
+
+int enqueue_query(mc_batch* b) {
+  hipStream_t s = b->stream;
+  const uint32_t n = (uint32_t)b->ms.size();
+  HIPCHK(launch_clear(s, b->ws + b->plan.tables, b->plan.tables_bytes));
+  HIPCHK(launch_reset_models(s, b->dmd, n, b->head));
+  HIPCHK(launch_seed_models(s, b->dmd, n));
+  PartQueue pq;
+  pq.models = b->dmd;
+  pq.parts = b->parts;
+  pq.n_parts = (uint32_t)b->plan.n_parts;
+  pq.batch_items = b->opts.chunk ? b->opts.chunk : 2u * b->opts.block;
+  pq.head = b->head;
+  HIPCHK(launch_super(s, b->grid, b->opts.block, pq));
+  HIPCHK(hipMemcpyAsync(b->hctrl, b->ws + b->plan.ctrl, kCtrlStride * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(b->htc, b->ws + b->plan.tc, 4ull * b->tc_words, hipMemcpyDeviceToHost, s));
+  return MC_OK;
+}
+
+void free_batch(mc_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->hctrl) (void)hipHostFree(b->hctrl);
+  if (b->htc) (void)hipHostFree(b->htc);
+  delete b;
+}
+
+// autotuner cache: batch signature -> chosen options
+std::mutex g_tune_mu;
+std::map<std::string, mc_batch_opts> g_tune_cache;
+
+std::string signature(const std::vector<ModelHost>& ms) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  for (const auto& m : ms) {
+    mix(m.desc.kind);
+    mix(m.m);
+    mix(m.n_cfg);
+    mix(m.states);
+    mix(m.desc.lat_global);
+    mix(m.desc.lat_local);
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "?";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  (void)hipGetLastError();
+  return arch + ":" + std::to_string(ms.size()) + ":" + std::to_string(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mc_batch_workspace_bytes(const mc_desc* models, uint32_t n, const mc_batch_opts* o,
+                             size_t* bytes) {
+  if (!bytes) return MC_E_INVAL;
+  try {
+    std::vector<ModelHost> ms;
+    int rc = build_models(models, n, &ms);
+    if (rc) return rc;
+    BatchPlan p;
+    rc = plan_batch(ms, default_bopts(o), &p);
+    if (rc) return rc;
+    *bytes = p.total;
+    return MC_OK;
+  } catch (...) {
+    return MC_E_INVAL;
+  }
+}
+
+int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, void* dev_ws,
+                    size_t ws_bytes, void* stream, mc_batch** out) {
+  if (!out || !dev_ws) return MC_E_INVAL;
+  *out = nullptr;
+  mc_batch* b = nullptr;
+  try {
+    b = new mc_batch();
+    int rc = build_models(models, n, &b->ms);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+    b->opts = default_bopts(o);
+    rc = plan_batch(b->ms, b->opts, &b->plan);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+    if (ws_bytes < b->plan.total) {
+      delete b;
+      return MC_E_NOMEM;
+    }
+    b->stream = reinterpret_cast<hipStream_t>(stream);
+    b->ws = reinterpret_cast<unsigned char*>(dev_ws);
+    b->dmd = reinterpret_cast<ModelDev*>(b->ws + b->plan.md);
+    b->parts = reinterpret_cast<uint2*>(b->ws + b->plan.parts);
+    b->head = reinterpret_cast<unsigned int*>(b->ws + b->plan.head);
+    for (const auto& m : b->ms) b->tc_words += m.n_cfg;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->hctrl), kCtrlStride * n, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->htc), 4ull * b->tc_words,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess) {
+      (void)hipGetLastError();
+      free_batch(b);
+      return MC_E_DEVICE;
+    }
+    // descriptors, configuration tables and the partition queue (largest first)
+    std::vector<ModelDev> md(n);
+    std::vector<CfgRec> cfgs;
+    struct P {
+      uint64_t size;
+      uint32_t model, cfg;
+    };
+    std::vector<P> ps;
+    ps.reserve(b->plan.n_parts);
+    for (uint32_t i = 0; i < n; ++i) {
+      const ModelHost& m = b->ms[i];
+      ModelDev& d = md[i];
+      std::memset(&d, 0, sizeof(d));
+      d.ctrl = reinterpret_cast<Ctrl*>(b->ws + b->plan.ctrl + kCtrlStride * i);
+      d.tc = reinterpret_cast<uint32_t*>(b->ws + b->plan.tc_off[i]);
+      d.cfgs = reinterpret_cast<const CfgRec*>(b->ws + b->plan.cfg_off[i]);
+      d.seeds = reinterpret_cast<Seed*>(b->ws + b->plan.seed_off[i]);
+      d.table = b->ws + b->plan.table_off[i];
+      d.mask = b->plan.slots[i] - 1;
+      d.L = m.layout;
+      d.n_cfg = m.n_cfg;
+      d.max_clock = m.max_clock;
+      for (uint32_t c = 0; c < m.n_cfg; ++c) ps.push_back({m.cfg_states[c], i, c});
+    }
+    std::stable_sort(ps.begin(), ps.end(), [](const P& a, const P& c) { return a.size > c.size; });
+    std::vector<uint2> parts(ps.size());
+    for (size_t k = 0; k < ps.size(); ++k) parts[k] = make_uint2(ps[k].model, ps[k].cfg);
+    hipStream_t s = b->stream;
+    for (uint32_t i = 0; i < n; ++i)
+      if (hipMemcpyAsync(b->ws + b->plan.cfg_off[i], b->ms[i].cfgs.data(),
+                         sizeof(CfgRec) * b->ms[i].n_cfg, hipMemcpyHostToDevice, s) != hipSuccess) {
+        (void)hipGetLastError();
+        free_batch(b);
+        return MC_E_DEVICE;
+      }
+    if (hipMemcpyAsync(b->dmd, md.data(), sizeof(ModelDev) * n, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(b->parts, parts.data(), 8ull * parts.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipGetLastError();
+      free_batch(b);
+      return MC_E_DEVICE;
+    }
+    b->grid = b->opts.grid ? b->opts.grid
+                           : (uint32_t)std::min<uint64_t>(b->plan.n_parts,
+                                                          b->opts.block >= 1024 ? 512u : 1024u);
+    if (b->opts.use_graph) {
+      if (s == nullptr) {  // the null stream cannot be captured
+        free_batch(b);
+        return MC_E_INVAL;
+      }
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        free_batch(b);
+        return MC_E_DEVICE;
+      }
+      const int erc = enqueue_query(b);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (erc != MC_OK || e2 != hipSuccess || !g ||
+          hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        free_batch(b);
+        return MC_E_DEVICE;
+      }
+      b->graph = g;
+    }
+    *out = b;
+    return MC_OK;
+  } catch (const std::bad_alloc&) {
+    if (b) free_batch(b);
+    return MC_E_NOMEM;
+  } catch (...) {
+    if (b) free_batch(b);
+    return MC_E_INVAL;
+  }
+}
+
+int mc_batch_min_time(mc_batch* b, uint32_t* t_min, uint64_t* states, mc_stats* st) {
+  if (!b) return MC_E_INVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = b->stream;
+  HIPCHK(hipEventRecord(b->ev[0], s));
+  if (b->exec) {
+    HIPCHK(hipGraphLaunch(b->exec, s));
+  } else {
+    const int rc = enqueue_query(b);
+    if (rc) return rc;
+  }
+  HIPCHK(hipEventRecord(b->ev[1], s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+  const uint32_t n = (uint32_t)b->ms.size();
+  mc_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  size_t tcpos = 0;
+  int rc = MC_OK;
+  for (uint32_t i = 0; i < n; ++i) {
+    const Ctrl* c = reinterpret_cast<const Ctrl*>(b->hctrl + kCtrlStride * i);
+    if (c->error && rc == MC_OK)
+      rc = c->error == 1u ? MC_E_TABLE_FULL : c->error == 2u ? MC_E_OVERFLOW : MC_E_DEVICE;
+    uint32_t best = kNoClock;
+    for (uint32_t k = 0; k < b->ms[i].n_cfg; ++k) best = std::min(best, b->htc[tcpos + k]);
+    tcpos += b->ms[i].n_cfg;
+    if (t_min) t_min[i] = best;
+    if (states) states[i] = c->states;
+    acc.states += c->states;
+    acc.terminals += c->terminals;
+    acc.edges += c->edges;
+    acc.dups += c->dups;
+    acc.probes += c->probes;
+    acc.levels = std::max<uint64_t>(acc.levels, c->max_depth + 1);
+    acc.supersteps += c->supersteps;
+    acc.batches += c->chunks;
+    acc.max_probe = std::max<uint64_t>(acc.max_probe, c->max_probe);
+    if (c->crit_ticks * 10ull > acc.critical_ns) {
+      acc.critical_ns = c->crit_ticks * 10ull;
+      acc.critical_cfg = c->crit_part;
+    }
+  }
+  acc.launches = b->exec ? 1 : 4;
+  acc.explore_ns = (uint64_t)(ms * 1e6);
+  acc.engine_ns = acc.explore_ns;
+  acc.total_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                     std::chrono::steady_clock::now() - t0)
+                     .count();
+  if (st) *st = acc;
+  b->ran = rc == MC_OK;
+  return rc;
+}
+
+int mc_batch_terminal_clocks(const mc_batch* b, uint32_t model, uint32_t* tc, size_t cap) {
+  if (!b || !tc || model >= b->ms.size()) return MC_E_INVAL;
+  if (!b->ran) return MC_E_STATE;
+  if (cap < b->ms[model].n_cfg) return MC_E_BUFFER;
+  size_t pos = 0;
+  for (uint32_t i = 0; i < model; ++i) pos += b->ms[i].n_cfg;
+  std::memcpy(tc, b->htc + pos, 4ull * b->ms[model].n_cfg);
+  return MC_OK;
+}
+
+int mc_batch_free(mc_batch* b) {
+  if (!b) return MC_E_INVAL;
+  free_batch(b);
+  return MC_OK;
+}
+
+// Autotuner: runs the batch once per candidate (block, load factor, batch items) in the
+// caller's workspace (sized for the smallest load factor tried) and keeps the fastest;
+// results are cached per batch signature and device architecture.
+int mc_batch_autotune(const mc_desc* models, uint32_t n, void* dev_ws, size_t ws_bytes,
+                      void* stream, mc_batch_opts* best, float* best_ms) {
+  if (!best) return MC_E_INVAL;
+  try {
+    std::vector<ModelHost> ms;
+    int rc = build_models(models, n, &ms);
+    if (rc) return rc;
+    const std::string sig = signature(ms);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(sig);
+      if (it != g_tune_cache.end()) {
+        *best = it->second;
+        if (best_ms) *best_ms = -1.f;
+        return MC_OK;
+      }
+    }
+    const uint32_t blocks[] = {256, 512, 1024};
+    const float lfs[] = {0.25f, 0.5f, 0.7f};
+    const uint32_t items_mult[] = {1, 2, 4};
+    float best_t = 1e30f;
+    mc_batch_opts bo;
+    std::memset(&bo, 0, sizeof(bo));
+    bool any = false;
+    for (float lf : lfs) {
+      for (uint32_t bl : blocks) {
+        for (uint32_t im : items_mult) {
+          mc_batch_opts o;
+          std::memset(&o, 0, sizeof(o));
+          o.block = bl;
+          o.load_factor = lf;
+          o.chunk = im * bl;
+          size_t need = 0;
+          rc = mc_batch_workspace_bytes(models, n, &o, &need);
+          if (rc || need > ws_bytes) continue;
+          mc_batch* b = nullptr;
+          rc = mc_batch_create(models, n, &o, dev_ws, ws_bytes, stream, &b);
+          if (rc) continue;
+          mc_stats st;
+          float t = 1e30f;
+          for (int rep = 0; rep < 2; ++rep) {  // first run warms the code object
+            if (mc_batch_min_time(b, nullptr, nullptr, &st) == MC_OK)
+              t = std::min(t, (float)(st.explore_ns * 1e-6));
+          }
+          mc_batch_free(b);
+          if (t < best_t) {
+            best_t = t;
+            bo = o;
+            any = true;
+          }
+        }
+      }
+    }
+    if (!any) return MC_E_NOMEM;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[sig] = bo;
+    }
+    *best = bo;
+    if (best_ms) *best_ms = best_t;
+    return MC_OK;
+  } catch (...) {
+    return MC_E_INVAL;
+  }
+}
+
+}  // extern "C"

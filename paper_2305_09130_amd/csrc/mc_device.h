@@ -26,7 +26,12 @@ struct Ctrl {
   unsigned int trace_len;
   unsigned int target_slot;
   unsigned int sim_t, sim_cfg;
-  unsigned int pad[16];
+  unsigned int max_probe;        // longest probe sequence of one insert
+  unsigned int crit_part;        // partition with the longest exploration time
+  unsigned long long supersteps; // super-steps (persistent engine)
+  unsigned long long chunks;     // insert batches (persistent engine)
+  unsigned long long crit_ticks; // longest partition time, 100 MHz ticks
+  unsigned int pad[8];
 };
 static_assert(sizeof(Ctrl) == 160, "Ctrl layout");
 
@@ -132,10 +137,10 @@ __device__ __forceinline__ unsigned long long fmix64(unsigned long long x) {
 
 template <int W>
 __device__ __forceinline__ unsigned long long key_hash(const Key<W>& k) {
-  unsigned long long h = fmix64(k.w[0] + 0x9e3779b97f4a7c15ull);
+  unsigned long long h = k.w[0] * 0x9e3779b97f4a7c15ull;
 #pragma unroll
-  for (int j = 1; j < W; ++j) h = fmix64(h ^ (k.w[j] + 0x632be59bd9b4e019ull * j));
-  return h;
+  for (int j = 1; j < W; ++j) h ^= (k.w[j] + (unsigned long long)j) * 0xd6e8feb86659fd93ull;
+  return fmix64(h);
 }
 
 __device__ __forceinline__ bool is_terminal(const St& s, int m) {
@@ -210,64 +215,112 @@ __device__ __forceinline__ uint32_t* slot_pub(unsigned char* base, unsigned long
   return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W + 4u);
 }
 constexpr uint32_t kPublished = 1u;
+// jump word: first predecessor of the lock-step run a state belongs to (else 0xFFFFFFFF);
+// one-word keys never publish, so they keep it in the publish word
+template <int W>
+__device__ __forceinline__ uint32_t* slot_jump(unsigned char* base, unsigned long long s) {
+  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + (W == 1 ? 12u : 8u * W + 8u));
+}
 
 constexpr int kScopeWG = __HIP_MEMORY_SCOPE_WORKGROUP;
 constexpr int kScopeAgent = __HIP_MEMORY_SCOPE_AGENT;
 
 enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 
-// Open addressing with linear probing; a 64-bit compare-and-swap on key word 0 claims
-// a slot.  Wider keys are claimed on word 0, then the winner writes the other words and
-// publishes them (release) through the slot's publish word;
-// a lane that finds its own word 0 in a slot waits for the publish and compares the
-// rest.  Waiting never blocks inside an iteration: every lane of the wavefront runs
-// the same iteration loop, and a winner publishes in the iteration it won, so a
-// waiting lane cannot starve a winner of its own wavefront.  SCOPE is the widest set
-// of threads that may insert the same key: the workgroup in the super-step engine
-// (one configuration's subgraph per workgroup, configuration index in word 0), the
-// device in the level engine.
+// Open addressing in windows of kWin consecutive slots; windows are visited in a
+// double-hashing sequence (odd step, so every window is reached).  A probe reads the
+// window's word 0 as hints (one round trip), then claims the first empty slot with a
+// 64-bit compare-and-swap on word 0 (a second round trip).  Hints can only be stale in
+// one direction (a slot never returns to empty within a query), and a failed CAS
+// returns the slot's actual word, so hints never cause a wrong verdict.
+// Wider keys are claimed on word 0; the winner then writes the other words and
+// publishes them (release) through the slot's publish word; a lane that finds its own
+// word 0 in a slot waits for the publish and compares the rest.  One slot is handled
+// per loop iteration and waiting never spins inside an iteration: every lane of the
+// wavefront runs the same loop, and a winner publishes in the iteration it won, so a
+// waiting lane cannot starve a winner of its own wavefront.  SCOPE is the widest set of
+// threads that may insert the same key: the workgroup in the super-step engine (one
+// configuration's subgraph per workgroup, configuration index in word 0), the device
+// in the level engine.  Empty slots never precede a key in its probe sequence, so a
+// lookup stops at the first empty slot.
+constexpr int kWin = 4;
+
+__device__ __forceinline__ void probe_start(unsigned long long h, unsigned long long mask,
+                                            unsigned long long& wi, unsigned long long& step) {
+  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  wi = h & nwin_mask;
+  step = ((h >> 33) | 1ull) & nwin_mask;
+  step |= 1ull;
+}
+
 template <int W, int SCOPE>
 __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long long mask,
                                             const Key<W>& k, uint32_t& slot_out,
                                             uint32_t& probes) {
-  unsigned long long s = key_hash<W>(k) & mask;
+  unsigned long long wi, step;
+  probe_start(key_hash<W>(k), mask, wi, step);
+  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  const unsigned long long max_iters =
+      (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
+  unsigned long long h0 = 0, h1 = 0, h2 = 0, h3 = 0;  // window hints (word 0)
+  int j = kWin;  // slot within the window; kWin = load the next window
   bool waiting = false;
-  const unsigned long long iters = mask < kMaxProbeIters ? mask + 1ull : kMaxProbeIters;
-  for (unsigned long long it = 0; it < iters; ++it) {
-    unsigned long long* p = slot_key<W>(base, s);
-    if (!waiting) {
+  for (unsigned long long it = 0; it < max_iters; ++it) {
+    if (j == kWin) {
       ++probes;
-      const unsigned long long old = atomicCAS(p, kEmptyWord, k.w[0]);
-      if (old == kEmptyWord) {
-        if (W > 1) {
+      const unsigned long long s0 = wi * kWin;
+      h0 = __hip_atomic_load(slot_key<W>(base, s0 + 0), __ATOMIC_RELAXED, SCOPE);
+      h1 = __hip_atomic_load(slot_key<W>(base, s0 + 1), __ATOMIC_RELAXED, SCOPE);
+      h2 = __hip_atomic_load(slot_key<W>(base, s0 + 2), __ATOMIC_RELAXED, SCOPE);
+      h3 = __hip_atomic_load(slot_key<W>(base, s0 + 3), __ATOMIC_RELAXED, SCOPE);
+      j = 0;
+    }
+    const unsigned long long s = wi * kWin + (unsigned long long)j;
+    unsigned long long* p = slot_key<W>(base, s);
+    bool advance = false;
+    if (waiting) {
+      const uint32_t pub = __hip_atomic_load(slot_pub<W>(base, s), __ATOMIC_ACQUIRE, SCOPE);
+      if (pub == kPublished) {
+        bool eq = true;
 #pragma unroll
-          for (int j = 1; j < W; ++j) __hip_atomic_store(p + j, k.w[j], __ATOMIC_RELAXED, SCOPE);
-          __hip_atomic_store(slot_pub<W>(base, s), kPublished, __ATOMIC_RELEASE, SCOPE);
+        for (int q = 1; q < W; ++q) eq &= __hip_atomic_load(p + q, __ATOMIC_RELAXED, SCOPE) == k.w[q];
+        if (eq) {
+          slot_out = (uint32_t)s;
+          return kInsDup;
         }
-        slot_out = (uint32_t)s;
-        return kInsNew;
+        waiting = false;
+        advance = true;
       }
-      if (old != k.w[0]) {
-        s = (s + 1) & mask;
-        continue;
-      }
-      if (W == 1) {
-        slot_out = (uint32_t)s;
-        return kInsDup;
-      }
-      waiting = true;
-    }
-    const uint32_t pub = __hip_atomic_load(slot_pub<W>(base, s), __ATOMIC_ACQUIRE, SCOPE);
-    if (pub != kPublished) continue;
-    bool eq = true;
+    } else {
+      unsigned long long v = j == 0 ? h0 : j == 1 ? h1 : j == 2 ? h2 : h3;
+      if (v == kEmptyWord) {
+        const unsigned long long old = atomicCAS(p, kEmptyWord, k.w[0]);
+        if (old == kEmptyWord) {
+          if (W > 1) {
 #pragma unroll
-    for (int j = 1; j < W; ++j) eq &= __hip_atomic_load(p + j, __ATOMIC_RELAXED, SCOPE) == k.w[j];
-    if (eq) {
-      slot_out = (uint32_t)s;
-      return kInsDup;
+            for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, k.w[q], __ATOMIC_RELAXED, SCOPE);
+            __hip_atomic_store(slot_pub<W>(base, s), kPublished, __ATOMIC_RELEASE, SCOPE);
+          }
+          slot_out = (uint32_t)s;
+          return kInsNew;
+        }
+        ++probes;
+        v = old;
+      }
+      if (v == k.w[0]) {
+        if (W == 1) {
+          slot_out = (uint32_t)s;
+          return kInsDup;
+        }
+        waiting = true;
+      } else {
+        advance = true;
+      }
     }
-    waiting = false;
-    s = (s + 1) & mask;
+    if (advance) {
+      ++j;
+      if (j == kWin) wi = (wi + step) & nwin_mask;
+    }
   }
   return kInsFail;
 }
@@ -276,15 +329,20 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
 template <int W>
 __device__ __forceinline__ uint32_t table_find(unsigned char* base, unsigned long long mask,
                                                const Key<W>& k) {
-  unsigned long long s = key_hash<W>(k) & mask;
-  for (unsigned long long it = 0; it <= mask; ++it) {
-    const unsigned long long* p = slot_key<W>(base, s);
-    if (p[0] == kEmptyWord) return kParentNone;
-    bool eq = true;
+  unsigned long long wi, step;
+  probe_start(key_hash<W>(k), mask, wi, step);
+  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  for (unsigned long long it = 0; it <= nwin_mask; ++it) {
+    for (int j = 0; j < kWin; ++j) {
+      const unsigned long long s = wi * kWin + (unsigned long long)j;
+      const unsigned long long* p = slot_key<W>(base, s);
+      if (p[0] == kEmptyWord) return kParentNone;
+      bool eq = true;
 #pragma unroll
-    for (int j = 0; j < W; ++j) eq &= p[j] == k.w[j];
-    if (eq) return (uint32_t)s;
-    s = (s + 1) & mask;
+      for (int q = 0; q < W; ++q) eq &= p[q] == k.w[q];
+      if (eq) return (uint32_t)s;
+    }
+    wi = (wi + step) & nwin_mask;
   }
   return kParentNone;
 }

@@ -259,223 +259,489 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
 // ---- persistent super-step engine ------------------------------------------------------
 //
 // After SELECT the state graph is a disjoint union of one subgraph per configuration
-// (the configuration index never changes), so each workgroup takes a whole subgraph
-// from a queue (largest first) and explores it with workgroup-local synchronisation
-// only.  A super-step expands one frontier state f:
+// (the configuration index never changes), and the models of a batch are disjoint too.
+// Each persistent workgroup takes a whole (model, configuration) subgraph from a queue
+// (largest first) and explores it with workgroup-local synchronisation only.  A
+// super-step expands one frontier state f:
 //   * its DISPATCH closure: every set S of f's free units with |S| <= k* =
 //     min(pending, #free) started (zero time; all dispatch orders reach the same set,
 //     so the closure is enumerated as subsets; parent of S = S minus its highest unit);
 //   * from every leaf (|S| = k*), the run of ADVANCE steps up to the next workgroup
 //     completion.  When the busy units of the leaf are in lock step (same remaining
-//     time) the j-th state of the run is E[i0 + j] on every busy unit, computed
-//     directly per lane; otherwise the leaf contributes one ADVANCE step and the next
-//     super-step continues from it.
-// All states of the super-step are inserted in one parallel batch; run ends that are
-// new and non-terminal form the next frontier.  Every state of the subgraph is still
-// generated and inserted once per generation; only the exploration order differs from
-// the level engine.
+//     time) the j-th state of the run has operation end E[i0 + j] on every busy unit;
+//     its key is built directly as base + rem * M (+ the clock field), M having one
+//     bit at the low end of every busy unit's field.  Otherwise the leaf contributes
+//     one ADVANCE step and the next super-step continues from it.
+// A lock-step run from a single leaf ends in a state whose successors are again a
+// closure and a run; up to kSegMax such segments are generated from one frontier
+// state in the same batch, without waiting for the visited-set verdict on the run end.
+// Every generated state is a successor of a generated state, so only reachable states
+// are inserted, and the visited set alone decides which are new: a run end found to be
+// a duplicate was expanded by whoever inserted it first, and its re-expansion only
+// produces duplicates.  Run ends that are new and non-terminal form the next frontier.
+constexpr int kSegMax = 8;
+constexpr int kEMax = 4096;  // operation ends kept in LDS
+constexpr int kFCap = 256;   // frontier states per super-step level (LDS)
 
+struct SegDesc {
+  unsigned long long fkey[4];  // frontier state of the segment
+  unsigned long long base[4];  // run key with clock 0 and busy units' rem 0
+  unsigned long long M[4];     // one bit at the low end of every busy unit's rem field
+  uint32_t start, nclos, nleaf, len;
+  uint32_t kstar, freem, lock, idx0;
+  uint32_t e0, fclock, pend, fdep;
+  uint32_t fslot, nfree, aux, pad;
+};
+
+template <int BLOCK>
+struct SuperShared {
+  uint32_t E[kEMax];
+  uint32_t mslot[kSegMax][256];
+  uint8_t leaf[256];
+  uint32_t chunk_slot[BLOCK];
+  SegDesc seg[kSegMax];
+  uint32_t segfslot[kSegMax];
+  unsigned long long fkey[2][kFCap][4];
+  uint32_t fslot[2][kFCap];
+  uint32_t fdep[2][kFCap];
+  uint32_t fcount[2];
+  uint32_t part, carry, stop, nseg, total;
+  ModelDev md;  // descriptor of the model being explored
+};
+
+struct Tally {
+  unsigned long long states = 0, terms = 0, edges = 0, dups = 0, depth = 0, super = 0,
+                     chunks = 0;
+  uint32_t probes = 0, max_probe = 0;
+};
+
+// adds v to field f of a packed key (the field must not overflow into its neighbour)
+template <int W>
+__device__ __forceinline__ void field_add(unsigned long long* k, const Layout& L, int f,
+                                          unsigned long long v) {
+  const unsigned long long x = v << L.shift[f];
+  const int wf = L.word[f];
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (wf == j) k[j] += x;
+}
+
+__device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
 
 template <int W, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_superstep(SuperArgs a) {
-  constexpr int FCAP = 256;
-  constexpr int NW = BLOCK / 64;
-  __shared__ uint32_t s_mask_slot[256];
-  __shared__ uint8_t s_leaf[256];
-  __shared__ uint32_t s_chunk_slot[BLOCK];
-  __shared__ unsigned long long s_fkey[2][FCAP][W];
-  __shared__ uint32_t s_fslot[2][FCAP];
-  __shared__ uint32_t s_fdep[2][FCAP];
-  __shared__ uint32_t s_fcount[2];
-  __shared__ uint32_t s_wcnt[NW];
-  __shared__ uint32_t s_part, s_carry, s_stop;
-  const QueryArgs& q = a.q;
-  const int m = q.L.m;
+__device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch_items,
+                                  SuperShared<BLOCK>& sh) {
+  Tally tl;
+  const Layout& L = md.L;
+  const int m = L.m;
   const uint32_t tid = threadIdx.x;
-  unsigned long long n_states = 0, n_terms = 0, n_edges = 0, n_dups = 0, depth_max = 0;
-  uint32_t probes = 0;
-
-  if (tid == 0) s_stop = 0u;
-  for (;;) {
-    if (tid == 0) {
-      s_part = atomicAdd(&q.ctrl->queue_head, 1u);
-      if (__hip_atomic_load(&q.ctrl->error, __ATOMIC_RELAXED, kScopeAgent)) s_stop = 1u;
-    }
-    __syncthreads();
-    const uint32_t part = s_part;
-    if (part >= a.n_parts || s_stop) break;
-    const uint32_t c = a.order[part];
-    const CfgRec r = q.cfgs[c];
-    if (tid == 0) {
-      const Seed sd = a.seeds[c];
+  const CfgRec r = md.cfgs[c];
+  const bool e_lds = r.b <= (uint32_t)kEMax;
+  if (e_lds)
+    for (uint32_t k = tid; k < r.b; k += BLOCK) sh.E[k] = end_at(r, k);
+  if (tid == 0) {
+    const Seed sd = md.seeds[c];
 #pragma unroll
-      for (int w = 0; w < W; ++w) s_fkey[0][0][w] = sd.k[w];
-      s_fslot[0][0] = sd.slot;
-      s_fdep[0][0] = sd.depth;
-      s_fcount[0] = sd.slot == kParentNone ? 0u : 1u;
-      s_fcount[1] = 0u;
-    }
-    __syncthreads();
-    int cur = 0;
-    while (s_fcount[cur] > 0u && !s_stop) {
-      const uint32_t nf = s_fcount[cur] < (uint32_t)FCAP ? s_fcount[cur] : (uint32_t)FCAP;
-      for (uint32_t fi = 0; fi < nf; ++fi) {
-        Key<W> fk;
+    for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = sd.k[w];
+    sh.fslot[0][0] = sd.slot;
+    sh.fdep[0][0] = sd.depth;
+    sh.fcount[0] = sd.slot == kParentNone ? 0u : 1u;
+    sh.fcount[1] = 0u;
+  }
+  __syncthreads();
+  int cur = 0;
+  while (sh.fcount[cur] > 0u && !sh.stop) {
+    const uint32_t nf = sh.fcount[cur] < (uint32_t)kFCap ? sh.fcount[cur] : (uint32_t)kFCap;
+    for (uint32_t fi = 0; fi < nf; ++fi) {
+      // ---- segments of this super-step (one thread builds them) ----
+      if (tid == 0) {
+        Key<W> ck;
 #pragma unroll
-        for (int w = 0; w < W; ++w) fk.w[w] = s_fkey[cur][fi][w];
-        const uint32_t fslot = s_fslot[cur][fi];
-        const uint32_t fdep = s_fdep[cur][fi];
-        const St x = decode<W>(fk, q.L);
-        uint32_t freem = 0, busy = 0, brem = 0;
-        bool bsame = true;
+        for (int w = 0; w < W; ++w) ck.w[w] = sh.fkey[cur][fi][w];
+        uint32_t fslot = sh.fslot[cur][fi], fdep = sh.fdep[cur][fi];
+        uint32_t total = 0, nseg = 0;
+        bool decoded = false;  // sh.seg[nseg] already derived from the previous segment
+        for (;;) {
+          SegDesc& sg = sh.seg[nseg];
+          if (!decoded) {
+            const St x = decode<W>(ck, L);
+            uint32_t freem = 0, busy = 0, brem = 0;
+            bool bsame = true;
 #pragma unroll
-        for (int u = 0; u < kMaxCU; ++u) {
-          if (u < m) {
-            if (x.rem[u] == 0u) {
-              freem |= 1u << u;
-            } else {
-              if (busy && x.rem[u] != brem) bsame = false;
-              brem = x.rem[u];
-              busy |= 1u << u;
+            for (int u = 0; u < kMaxCU; ++u) {
+              if (u < m) {
+                if (x.rem[u] == 0u) {
+                  freem |= 1u << u;
+                } else {
+                  if (busy && x.rem[u] != brem) bsame = false;
+                  brem = x.rem[u];
+                  busy |= 1u << u;
+                }
+              }
             }
+            const uint32_t nfree = (uint32_t)__popc(freem);
+            const uint32_t kstar = x.pending < nfree ? x.pending : nfree;
+            if (kstar == 0u && busy == 0u) break;  // terminal
+#pragma unroll
+            for (int w = 0; w < W; ++w) sg.fkey[w] = ck.w[w];
+            sg.kstar = kstar;
+            sg.freem = freem;
+            sg.nfree = nfree;
+            sg.nclos = kstar ? (1u << nfree) - 1u : 0u;
+            uint32_t nleaf = 1;  // C(nfree, kstar)
+            for (uint32_t i = 1; i <= kstar; ++i) nleaf = nleaf * (nfree - kstar + i) / i;
+            sg.nleaf = nleaf;
+            const bool lock = kstar ? (busy == 0u) : bsame;
+            sg.lock = lock ? 1u : 0u;
+            sg.e0 = kstar ? 0u : r.d - brem;
+            sg.idx0 = lock ? ends_upto(r, sg.e0) : 0u;
+            sg.len = lock ? r.b - sg.idx0 : 1u;
+            sg.pend = x.pending - kstar;
+            sg.fclock = x.clock;
+            // run keys: every unit not busy in a lock-step run is idle
+            St b{};
+            b.cfg = x.cfg;
+            b.pending = sg.pend;
+            const Key<W> bk = encode<W>(b, L);
+            unsigned long long Mv[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) Mv[w] = 0ull;
+            const uint32_t busy_run = kstar ? freem : busy;  // single leaf: all free units start
+#pragma unroll
+            for (int u = 0; u < kMaxCU; ++u)
+              if (u < m && ((busy_run >> u) & 1u)) field_add<W>(Mv, L, kFRem + u, 1ull);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              sg.base[w] = bk.w[w];
+              sg.M[w] = Mv[w];
+            }
+            sg.aux = (kstar && busy == 0u && nleaf == 1u) ? 1u : 0u;  // a full round start
+          }
+          sg.fdep = fdep;
+          sg.fslot = fslot;
+          sg.start = total;
+          total += sg.nclos + sg.nleaf * sg.len;
+          ++nseg;
+          // continue with the run end: a single lock-step run ending with work pending
+          const uint32_t end_clock = sg.fclock + (r.d - sg.e0);
+          const bool more = sg.lock && sg.nleaf == 1u && sg.pend > 0u &&
+                            nseg < (uint32_t)kSegMax && total < batch_items &&
+                            !(md.prune && end_clock > md.T) && end_clock <= md.max_clock;
+          if (!more) break;
+          // the run end: every unit idle, `pend` workgroups pending
+          unsigned long long ek[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) ek[w] = sg.base[w];
+          field_add<W>(ek, L, kFClock, end_clock);
+#pragma unroll
+          for (int w = 0; w < W; ++w) ck.w[w] = ek[w];
+          fslot = kParentNone;  // known once the run end is claimed
+          fdep = fdep + sg.kstar + sg.len;
+          // a full round from an idle start followed by at least one more full round has
+          // the same shape: only the clock and the pending count move
+          decoded = sg.aux && sg.pend >= sg.nfree;
+          if (decoded) {
+            SegDesc& nx = sh.seg[nseg];
+            nx = sg;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              nx.fkey[w] = ek[w];
+              nx.base[w] = sg.base[w];
+            }
+            field_add<W>(nx.base, L, kFPending, (unsigned long long)(-(long long)sg.kstar));
+            nx.pend = sg.pend - sg.kstar;
+            nx.fclock = end_clock;
           }
         }
-        const uint32_t nfree = (uint32_t)__popc(freem);
-        const uint32_t kstar = x.pending < nfree ? x.pending : nfree;
-        if (kstar == 0u && busy == 0u) continue;  // terminal: no successors
-        const uint32_t nclos = kstar ? (1u << nfree) - 1u : 0u;
-        // leaves of the closure in ascending mask order
-        uint32_t nleaf = 1u;
-        if (kstar) {
-          const uint32_t mk = tid + 1u;
-          const bool isleaf = mk <= nclos && (uint32_t)__popc(mk) == kstar;
-          const unsigned long long bm = __ballot(isleaf);
-          if (lane_id() == 0) s_wcnt[tid >> 6] = (uint32_t)__popcll(bm);
-          __syncthreads();
+        sh.nseg = nseg;
+        sh.total = total;
+        sh.carry = sh.fslot[cur][fi];
+      }
+      __syncthreads();
+      const uint32_t nseg = sh.nseg;
+      const uint32_t total = sh.total;
+      tl.super += nseg;
+      // leaf list of a segment with several leaves (a partial round); only the last
+      // segment of a batch can have several
+      if (nseg && sh.seg[nseg - 1].nleaf > 1u) {
+        const SegDesc& sg = sh.seg[nseg - 1];
+        if (tid < 64) {
           uint32_t off = 0;
-          for (uint32_t w = 0; w < (tid >> 6); ++w) off += s_wcnt[w];
-          if (isleaf) s_leaf[off + lanes_below(bm)] = (uint8_t)mk;
-          nleaf = 0;
-          for (int w = 0; w < NW; ++w) nleaf += s_wcnt[w];
-          __syncthreads();
+          for (uint32_t g0 = 1; g0 <= sg.nclos; g0 += 64) {
+            const uint32_t mk = g0 + tid;
+            const bool isleaf = mk <= sg.nclos && (uint32_t)__popc(mk) == sg.kstar;
+            const unsigned long long bm = __ballot(isleaf);
+            if (isleaf) sh.leaf[off + lanes_below(bm)] = (uint8_t)mk;
+            off += (uint32_t)__popcll(bm);
+          }
         }
-        // lock step: round start (no unit busy before the dispatches) or a pure run
-        const bool lock = kstar ? (busy == 0u) : bsame;
-        const uint32_t e0 = kstar ? 0u : r.d - brem;
-        const uint32_t idx0 = lock ? ends_upto(r, e0) : 0u;
-        const uint32_t len = lock ? r.b - idx0 : 1u;
-        const uint32_t total = nclos + nleaf * len;
-        if (tid == 0) s_carry = fslot;
-        for (uint32_t base = 0; base < total; base += BLOCK) {
-          const uint32_t i = base + tid;
-          bool active = i < total;
-          const bool is_clos = i < nclos;
-          uint32_t rmask = 0, j = 0;
-          St y = x;
-          uint32_t dep = 0;
-          if (active) {
-            if (is_clos) {
-              rmask = i + 1u;
-            } else {
-              const uint32_t qq = i - nclos;
-              const uint32_t leaf = qq / len;
-              j = qq - leaf * len;
-              rmask = kstar ? (uint32_t)s_leaf[leaf] : 0u;
-            }
+        __syncthreads();
+      }
+      for (uint32_t base = 0; base < total; base += BLOCK) {
+        ++tl.chunks;
+        const uint32_t i = base + tid;
+        bool active = i < total;
+        uint32_t sgi = 0;
+        for (uint32_t k = 1; k < nseg; ++k)
+          if (i >= sh.seg[k].start) sgi = k;
+        const SegDesc& sg = sh.seg[sgi];
+        const uint32_t loc = i - sg.start;
+        const bool is_clos = loc < sg.nclos;
+        uint32_t rmask = 0, j = 0, dep = 0, clk = sg.fclock;
+        bool term = false;
+        unsigned long long key[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) key[w] = 0ull;
+        if (active) {
+          if (is_clos) {
+            rmask = loc + 1u;
             const uint32_t ns = (uint32_t)__popc(rmask);
-            if (is_clos && ns > kstar) active = false;
-            // start the units of rmask: bit t of rmask is the t-th free unit
+            if (ns > sg.kstar) active = false;
+#pragma unroll
+            for (int w = 0; w < W; ++w) key[w] = sg.fkey[w];
             uint32_t t = 0;
 #pragma unroll
             for (int u = 0; u < kMaxCU; ++u) {
-              if ((freem >> u) & 1u) {
-                if ((rmask >> t) & 1u) y.rem[u] = r.d;
+              if ((sg.freem >> u) & 1u) {
+                if ((rmask >> t) & 1u) field_add<W>(key, L, kFRem + u, r.d);
                 ++t;
               }
             }
-            y.pending -= ns;
-            dep = fdep + ns;
-            if (!is_clos) {
-              if (lock) {
-                const uint32_t e = end_at(r, idx0 + j);
-                y.clock = x.clock + (e - e0);
+            field_add<W>(key, L, kFPending, (unsigned long long)(-(long long)ns));
+            dep = sg.fdep + ns;
+          } else {
+            const uint32_t qq = loc - sg.nclos;
+            const uint32_t leaf = qq / sg.len;
+            j = qq - leaf * sg.len;
+            rmask = sg.kstar ? (sg.nleaf == 1u ? (1u << sg.nfree) - 1u : (uint32_t)sh.leaf[leaf])
+                             : 0u;
+            dep = sg.fdep + sg.kstar + j + 1u;
+            if (sg.lock) {
+              const uint32_t e = e_lds ? sh.E[sg.idx0 + j] : end_at(r, sg.idx0 + j);
+              clk = sg.fclock + (e - sg.e0);
+              const unsigned long long rem = r.d - e;
+              unsigned long long Mv[W];
 #pragma unroll
-                for (int u = 0; u < kMaxCU; ++u)
-                  if (u < m && y.rem[u]) y.rem[u] = r.d - e;
-              } else {
-                advance_once(y, r, m);
+              for (int w = 0; w < W; ++w) Mv[w] = sg.M[w];
+              if (sg.kstar && sg.nleaf > 1u) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) Mv[w] = 0ull;
+                uint32_t t = 0;
+#pragma unroll
+                for (int u = 0; u < kMaxCU; ++u) {
+                  if ((sg.freem >> u) & 1u) {
+                    if ((rmask >> t) & 1u) field_add<W>(Mv, L, kFRem + u, 1ull);
+                    ++t;
+                  }
+                }
               }
-              dep += j + 1u;
-              if (q.prune && y.clock > q.T) active = false;
-            }
-          }
-          if (active && y.clock > q.max_clock) {
-            set_error(q.ctrl, kDevErrOverflow);
-            active = false;
-          }
-          uint32_t slot = kParentNone;
-          bool fresh = false, term = false;
-          if (active) {
-            const Key<W> k = encode<W>(y, q.L);
-            ++n_edges;
-            const int res = table_insert<W, kScopeWG>(q.table, q.mask, k, slot, probes);
-            if (res == kInsFail) {
-              set_error(q.ctrl, kDevErrTableFull);
-              s_stop = 1u;
-              active = false;
-              slot = kParentNone;
-            } else if (res == kInsNew) {
-              fresh = true;
-              ++n_states;
-              depth_max = dep > depth_max ? dep : depth_max;
+#pragma unroll
+              for (int w = 0; w < W; ++w) key[w] = sg.base[w] + rem * Mv[w];
+              field_add<W>(key, L, kFClock, clk);
+              term = sg.pend == 0u && e == r.d;
+            } else {
+              Key<W> fk;
+#pragma unroll
+              for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
+              St y = decode<W>(fk, L);
+              uint32_t t = 0;
+#pragma unroll
+              for (int u = 0; u < kMaxCU; ++u) {
+                if ((sg.freem >> u) & 1u) {
+                  if ((rmask >> t) & 1u) y.rem[u] = r.d;
+                  ++t;
+                }
+              }
+              y.pending -= sg.kstar;
+              advance_once(y, r, m);
+              clk = y.clock;
               term = is_terminal(y, m);
-              if (term) {
-                ++n_terms;
-                atomicMin(&q.tc[c], y.clock);
-                if (q.prune) q.ctrl->violated = 1u;
-              }
-            } else {
-              ++n_dups;
-            }
-            if (is_clos) s_mask_slot[rmask] = slot;
-          }
-          s_chunk_slot[tid] = slot;
-          __syncthreads();
-          if (fresh) {
-            uint32_t par;
-            if (is_clos) {
-              const uint32_t pm = rmask & ~(1u << (31 - __clz(rmask)));
-              par = pm ? s_mask_slot[pm] : fslot;
-            } else if (j == 0u) {
-              par = rmask ? s_mask_slot[rmask] : fslot;
-            } else {
-              par = tid ? s_chunk_slot[tid - 1] : s_carry;
-            }
-            *slot_parent<W>(q.table, slot) = par;
-            if (!is_clos && j + 1u == len && !term) {
-              const uint32_t pos = atomicAdd(&s_fcount[cur ^ 1], 1u);
-              if (pos < (uint32_t)FCAP) {
-                const Key<W> k = encode<W>(y, q.L);
+              const Key<W> yk = encode<W>(y, L);
 #pragma unroll
-                for (int w = 0; w < W; ++w) s_fkey[cur ^ 1][pos][w] = k.w[w];
-                s_fslot[cur ^ 1][pos] = slot;
-                s_fdep[cur ^ 1][pos] = dep;
-              } else {
-                set_error(q.ctrl, kDevErrOverflow);
-              }
+              for (int w = 0; w < W; ++w) key[w] = yk.w[w];
+            }
+            if (md.prune && clk > md.T) active = false;
+          }
+        }
+        if (active && clk > md.max_clock) {
+          set_error(md.ctrl, kDevErrOverflow);
+          active = false;
+        }
+        uint32_t slot = kParentNone;
+        bool fresh = false;
+        if (active) {
+          Key<W> k;
+#pragma unroll
+          for (int w = 0; w < W; ++w) k.w[w] = key[w];
+          ++tl.edges;
+          const uint32_t p0 = tl.probes;
+          const int res = table_insert<W, kScopeWG>(md.table, md.mask, k, slot, tl.probes);
+          tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
+          if (res == kInsFail) {
+            set_error(md.ctrl, kDevErrTableFull);
+            sh.stop = 1u;
+            active = false;
+            slot = kParentNone;
+          } else if (res == kInsNew) {
+            fresh = true;
+            ++tl.states;
+            tl.depth = dep > tl.depth ? dep : tl.depth;
+            if (term) {
+              ++tl.terms;
+              atomicMin(&md.tc[c], clk);
+              if (md.prune) md.ctrl->violated = 1u;
+            }
+          } else {
+            ++tl.dups;
+          }
+          if (is_clos) sh.mslot[sgi][rmask] = slot;
+          else if (j + 1u == sg.len && sgi + 1u < nseg) sh.segfslot[sgi + 1u] = slot;
+        }
+        sh.chunk_slot[tid] = slot;
+        __syncthreads();
+        if (fresh) {
+          const uint32_t segf = sgi ? sh.segfslot[sgi] : sg.fslot;
+          uint32_t par, jmp = kParentNone;
+          if (is_clos) {
+            const uint32_t pm = rmask & ~(1u << (31 - __clz(rmask)));
+            par = pm ? sh.mslot[sgi][pm] : segf;
+          } else {
+            const uint32_t leaf_slot = rmask ? sh.mslot[sgi][rmask] : segf;
+            par = j == 0u ? leaf_slot : (tid ? sh.chunk_slot[tid - 1] : sh.carry);
+            if (sg.lock) jmp = leaf_slot;
+          }
+          *slot_parent<W>(md.table, slot) = par;
+          if (jmp != kParentNone) *slot_jump<W>(md.table, slot) = jmp;
+          if (!is_clos && j + 1u == sg.len && !term && sgi + 1u == nseg) {
+            const uint32_t pos = atomicAdd(&sh.fcount[cur ^ 1], 1u);
+            if (pos < (uint32_t)kFCap) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) sh.fkey[cur ^ 1][pos][w] = key[w];
+              sh.fslot[cur ^ 1][pos] = slot;
+              sh.fdep[cur ^ 1][pos] = dep;
+            } else {
+              set_error(md.ctrl, kDevErrOverflow);
             }
           }
-          __syncthreads();
-          if (tid == BLOCK - 1) s_carry = s_chunk_slot[BLOCK - 1];
-          __syncthreads();
         }
+        __syncthreads();
+        if (tid == BLOCK - 1) sh.carry = sh.chunk_slot[BLOCK - 1];
+        __syncthreads();
       }
-      if (tid == 0) s_fcount[cur] = 0u;
-      __syncthreads();
-      cur ^= 1;
     }
+    if (tid == 0) sh.fcount[cur] = 0u;
+    __syncthreads();
+    cur ^= 1;
   }
-  flush_counters(q.ctrl, n_states, n_terms, n_edges, n_dups, probes, depth_max);
+  flush_tally(md, tl);
+}
+
+__device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl) {
+  flush_counters(md.ctrl, tl.states, tl.terms, tl.edges, tl.dups, tl.probes, tl.depth);
+  const unsigned long long mp = wave_max(tl.max_probe);
+  if (lane_id() == 0 && mp) atomicMax(&md.ctrl->max_probe, (unsigned int)mp);
+  if (threadIdx.x == 0) {
+    if (tl.super) atomicAdd(&md.ctrl->supersteps, tl.super);
+    if (tl.chunks) atomicAdd(&md.ctrl->chunks, tl.chunks);
+  }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
+  __shared__ SuperShared<BLOCK> sh;
+  const uint32_t tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      sh.part = atomicAdd(a.head, 1u);
+      sh.stop = 0u;
+    }
+    __syncthreads();
+    const uint32_t part = sh.part;
+    if (part >= a.n_parts) break;
+    const uint2 pc = a.parts[part];
+    if (tid == 0) sh.md = a.models[pc.x];
+    __syncthreads();
+    const ModelDev& md = sh.md;
+    const uint32_t c = pc.y;
+    const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
+    const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
+    if (!skip) {
+      switch (md.L.W) {
+        case 1: explore_partition<1, BLOCK>(md, c, a.batch_items, sh); break;
+        case 2: explore_partition<2, BLOCK>(md, c, a.batch_items, sh); break;
+        default: explore_partition<4, BLOCK>(md, c, a.batch_items, sh); break;
+      }
+    }
+    if (tid == 0) {
+      const unsigned long long dt = __builtin_amdgcn_s_memrealtime() - t_part;
+      const unsigned long long prev = atomicMax(&md.ctrl->crit_ticks, dt);
+      if (dt > prev) md.ctrl->crit_part = c;
+    }
+    __syncthreads();
+  }
+}
+
+// Root and SELECT successors of every model of a queue, one workgroup per model.
+template <int W>
+__device__ void seed_model(const ModelDev& md) {
+  __shared__ uint32_t s_root;
+  uint32_t probes = 0;
+  if (threadIdx.x == 0) {
+    St r{};
+    r.cfg = md.n_cfg;
+    const Key<W> k = encode<W>(r, md.L);
+    uint32_t slot = kParentNone;
+    const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes);
+    if (res != kInsNew) set_error(md.ctrl, kDevErrTableFull);
+    else *slot_parent<W>(md.table, slot) = kParentRoot;
+    s_root = slot;
+    md.ctrl->root_slot = slot;
+    md.ctrl->max_depth = 1;
+    atomicAdd(&md.ctrl->states, 1ull + md.n_cfg);
+    atomicAdd(&md.ctrl->edges, (unsigned long long)md.n_cfg);
+  }
+  __syncthreads();
+  for (uint32_t c = threadIdx.x; c < md.n_cfg; c += blockDim.x) {
+    St s{};
+    s.cfg = c;
+    s.pending = md.cfgs[c].n;
+    const Key<W> k = encode<W>(s, md.L);
+    uint32_t slot = kParentNone;
+    const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes);
+    if (res != kInsNew) {
+      set_error(md.ctrl, kDevErrTableFull);
+      slot = kParentNone;
+    } else {
+      *slot_parent<W>(md.table, slot) = s_root;
+    }
+    Seed sd;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sd.k[j] = j < W ? k.w[j] : 0ull;
+    sd.slot = slot;
+    sd.depth = 1;
+    sd.pad[0] = sd.pad[1] = 0;
+    md.seeds[c] = sd;
+  }
+  const unsigned long long p = wave_sum(probes);
+  if (lane_id() == 0 && p) atomicAdd(&md.ctrl->probes, p);
+}
+
+__global__ __launch_bounds__(256) void k_seed_models(const ModelDev* models) {
+  const ModelDev md = models[blockIdx.x];
+  switch (md.L.W) {
+    case 1: seed_model<1>(md); break;
+    case 2: seed_model<2>(md); break;
+    default: seed_model<4>(md); break;
+  }
+}
+
+// Per-model counters and clocks of every model of a queue, and the queue head.
+__global__ void k_reset_models(const ModelDev* models, unsigned int* head) {
+  const ModelDev md = models[blockIdx.x];
+  unsigned int* cw = reinterpret_cast<unsigned int*>(md.ctrl);
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) cw[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < md.n_cfg; i += blockDim.x) md.tc[i] = kNoClock;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *head = 0u;
 }
 
 // ---- counterexample -----------------------------------------------------------------
@@ -485,24 +751,84 @@ __global__ void k_find(QueryArgs a, Key<W> k) {
   if (threadIdx.x == 0 && blockIdx.x == 0) a.ctrl->target_slot = table_find<W>(a.table, a.mask, k);
 }
 
-// Follows parent slots from the target to the root, writing keys terminal-first.
+// Follows parent slots from the target to the root, writing keys terminal-first.  A
+// state of a lock-step run carries a jump to the run's first predecessor (the leaf);
+// the run's states are regenerated lane-parallel from the leaf (operation end E[i0+j]
+// on every busy unit) instead of being chased one parent at a time.
 template <int W>
-__global__ void k_chase(QueryArgs a, unsigned long long* out, uint32_t cap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* out, uint32_t cap) {
+  if (blockIdx.x != 0) return;
+  const uint32_t lane = threadIdx.x;
+  const Layout& L = a.L;
+  const int m = L.m;
   uint32_t s = a.ctrl->target_slot;
   uint32_t n = 0;
+  bool bad = false;
   while (s != kParentRoot) {
     if (s == kParentNone || (unsigned long long)s > a.mask || n >= cap) {
-      set_error(a.ctrl, kDevErrTrace);
+      bad = true;
       break;
     }
     const unsigned long long* p = slot_key<W>(a.table, s);
+    Key<W> k;
 #pragma unroll
-    for (int w = 0; w < W; ++w) out[(unsigned long long)n * W + w] = p[w];
-    ++n;
-    s = *slot_parent<W>(a.table, s);
+    for (int w = 0; w < W; ++w) k.w[w] = p[w];
+    const uint32_t par = *slot_parent<W>(a.table, s);
+    const uint32_t jmp = *slot_jump<W>(a.table, s);
+    if (jmp == kParentNone || (unsigned long long)jmp > a.mask) {
+      if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) out[(unsigned long long)n * W + w] = k.w[w];
+      }
+      ++n;
+      s = par;
+      continue;
+    }
+    // regenerate the run leaf -> s
+    const unsigned long long* lp = slot_key<W>(a.table, jmp);
+    Key<W> lk;
+#pragma unroll
+    for (int w = 0; w < W; ++w) lk.w[w] = lp[w];
+    const St leaf = decode<W>(lk, L);
+    const St x = decode<W>(k, L);
+    const CfgRec r = a.cfgs[leaf.cfg];
+    uint32_t busy = 0, lrem = 0;
+    for (int u = 0; u < m; ++u)
+      if (leaf.rem[u]) {
+        busy |= 1u << u;
+        lrem = leaf.rem[u];
+      }
+    uint32_t xrem = 0;
+    for (int u = 0; u < m; ++u)
+      if ((busy >> u) & 1u) xrem = x.rem[u];
+    const uint32_t e0 = r.d - lrem, ex = r.d - xrem;
+    const uint32_t idx0 = ends_upto(r, e0);
+    const uint32_t cnt = ends_upto(r, ex) - idx0;  // run states from the leaf's successor to x
+    if (n + cnt > cap || cnt == 0u) {
+      bad = true;
+      break;
+    }
+    for (uint32_t t0 = 0; t0 < cnt; t0 += 64) {
+      const uint32_t t = t0 + lane;
+      if (t < cnt) {
+        const uint32_t pos = cnt - 1u - t;  // terminal-first order
+        const uint32_t e = end_at(r, idx0 + pos);
+        St y = leaf;
+        y.clock = leaf.clock + (e - e0);
+        for (int u = 0; u < m; ++u)
+          if ((busy >> u) & 1u) y.rem[u] = r.d - e;
+        const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+        for (int w = 0; w < W; ++w) out[(unsigned long long)(n + t) * W + w] = yk.w[w];
+      }
+    }
+    n += cnt;
+    s = jmp;
   }
-  a.ctrl->trace_len = n;
+  if (lane == 0) {
+    if (bad) set_error(a.ctrl, kDevErrTrace);
+    a.ctrl->trace_len = n;
+  }
 }
 
 // ---- simulation mode ------------------------------------------------------------------
@@ -581,19 +907,29 @@ hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, cons
   return hipGetLastError();
 }
 
-template <int W>
-hipError_t launch_super(hipStream_t st, uint32_t grid, uint32_t block, const SuperArgs& sa) {
+hipError_t launch_super(hipStream_t st, uint32_t grid, uint32_t block, const PartQueue& pq) {
   switch (block) {
     case 256:
-      hipLaunchKernelGGL((k_superstep<W, 256>), dim3(grid), dim3(256), 0, st, sa);
+      hipLaunchKernelGGL((k_superstep<256>), dim3(grid), dim3(256), 0, st, pq);
       break;
     case 512:
-      hipLaunchKernelGGL((k_superstep<W, 512>), dim3(grid), dim3(512), 0, st, sa);
+      hipLaunchKernelGGL((k_superstep<512>), dim3(grid), dim3(512), 0, st, pq);
       break;
     default:
-      hipLaunchKernelGGL((k_superstep<W, 1024>), dim3(grid), dim3(1024), 0, st, sa);
+      hipLaunchKernelGGL((k_superstep<1024>), dim3(grid), dim3(1024), 0, st, pq);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n) {
+  hipLaunchKernelGGL(k_seed_models, dim3(n), dim3(256), 0, st, models);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_models(hipStream_t st, const ModelDev* models, uint32_t n,
+                               unsigned int* head) {
+  hipLaunchKernelGGL(k_reset_models, dim3(n), dim3(256), 0, st, models, head);
   return hipGetLastError();
 }
 
@@ -615,7 +951,6 @@ hipError_t launch_chase(hipStream_t st, const QueryArgs& q, unsigned long long* 
   template hipError_t launch_seed<W>(hipStream_t, const QueryArgs&, Seed*, void*);         \
   template hipError_t launch_level<W>(hipStream_t, uint32_t, const LevelArgs&, const void*, \
                                       void*);                                              \
-  template hipError_t launch_super<W>(hipStream_t, uint32_t, uint32_t, const SuperArgs&);  \
   template hipError_t launch_find<W>(hipStream_t, const QueryArgs&,                       \
                                      const unsigned long long*);                           \
   template hipError_t launch_chase<W>(hipStream_t, const QueryArgs&, unsigned long long*,  \

@@ -28,11 +28,29 @@ struct LevelArgs {
   uint32_t fcap;
 };
 
-struct SuperArgs {
-  QueryArgs q;
-  const uint32_t* order;  // partitions, largest first
-  const Seed* seeds;
+// One model of a persistent launch (device memory, written by the host).
+struct ModelDev {
+  Ctrl* ctrl;
+  uint32_t* tc;
+  const CfgRec* cfgs;
+  Seed* seeds;
+  unsigned char* table;
+  unsigned long long mask;  // slots - 1
+  Layout L;
+  uint32_t n_cfg;
+  uint32_t prune;
+  uint32_t T;
+  uint32_t max_clock;
+  uint32_t pad[2];
+};
+
+// Partitions of a persistent launch: (model index, configuration), largest first.
+struct PartQueue {
+  const ModelDev* models;
+  const uint2* parts;
   uint32_t n_parts;
+  uint32_t batch_items;  // states generated per super-step batch before waiting (target)
+  unsigned int* head;
 };
 
 template <int W>
@@ -40,8 +58,10 @@ hipError_t launch_seed(hipStream_t st, const QueryArgs& q, Seed* seeds, void* fr
 template <int W>
 hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, const void* fin,
                         void* fout);
-template <int W>
-hipError_t launch_super(hipStream_t st, uint32_t grid, uint32_t block, const SuperArgs& sa);
+hipError_t launch_super(hipStream_t st, uint32_t grid, uint32_t block, const PartQueue& pq);
+hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n);
+hipError_t launch_reset_models(hipStream_t st, const ModelDev* models, uint32_t n,
+                               unsigned int* head);
 template <int W>
 hipError_t launch_find(hipStream_t st, const QueryArgs& q, const unsigned long long* key);
 template <int W>
