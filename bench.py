@@ -82,6 +82,135 @@ def cpu_baseline(model, t_min, budget_s: float = 30.0):
             "agrees": r["t_min"] == t_min}
 
 
+BATCH_BUDGET = 1 << 20
+
+
+def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int):
+    """The seeded mix of uneven instances explored in one persistent launch (hipGraph
+    replay, autotuned options), against the same instances explored one at a time."""
+    models, rejected = workloads.draw_batch(
+        3, n_inst, lambda x: (mc.state_count(x) or BATCH_BUDGET + 1) <= BATCH_BUDGET)
+    need = mc.mc_batch_workspace_bytes(models, mc.make_batch_opts(load_factor=0.25))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    t0 = time.perf_counter()
+    best, best_ms = mc.mc_batch_autotune(models, ws)
+    tune_s = time.perf_counter() - t0
+    best.use_graph = 1
+    b = mc.Batch(models, best, workspace=ws)
+    b.mc_batch_min_time()  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        t_min, states = b.mc_batch_min_time()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    gpu_ms = b.last_stats["explore_ns"] / 1e6
+    total = sum(states)
+    b.close()
+    del ws
+    torch.cuda.empty_cache()
+    # one at a time (fresh load per instance), on a sample
+    idx = list(range(0, n_inst, max(1, n_inst // sample_alone)))[:sample_alone]
+    t_alone, s_alone = 0.0, 0
+    for i in idx:
+        t1 = time.perf_counter()
+        g = mc.Model(models[i], block=512)
+        tm, _ = g.mc_min_time()
+        s_alone += g.last_stats["states"]
+        g.close()
+        t_alone += time.perf_counter() - t1
+        assert tm == t_min[i]
+    return {"instances": n_inst, "rejected_draws": rejected, "states": total,
+            "value": total / el, "unit": "states/s", "queries_per_s": n_inst / el,
+            "ms_per_batch": 1e3 * el, "gpu_ms": gpu_ms,
+            "autotuned": best.as_dict(), "autotune_s": tune_s,
+            "one_at_a_time": {"sample": len(idx), "value": s_alone / t_alone,
+                              "queries_per_s": len(idx) / t_alone},
+            "speedup_vs_one_at_a_time": (total / el) / (s_alone / t_alone)}
+
+
+def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int = 32):
+    """Poisson arrivals of check(T)/min_time queries over a pool of models; continuous
+    batching engine vs FIFO one-query-at-a-time service (fresh load per query)."""
+    pool, _ = workloads.draw_batch(
+        4, pool_size, lambda x: (mc.state_count(x) or BATCH_BUDGET + 1) <= BATCH_BUDGET)
+    mix = workloads.query_mix(4, n_queries, pool_size)
+    tmins = []  # the threshold recipe needs each model's T_min: one untimed GPU query each
+    for m in pool:
+        g = mc.Model(m, block=512)
+        tmins.append(g.mc_min_time()[0])
+        g.close()
+    qs = [(i, kind, int(u * tmins[i])) for i, kind, u in mix]
+    # FIFO one-at-a-time service times (super-step engine alone, fresh load per query)
+    svc = {}
+    for i, kind, T in qs[:min(len(qs), 200)]:
+        key = (i, kind, T)
+        if key in svc:
+            continue
+        t1 = time.perf_counter()
+        g = mc.Model(pool[i], block=512)
+        if kind == "min_time":
+            g.mc_min_time()
+        else:
+            g.mc_check(T)
+        g.close()
+        svc[key] = time.perf_counter() - t1
+    mean_svc = sum(svc.values()) / len(svc)
+    fifo_capacity = 1.0 / mean_svc
+    out = {"queries": n_queries, "pool": pool_size, "fifo_capacity_qps": fifo_capacity,
+           "runs": []}
+
+    def pct(xs, p):
+        xs = sorted(xs)
+        return xs[min(len(xs) - 1, int(p * len(xs)))]
+
+    for f in qps_factors:
+        qps = f * fifo_capacity
+        arr = workloads.poisson_arrivals(4, n_queries, qps)
+        # FIFO one at a time: exact single-server simulation from measured service times
+        svc_list = list(svc.values())
+        done, lat_fifo = 0.0, []
+        for k, a in enumerate(arr):
+            s_k = svc.get(qs[k], svc_list[k % len(svc_list)])
+            start = max(a, done)
+            done = start + s_k
+            lat_fifo.append(done - a)
+        # continuous batching engine, driven in real time
+        e = mc.Engine(arena_bytes=24 << 30, max_active=128, max_cfg=512, block=512, slice=16)
+        tickets = []
+        t0 = time.perf_counter()
+        nxt = 0
+        while nxt < n_queries or any(e.mc_engine_poll(t) is None for t in tickets[-64:]):
+            now = time.perf_counter() - t0
+            while nxt < n_queries and arr[nxt] <= now:
+                i, kind, T = qs[nxt]
+                tickets.append(e.mc_engine_submit(
+                    pool[i], mc.MC_QUERY_MIN_TIME if kind == "min_time" else mc.MC_QUERY_CHECK,
+                    T))
+                nxt += 1
+            a_, w_ = e.mc_engine_step()
+            if a_ == 0 and w_ == 0 and nxt < n_queries:
+                time.sleep(max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.001)))
+        e.drain()
+        wall = time.perf_counter() - t0
+        lat = []
+        base_ns = None
+        for k, t in enumerate(tickets):
+            r = e.mc_engine_poll(t)
+            assert r is not None and r["status"] == 0
+            if base_ns is None:
+                base_ns = r["submit_ns"] - int(arr[0] * 1e9)
+            lat.append((r["done_ns"] - base_ns) * 1e-9 - arr[k])
+        e.close()
+        torch.cuda.empty_cache()
+        out["runs"].append({
+            "qps_offered": qps, "factor": f, "queries_per_s": n_queries / wall,
+            "p50_ms": 1e3 * pct(lat, 0.5), "p99_ms": 1e3 * pct(lat, 0.99),
+            "fifo_p50_ms": 1e3 * pct(lat_fifo, 0.5), "fifo_p99_ms": 1e3 * pct(lat_fifo, 0.99),
+            "fifo_queries_per_s": n_queries / max(done, arr[-1])})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +221,12 @@ def main():
     ap.add_argument("--load-factor", type=float, default=0.0)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-instances", type=int, default=512)
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--legs", default="plain,cpu,batch,serve",
+                    help="extra legs beside the timed single-query step")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the exploration "
@@ -101,6 +236,16 @@ def main():
     import torch
     import workloads
     import paper_2305_09130_amd as mc
+
+    if args.copy_probe_mib:
+        # a copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters give the factor
+        # that turns those counters into bytes for the exploration kernel
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     model = workloads.WORKLOADS[args.workload]()
     nbytes = max(mc.mc_workspace_bytes(model, mc.make_opts(engine=e, block=args.block,
@@ -131,8 +276,9 @@ def main():
     src_hash = kernel_source_hash()
     traffic = read_traffic(args.workload, "k_superstep", src_hash)
 
+    legs = set(x for x in args.legs.split(",") if x)
     plain = None
-    if args.plain_steps > 0:
+    if args.plain_steps > 0 and "plain" in legs:
         ps = [run_step(mc, model, mc.MC_ENGINE_LEVEL, workspace, args.block, args.load_factor)
               for _ in range(args.plain_steps)]
         p_states = sum(s["states"] for s in ps)
@@ -145,8 +291,13 @@ def main():
         assert all(s["t_min"] == steps[0]["t_min"] for s in ps)
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and "cpu" in legs:
         cpu = cpu_baseline(model, steps[0]["t_min"])
+    batched = served = None
+    if "batch" in legs:
+        batched = batched_leg(mc, torch, workloads, args.batch_instances, 5, 16)
+    if "serve" in legs:
+        served = served_leg(mc, torch, workloads, args.serve_queries, (0.5, 1.0, 2.0))
 
     cfg = {"workload": args.workload, "kind": model["kind"], "cu": model["m"],
            "configurations": len(model["params"]),
@@ -181,6 +332,8 @@ def main():
                      "avg_launch_ms": eng_s * 1e3, "kernel_source_hash": src_hash},
         "cpu_baseline": cpu,
         "plain_bfs": plain,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
 

@@ -94,8 +94,10 @@ typedef struct mc_opts {
     float load_factor;       /* target states/slots when sizing (0 = 0.5) */
     uint32_t grid;           /* persistent workgroups (0 = automatic) */
     uint32_t batch_items;    /* super-step engine: states generated from one frontier state
-                                before waiting for the visited set (0 = 2 x block) */
-    uint32_t reserved[2];
+                                before waiting for the visited set (0 = 2 x lanes) */
+    uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
+                                (any other value = 2) */
+    uint32_t reserved[1];
 } mc_opts;
 
 /* ---- statistics of the last query ---------------------------------------------- */
@@ -211,10 +213,12 @@ typedef struct mc_batch_opts {
     uint32_t grid;           /* persistent workgroups (0 = automatic) */
     float load_factor;       /* visited-set load factor (0 = 0.5) */
     uint32_t chunk;          /* states generated per super-step before waiting for the
-                                visited set (0 = 2 x block) */
+                                visited set (0 = 2 x block x lane_items) */
     uint32_t use_graph;      /* 1: capture the query's launch sequence once in a hipGraph
                                 and replay it (needs a non-null stream: MC_E_INVAL) */
-    uint32_t reserved[3];
+    uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
+                                (any other value = 2) */
+    uint32_t reserved[2];
 } mc_batch_opts;
 
 /* Workspace bytes of a batch of n models (host array of n descriptors). */
@@ -231,12 +235,76 @@ int mc_batch_min_time(mc_batch *b, uint32_t *t_min, uint64_t *states, mc_stats *
 /* Per-configuration least terminal clocks of one model of the last mc_batch_min_time. */
 int mc_batch_terminal_clocks(const mc_batch *b, uint32_t model, uint32_t *tc, size_t cap);
 int mc_batch_free(mc_batch *b);
-/* Autotuner: tries block in {256,512,1024} x load factor in {0.25,0.5,0.7} x chunk in
- * {1,2,4} x block on the batch itself, in the caller's workspace (candidates that do not
- * fit are skipped), and returns the fastest options and their GPU time (-1 when served
+/* Autotuner: tries block in {256,512,1024} x load factor in {0.25,0.5,0.7} x lane_items
+ * in {1,2} x chunk in {1,2} x block x lane_items on the batch itself, in the caller's
+ * workspace (candidates that do not fit are skipped), and returns the fastest options and their GPU time (-1 when served
  * from the per-process cache, keyed by the batch and the device architecture). */
 int mc_batch_autotune(const mc_desc *models, uint32_t n, void *dev_ws, size_t ws_bytes,
                       void *stream, mc_batch_opts *best, float *best_ms);
+
+/* ---- serving: continuous batching of queries ------------------------------------ */
+/* A query server over the persistent engine.  Queries (min_time or check(T) of a
+ * model) are submitted at any time.  Each mc_engine_step:
+ *   1. admits waiting queries in arrival order while their footprint (visited set,
+ *      tables, saved frontiers) fits the engine's arena and a model slot is free;
+ *   2. runs one persistent launch over the unfinished partitions of every active
+ *      query, where a partition explores at most `slice` super-step levels, then saves
+ *      its frontier and yields;
+ *   3. retires the queries whose partitions are all explored, freeing their memory.
+ * Queries admitted later therefore share the device with queries already running.
+ * Every query owns its visited set, so its result is the same alone and in the mix. */
+#define MC_QUERY_MIN_TIME 0u
+#define MC_QUERY_CHECK 1u
+
+typedef struct mc_engine mc_engine;
+
+typedef struct mc_engine_opts {
+    uint32_t max_active;     /* model slots: queries on the device at once (>= 1) */
+    uint32_t max_cfg;        /* largest configuration count a query may have (>= 1) */
+    uint32_t block;          /* threads per workgroup: 256, 512, 1024 (0 = 512) */
+    uint32_t slice;          /* super-step levels per partition per step (0 = no limit) */
+    uint32_t chunk;          /* states per super-step batch (0 = 2 x block x lane_items) */
+    uint32_t grid;           /* persistent workgroups per step (0 = up to 1024) */
+    float load_factor;       /* visited-set load factor (0 = 0.5) */
+    uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
+                                (any other value = 2) */
+    uint32_t reserved[4];
+} mc_engine_opts;
+
+typedef struct mc_query_result {
+    uint32_t kind, T;
+    int status;              /* MC_OK, MC_E_ADMIT (can never fit), or a query error */
+    int done;                /* 1 once the result is final */
+    int violated;            /* check(T): some terminal with clock <= T */
+    uint32_t t_min;          /* least terminal clock reached (under T for check) */
+    uint32_t n_argmin;       /* configurations attaining it */
+    uint32_t argmin_first;   /* the smallest of them */
+    uint64_t states;         /* states explored (count_T for check) */
+    uint64_t levels;         /* BFS levels */
+    uint64_t submit_ns, admit_ns, done_ns;  /* host monotonic clock */
+    uint32_t steps;          /* engine steps the query was active */
+    uint32_t pad;
+} mc_query_result;
+
+/* Device bytes for an engine whose query arena holds arena_bytes. */
+int mc_engine_bytes(const mc_engine_opts *o, size_t arena_bytes, size_t *bytes);
+/* Create an engine in the caller's device buffer on the given stream (library owns
+ * *out; the buffer must outlive it).  MC_E_NOMEM if the buffer leaves no arena. */
+int mc_engine_create(const mc_engine_opts *o, void *dev_buf, size_t buf_bytes, void *stream,
+                     mc_engine **out);
+/* Queue a query (kind MC_QUERY_*; T is used by check).  A query that can never fit the
+ * arena or max_cfg completes at once with status MC_E_ADMIT.  MC_E_INVAL for an invalid
+ * model. */
+int mc_engine_submit(mc_engine *e, const mc_desc *model, uint32_t kind, uint32_t T,
+                     uint64_t *ticket);
+/* One engine iteration (admit, launch, retire); synchronous.  Returns the number of
+ * active and waiting queries afterwards. */
+int mc_engine_step(mc_engine *e, uint32_t *n_active, uint32_t *n_waiting);
+/* Result of a ticket: MC_OK when done, MC_E_STATE while pending, MC_E_NOTFOUND. */
+int mc_engine_poll(mc_engine *e, uint64_t ticket, mc_query_result *out);
+/* Forget a finished ticket. */
+int mc_engine_release(mc_engine *e, uint64_t ticket);
+int mc_engine_destroy(mc_engine *e);
 
 #ifdef __cplusplus
 }

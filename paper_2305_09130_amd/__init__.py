@@ -47,7 +47,7 @@ class McOpts(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_uint32), ("block", ctypes.c_uint32),
                 ("log2_slots", ctypes.c_uint32), ("load_factor", ctypes.c_float),
                 ("grid", ctypes.c_uint32), ("batch_items", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("lane_items", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 1)]
 
 
 class McStats(ctypes.Structure):
@@ -70,12 +70,34 @@ class McModelInfo(ctypes.Structure):
 class McBatchOpts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("load_factor", ctypes.c_float), ("chunk", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("use_graph", ctypes.c_uint32), ("lane_items", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
     def as_dict(self) -> dict:
         return {"block": int(self.block), "grid": int(self.grid),
                 "load_factor": float(self.load_factor), "chunk": int(self.chunk),
-                "use_graph": int(self.use_graph)}
+                "use_graph": int(self.use_graph), "lane_items": int(self.lane_items)}
+
+
+class McEngineOpts(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_uint32), ("max_cfg", ctypes.c_uint32),
+                ("block", ctypes.c_uint32), ("slice", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("load_factor", ctypes.c_float), ("lane_items", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class McQueryResult(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("T", ctypes.c_uint32), ("status", ctypes.c_int),
+                ("done", ctypes.c_int), ("violated", ctypes.c_int), ("t_min", ctypes.c_uint32),
+                ("n_argmin", ctypes.c_uint32), ("argmin_first", ctypes.c_uint32),
+                ("states", ctypes.c_uint64), ("levels", ctypes.c_uint64),
+                ("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("steps", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "pad"}
 
 
 _P = ctypes.POINTER
@@ -105,6 +127,14 @@ _SIGS = {
     "mc_batch_free": ([_vp], ctypes.c_int),
     "mc_batch_autotune": ([_P(McDesc), ctypes.c_uint32, _vp, ctypes.c_size_t, _vp,
                            _P(McBatchOpts), _P(ctypes.c_float)], ctypes.c_int),
+    "mc_engine_bytes": ([_P(McEngineOpts), ctypes.c_size_t, _P(ctypes.c_size_t)], ctypes.c_int),
+    "mc_engine_create": ([_P(McEngineOpts), _vp, ctypes.c_size_t, _vp, _P(_vp)], ctypes.c_int),
+    "mc_engine_submit": ([_vp, _P(McDesc), ctypes.c_uint32, ctypes.c_uint32, _u64p],
+                         ctypes.c_int),
+    "mc_engine_step": ([_vp, _u32p, _u32p], ctypes.c_int),
+    "mc_engine_poll": ([_vp, ctypes.c_uint64, _P(McQueryResult)], ctypes.c_int),
+    "mc_engine_release": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "mc_engine_destroy": ([_vp], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -146,11 +176,12 @@ def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
 
 
 def make_opts(engine: int = MC_ENGINE_SUPERSTEP, block: int = 0, log2_slots: int = 0,
-              load_factor: float = 0.0, grid: int = 0, batch_items: int = 0) -> McOpts:
+              load_factor: float = 0.0, grid: int = 0, batch_items: int = 0,
+              lane_items: int = 0) -> McOpts:
     o = McOpts()
     o.engine, o.block, o.log2_slots, o.load_factor, o.grid = engine, block, log2_slots, \
         load_factor, grid
-    o.batch_items = batch_items
+    o.batch_items, o.lane_items = batch_items, lane_items
     return o
 
 
@@ -185,13 +216,15 @@ class Model:
 
     def __init__(self, model: dict, engine: int = MC_ENGINE_SUPERSTEP, block: int = 0,
                  log2_slots: int = 0, load_factor: float = 0.0, grid: int = 0,
-                 device: str = "cuda:0", stream=None, workspace=None, batch_items: int = 0):
+                 device: str = "cuda:0", stream=None, workspace=None, batch_items: int = 0,
+                 lane_items: int = 0):
         import torch
         self.model = model
         self.m = model["m"]
         self.n_cfg = len(model["params"])
         self._desc, self._params = make_desc(model)
-        self._opts = make_opts(engine, block, log2_slots, load_factor, grid, batch_items)
+        self._opts = make_opts(engine, block, log2_slots, load_factor, grid, batch_items,
+                               lane_items)
         nbytes = mc_workspace_bytes(model, self._opts)
         self.device = torch.device(device)
         if workspace is None:
@@ -287,10 +320,11 @@ def _desc_array(models: list[dict]):
 
 
 def make_batch_opts(block: int = 0, grid: int = 0, load_factor: float = 0.0, chunk: int = 0,
-                    use_graph: bool = False) -> McBatchOpts:
+                    use_graph: bool = False, lane_items: int = 0) -> McBatchOpts:
     o = McBatchOpts()
     o.block, o.grid, o.load_factor, o.chunk = block, grid, load_factor, chunk
     o.use_graph = 1 if use_graph else 0
+    o.lane_items = lane_items
     return o
 
 
@@ -374,6 +408,75 @@ class Batch:
         _check("mc_batch_terminal_clocks",
                _lib.mc_batch_terminal_clocks(self._h, i, tc.ctypes.data_as(_u32p), nc))
         return [None if int(v) == NO_CLOCK else int(v) for v in tc]
+
+
+MC_QUERY_MIN_TIME, MC_QUERY_CHECK = 0, 1
+
+
+class Engine:
+    """Continuous-batching query server (mc_engine_*) on its own device buffer."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 64, max_cfg: int = 512,
+                 block: int = 512, slice: int = 16, chunk: int = 0, grid: int = 0,
+                 load_factor: float = 0.5, device: str = "cuda:0", stream=None,
+                 lane_items: int = 0):
+        import torch
+        o = McEngineOpts()
+        o.max_active, o.max_cfg, o.block, o.slice = max_active, max_cfg, block, slice
+        o.chunk, o.grid, o.load_factor = chunk, grid, load_factor
+        o.lane_items = lane_items
+        self._o = o
+        n = ctypes.c_size_t()
+        _check("mc_engine_bytes", _lib.mc_engine_bytes(ctypes.byref(o), arena_bytes,
+                                                       ctypes.byref(n)))
+        self.device = torch.device(device)
+        self.buffer = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check("mc_engine_create",
+               _lib.mc_engine_create(ctypes.byref(o), ctypes.c_void_p(self.buffer.data_ptr()),
+                                     n.value, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.mc_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def mc_engine_submit(self, model: dict, kind: int, T: int = 0) -> int:
+        d, p = make_desc(model)
+        t = ctypes.c_uint64()
+        _check("mc_engine_submit", _lib.mc_engine_submit(self._h, ctypes.byref(d), kind, int(T),
+                                                         ctypes.byref(t)))
+        return t.value
+
+    def mc_engine_step(self) -> tuple[int, int]:
+        a, w = ctypes.c_uint32(), ctypes.c_uint32()
+        _check("mc_engine_step", _lib.mc_engine_step(self._h, ctypes.byref(a), ctypes.byref(w)))
+        return a.value, w.value
+
+    def mc_engine_poll(self, ticket: int) -> dict | None:
+        r = McQueryResult()
+        rc = _lib.mc_engine_poll(self._h, ticket, ctypes.byref(r))
+        if rc == MC_E_STATE:
+            return None
+        _check("mc_engine_poll", rc)
+        return r.as_dict()
+
+    def mc_engine_release(self, ticket: int) -> None:
+        _check("mc_engine_release", _lib.mc_engine_release(self._h, ticket))
+
+    def drain(self, max_steps: int = 1 << 20) -> None:
+        for _ in range(max_steps):
+            a, w = self.mc_engine_step()
+            if a == 0 and w == 0:
+                return
+        raise RuntimeError("engine did not drain")
 
 
 def exported_symbols() -> list[str]:

@@ -80,6 +80,7 @@ mc_opts default_opts(const mc_opts* o) {
   if (o) r = *o;
   if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 256;
   if (r.engine > MC_ENGINE_LEVEL) r.engine = MC_ENGINE_SUPERSTEP;
+  if (r.lane_items != 1) r.lane_items = 2;
   return r;
 }
 
@@ -234,8 +235,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     md.prune = prune ? 1u : 0u;
     md.T = T;
     md.max_clock = h->mh.max_clock;
+    md.pstate = nullptr;
     HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_reset_models(s, h->dmd, 1, h->head));
+    HIPCHK(launch_reset_models(s, h->dmd, 1, h->head, 1));
     HIPCHK(hipEventRecord(h->ev[2], s));
     HIPCHK(launch_seed_models(s, h->dmd, 1));
     HIPCHK(hipEventRecord(h->ev[4], s));
@@ -243,10 +245,15 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     pq.models = h->dmd;
     pq.parts = h->parts;
     pq.n_parts = h->mh.n_cfg;
-    pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * h->opts.block;
+    const uint32_t li = h->opts.lane_items ? h->opts.lane_items : 2u;
+    pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
     pq.head = h->head;
+    pq.slice = 0u;
+    pq.pad = 0u;
+    pq.yielded = nullptr;
+    pq.n_yielded = nullptr;
     const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->mh.n_cfg, 4096u);
-    HIPCHK(launch_super(s, grid, h->opts.block, pq));
+    HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq));
     HIPCHK(hipEventRecord(h->ev[5], s));
     launches = 2;
   } else {

@@ -44,6 +44,7 @@ mc_batch_opts default_bopts(const mc_batch_opts* o) {
   if (o) r = *o;
   if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 512;
   if (!(r.load_factor > 0.f && r.load_factor < 1.f)) r.load_factor = 0.5f;
+  if (r.lane_items != 1) r.lane_items = 2;
   return r;
 }
 
@@ -80,7 +81,7 @@ int plan_batch(const std::vector<ModelHost>& ms, const mc_batch_opts& o, BatchPl
   p->parts = off;
   off = align_up(off + 8ull * p->n_parts);
   p->head = off;
-  off = align_up(off + 4);
+  off = align_up(off + 16);
   p->tables = off;
   p->table_off.resize(n);
   p->slots.resize(n);
@@ -135,7 +136,9 @@ struct mc_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool ran = false;
-  uint32_t grid = 0;
+  uint32_t grid[3] = {0, 0, 0};
+  uint32_t group_off[3] = {0, 0, 0}, group_n[3] = {0, 0, 0};  // partitions per key width
+  Fork fork;
 };
 
 namespace {
@@ -144,15 +147,22 @@ int enqueue_query(mc_batch* b) {
   hipStream_t s = b->stream;
   const uint32_t n = (uint32_t)b->ms.size();
   HIPCHK(launch_clear(s, b->ws + b->plan.tables, b->plan.tables_bytes));
-  HIPCHK(launch_reset_models(s, b->dmd, n, b->head));
+  HIPCHK(launch_reset_models(s, b->dmd, n, b->head, 3));
   HIPCHK(launch_seed_models(s, b->dmd, n));
-  PartQueue pq;
-  pq.models = b->dmd;
-  pq.parts = b->parts;
-  pq.n_parts = (uint32_t)b->plan.n_parts;
-  pq.batch_items = b->opts.chunk ? b->opts.chunk : 2u * b->opts.block;
-  pq.head = b->head;
-  HIPCHK(launch_super(s, b->grid, b->opts.block, pq));
+  const uint32_t li = b->opts.lane_items ? b->opts.lane_items : 2u;
+  PartQueue pq[3];
+  for (int w = 0; w < 3; ++w) {
+    pq[w].models = b->dmd;
+    pq[w].parts = b->parts + b->group_off[w];
+    pq[w].n_parts = b->group_n[w];
+    pq[w].batch_items = b->opts.chunk ? b->opts.chunk : 2u * li * b->opts.block;
+    pq[w].head = b->head + w;
+    pq[w].slice = 0u;
+    pq[w].pad = 0u;
+    pq[w].yielded = nullptr;
+    pq[w].n_yielded = nullptr;
+  }
+  HIPCHK(launch_super_fork(s, b->fork, pq, b->grid, b->opts.block, li));
   HIPCHK(hipMemcpyAsync(b->hctrl, b->ws + b->plan.ctrl, kCtrlStride * n, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(b->htc, b->ws + b->plan.tc, 4ull * b->tc_words, hipMemcpyDeviceToHost, s));
   return MC_OK;
@@ -166,6 +176,7 @@ void free_batch(mc_batch* b) {
     if (e) (void)hipEventDestroy(e);
   if (b->hctrl) (void)hipHostFree(b->hctrl);
   if (b->htc) (void)hipHostFree(b->htc);
+  b->fork.destroy();
   delete b;
 }
 
@@ -249,7 +260,8 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&b->htc), 4ull * b->tc_words,
                       hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess) {
+        hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess ||
+        b->fork.create() != hipSuccess) {
       (void)hipGetLastError();
       free_batch(b);
       return MC_E_DEVICE;
@@ -278,9 +290,20 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
       d.max_clock = m.max_clock;
       for (uint32_t c = 0; c < m.n_cfg; ++c) ps.push_back({m.cfg_states[c], i, c});
     }
-    std::stable_sort(ps.begin(), ps.end(), [](const P& a, const P& c) { return a.size > c.size; });
+    // group by key width (one launch each), largest partition first within a group
+    auto wgroup = [&](const P& p) { const uint32_t W = b->ms[p.model].W; return W == 1 ? 0 : W == 2 ? 1 : 2; };
+    std::stable_sort(ps.begin(), ps.end(), [&](const P& a, const P& c) {
+      const int ga = wgroup(a), gc = wgroup(c);
+      return ga != gc ? ga < gc : a.size > c.size;
+    });
     std::vector<uint2> parts(ps.size());
-    for (size_t k = 0; k < ps.size(); ++k) parts[k] = make_uint2(ps[k].model, ps[k].cfg);
+    for (size_t k = 0; k < ps.size(); ++k) {
+      parts[k] = make_uint2(ps[k].model, ps[k].cfg);
+      ++b->group_n[wgroup(ps[k])];
+    }
+    b->group_off[0] = 0;
+    b->group_off[1] = b->group_n[0];
+    b->group_off[2] = b->group_n[0] + b->group_n[1];
     hipStream_t s = b->stream;
     for (uint32_t i = 0; i < n; ++i)
       if (hipMemcpyAsync(b->ws + b->plan.cfg_off[i], b->ms[i].cfgs.data(),
@@ -298,9 +321,10 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
       free_batch(b);
       return MC_E_DEVICE;
     }
-    b->grid = b->opts.grid ? b->opts.grid
-                           : (uint32_t)std::min<uint64_t>(b->plan.n_parts,
-                                                          b->opts.block >= 1024 ? 512u : 1024u);
+    for (int w = 0; w < 3; ++w)
+      b->grid[w] = b->opts.grid ? b->opts.grid
+                                : std::min<uint32_t>(std::max<uint32_t>(b->group_n[w], 1u),
+                                                     b->opts.block >= 1024 ? 512u : 1024u);
     if (b->opts.use_graph) {
       if (s == nullptr) {  // the null stream cannot be captured
         free_batch(b);
@@ -426,19 +450,22 @@ int mc_batch_autotune(const mc_desc* models, uint32_t n, void* dev_ws, size_t ws
     }
     const uint32_t blocks[] = {256, 512, 1024};
     const float lfs[] = {0.25f, 0.5f, 0.7f};
-    const uint32_t items_mult[] = {1, 2, 4};
+    const uint32_t lane_items[] = {1, 2};
+    const uint32_t items_mult[] = {1, 2};
     float best_t = 1e30f;
     mc_batch_opts bo;
     std::memset(&bo, 0, sizeof(bo));
     bool any = false;
     for (float lf : lfs) {
       for (uint32_t bl : blocks) {
+        for (uint32_t li : lane_items) {
         for (uint32_t im : items_mult) {
           mc_batch_opts o;
           std::memset(&o, 0, sizeof(o));
           o.block = bl;
           o.load_factor = lf;
-          o.chunk = im * bl;
+          o.lane_items = li;
+          o.chunk = im * bl * li;
           size_t need = 0;
           rc = mc_batch_workspace_bytes(models, n, &o, &need);
           if (rc || need > ws_bytes) continue;
@@ -457,6 +484,7 @@ int mc_batch_autotune(const mc_desc* models, uint32_t n, void* dev_ws, size_t ws
             bo = o;
             any = true;
           }
+        }
         }
       }
     }

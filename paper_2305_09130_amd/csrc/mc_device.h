@@ -31,7 +31,8 @@ struct Ctrl {
   unsigned long long supersteps; // super-steps (persistent engine)
   unsigned long long chunks;     // insert batches (persistent engine)
   unsigned long long crit_ticks; // longest partition time, 100 MHz ticks
-  unsigned int pad[8];
+  unsigned int parts_done;       // partitions explored to the end (resumable queues)
+  unsigned int pad[7];
 };
 static_assert(sizeof(Ctrl) == 160, "Ctrl layout");
 
@@ -323,6 +324,133 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
     }
   }
   return kInsFail;
+}
+
+// N independent inserts per lane, stepped together so that their round trips overlap:
+// every iteration first issues the window loads of all keys that need one, then the
+// compare-and-swaps of all keys whose current slot looks empty, then the publish checks
+// of waiting keys, and only then looks at the results.  Same protocol and guarantees as
+// table_insert, one state machine per key.  A window hint is the low half of word 0:
+// the configuration field sits in the low bits and is never all-ones in a valid key, so
+// the low half alone tells an empty slot; a slot whose low half equals the key's is
+// resolved by the compare-and-swap's return value or the full compare.
+template <int W, int SCOPE, int N>
+__device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned long long mask,
+                                               const unsigned long long (&key)[N][W],
+                                               const bool (&act)[N], uint32_t (&slot)[N],
+                                               int (&res)[N], uint32_t& probes) {
+  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  const unsigned long long max_iters =
+      (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
+  constexpr uint32_t kLoEmpty = 0xFFFFFFFFu;
+  unsigned long long wi[N], step[N], old[N];
+  uint32_t h[N][kWin];
+  int j[N];
+  bool waiting[N], done[N], cas[N];
+  uint32_t pub[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    res[n] = kInsFail;
+    slot[n] = kParentNone;
+    done[n] = !act[n];
+    waiting[n] = false;
+    j[n] = kWin;
+    wi[n] = step[n] = 0ull;
+    if (act[n]) {
+      Key<W> k;
+#pragma unroll
+      for (int q = 0; q < W; ++q) k.w[q] = key[n][q];
+      probe_start(key_hash<W>(k), mask, wi[n], step[n]);
+    }
+  }
+  for (unsigned long long it = 0; it < max_iters; ++it) {
+    bool any = false;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {  // window loads
+      if (done[n] || j[n] != kWin) continue;
+      ++probes;
+      const unsigned long long s0 = wi[n] * kWin;
+#pragma unroll
+      for (int q = 0; q < kWin; ++q)
+        h[n][q] = __hip_atomic_load(reinterpret_cast<uint32_t*>(slot_key<W>(base, s0 + q)),
+                                    __ATOMIC_RELAXED, SCOPE);
+      j[n] = 0;
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {  // claims
+      cas[n] = false;
+      if (done[n] || waiting[n]) continue;
+      const uint32_t v = j[n] == 0 ? h[n][0] : j[n] == 1 ? h[n][1] : j[n] == 2 ? h[n][2] : h[n][3];
+      if (v == kLoEmpty || v == (uint32_t)key[n][0]) {
+        // empty: claim it; same low half: the CAS returns the slot's word 0 either way
+        cas[n] = true;
+        old[n] = atomicCAS(slot_key<W>(base, wi[n] * kWin + (unsigned long long)j[n]), kEmptyWord,
+                           key[n][0]);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {  // publish checks
+      if (done[n] || !waiting[n]) continue;
+      pub[n] = __hip_atomic_load(slot_pub<W>(base, wi[n] * kWin + (unsigned long long)j[n]),
+                                 __ATOMIC_ACQUIRE, SCOPE);
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {  // results
+      if (done[n]) continue;
+      any = true;
+      const unsigned long long s = wi[n] * kWin + (unsigned long long)j[n];
+      unsigned long long* p = slot_key<W>(base, s);
+      bool advance = false;
+      if (waiting[n]) {
+        if (pub[n] == kPublished) {
+          bool eq = true;
+#pragma unroll
+          for (int q = 1; q < W; ++q)
+            eq &= __hip_atomic_load(p + q, __ATOMIC_RELAXED, SCOPE) == key[n][q];
+          if (eq) {
+            slot[n] = (uint32_t)s;
+            res[n] = kInsDup;
+            done[n] = true;
+            continue;
+          }
+          waiting[n] = false;
+          advance = true;
+        }
+      } else if (cas[n]) {
+        if (old[n] == kEmptyWord) {
+          if (W > 1) {
+#pragma unroll
+            for (int q = 1; q < W; ++q)
+              __hip_atomic_store(p + q, key[n][q], __ATOMIC_RELAXED, SCOPE);
+            __hip_atomic_store(slot_pub<W>(base, s), kPublished, __ATOMIC_RELEASE, SCOPE);
+          }
+          slot[n] = (uint32_t)s;
+          res[n] = kInsNew;
+          done[n] = true;
+          continue;
+        }
+        ++probes;
+        if (old[n] == key[n][0]) {
+          if (W == 1) {
+            slot[n] = (uint32_t)s;
+            res[n] = kInsDup;
+            done[n] = true;
+            continue;
+          }
+          waiting[n] = true;
+        } else {
+          advance = true;
+        }
+      } else {
+        advance = true;  // another key's slot
+      }
+      if (advance) {
+        ++j[n];
+        if (j[n] == kWin) wi[n] = (wi[n] + step[n]) & nwin_mask;
+      }
+    }
+    if (!any) break;
+  }
 }
 
 // Lookup only (after the exploration finished; plain loads).

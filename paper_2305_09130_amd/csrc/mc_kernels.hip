@@ -282,6 +282,7 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
 constexpr int kSegMax = 8;
 constexpr int kEMax = 4096;  // operation ends kept in LDS
 constexpr int kFCap = 256;   // frontier states per super-step level (LDS)
+constexpr int kMaxLeaves = 72;  // C(8, 4) = 70 leaves at most
 
 struct SegDesc {
   unsigned long long fkey[4];  // frontier state of the segment
@@ -293,12 +294,12 @@ struct SegDesc {
   uint32_t fslot, nfree, aux, pad;
 };
 
-template <int BLOCK>
+template <int BLOCK, int NI>
 struct SuperShared {
   uint32_t E[kEMax];
   uint32_t mslot[kSegMax][256];
   uint8_t leaf[256];
-  uint32_t chunk_slot[BLOCK];
+  uint32_t chunk_slot[NI * BLOCK];
   SegDesc seg[kSegMax];
   uint32_t segfslot[kSegMax];
   unsigned long long fkey[2][kFCap][4];
@@ -307,6 +308,11 @@ struct SuperShared {
   uint32_t fcount[2];
   uint32_t part, carry, stop, nseg, total;
   ModelDev md;  // descriptor of the model being explored
+  // successors of the leaves of a segment whose run is not in lock step (one ADVANCE
+  // each), computed once per super-step outside the batch loop
+  unsigned long long gkey[kMaxLeaves][4];
+  uint32_t gclk[kMaxLeaves];
+  uint32_t gterm[kMaxLeaves];
 };
 
 struct Tally {
@@ -326,11 +332,102 @@ __device__ __forceinline__ void field_add(unsigned long long* k, const Layout& L
     if (wf == j) k[j] += x;
 }
 
+template <int W>
+struct Item {
+  unsigned long long key[W];
+  uint32_t sgi, rmask, j, dep, clk;
+  bool active, is_clos, term;
+};
+
+// State number i of the current batch: a closure state (a set of started units) or the
+// j-th state of a run from a leaf, built directly from the segment's templates.
+template <int W, int BLOCK, int NI, bool KEY>
+__device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t nseg,
+                                         const SuperShared<BLOCK, NI>& sh, const CfgRec& r,
+                                         bool e_lds, const ModelDev& md, int m, Item<W>& it) {
+  const Layout& L = md.L;
+  it.active = i < total;
+  it.sgi = 0;
+  for (uint32_t k = 1; k < nseg; ++k)
+    if (i >= sh.seg[k].start) it.sgi = k;
+  const SegDesc& sg = sh.seg[it.sgi];
+  const uint32_t loc = i - sg.start;
+  it.is_clos = loc < sg.nclos;
+  it.rmask = 0;
+  it.j = 0;
+  it.dep = 0;
+  it.clk = sg.fclock;
+  it.term = false;
+#pragma unroll
+  for (int w = 0; w < W; ++w) it.key[w] = 0ull;
+  if (!it.active) return;
+  if (it.is_clos) {
+    it.rmask = loc + 1u;
+    const uint32_t ns = (uint32_t)__popc(it.rmask);
+    if (ns > sg.kstar) it.active = false;
+    if (KEY) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) it.key[w] = sg.fkey[w];
+      uint32_t t = 0;
+#pragma unroll
+      for (int u = 0; u < kMaxCU; ++u) {
+        if ((sg.freem >> u) & 1u) {
+          if ((it.rmask >> t) & 1u) field_add<W>(it.key, L, kFRem + u, r.d);
+          ++t;
+        }
+      }
+      field_add<W>(it.key, L, kFPending, (unsigned long long)(-(long long)ns));
+    }
+    it.dep = sg.fdep + ns;
+    return;
+  }
+  const uint32_t qq = loc - sg.nclos;
+  const uint32_t leaf = qq / sg.len;
+  it.j = qq - leaf * sg.len;
+  it.rmask = sg.kstar ? (sg.nleaf == 1u ? (1u << sg.nfree) - 1u : (uint32_t)sh.leaf[leaf]) : 0u;
+  it.dep = sg.fdep + sg.kstar + it.j + 1u;
+  if (sg.lock) {
+    const uint32_t e = e_lds ? sh.E[sg.idx0 + it.j] : end_at(r, sg.idx0 + it.j);
+    it.clk = sg.fclock + (e - sg.e0);
+    if (KEY) {
+      const unsigned long long rem = r.d - e;
+      unsigned long long Mv[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) Mv[w] = sg.M[w];
+      if (sg.kstar && sg.nleaf > 1u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) Mv[w] = 0ull;
+        uint32_t t = 0;
+#pragma unroll
+        for (int u = 0; u < kMaxCU; ++u) {
+          if ((sg.freem >> u) & 1u) {
+            if ((it.rmask >> t) & 1u) field_add<W>(Mv, L, kFRem + u, 1ull);
+            ++t;
+          }
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) it.key[w] = sg.base[w] + rem * Mv[w];
+      field_add<W>(it.key, L, kFClock, it.clk);
+    }
+    it.term = sg.pend == 0u && e == r.d;
+  } else {
+    it.clk = sh.gclk[leaf];
+    it.term = sh.gterm[leaf] != 0u;
+    if (KEY) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[leaf][w];
+    }
+  }
+  if (md.prune && it.clk > md.T) it.active = false;
+}
+
 __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
 
-template <int W, int BLOCK>
+template <int W, int BLOCK, int NI>
 __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch_items,
-                                  SuperShared<BLOCK>& sh) {
+                                  uint32_t slice, const PartQueue& pq, uint32_t model,
+                                  SuperShared<BLOCK, NI>& sh) {
   Tally tl;
   const Layout& L = md.L;
   const int m = L.m;
@@ -340,17 +437,46 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
   if (e_lds)
     for (uint32_t k = tid; k < r.b; k += BLOCK) sh.E[k] = end_at(r, k);
   if (tid == 0) {
-    const Seed sd = md.seeds[c];
+    if (md.pstate && md.pstate[c].status == 1u) {  // resume a partition that yielded
+      const PartState ps = md.pstate[c];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = sd.k[w];
-    sh.fslot[0][0] = sd.slot;
-    sh.fdep[0][0] = sd.depth;
-    sh.fcount[0] = sd.slot == kParentNone ? 0u : 1u;
+      for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = ps.k[w];
+      sh.fslot[0][0] = ps.slot;
+      sh.fdep[0][0] = ps.depth;
+      sh.fcount[0] = 1u;
+    } else {
+      const Seed sd = md.seeds[c];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = sd.k[w];
+      sh.fslot[0][0] = sd.slot;
+      sh.fdep[0][0] = sd.depth;
+      sh.fcount[0] = sd.slot == kParentNone ? 0u : 1u;
+    }
     sh.fcount[1] = 0u;
   }
   __syncthreads();
   int cur = 0;
+  uint32_t levels = 0;
+  bool yielded = false;
   while (sh.fcount[cur] > 0u && !sh.stop) {
+    if (slice && md.pstate && levels >= slice && sh.fcount[cur] == 1u) {
+      // out of budget for this launch: save the single frontier state and yield
+      if (tid == 0) {
+        PartState ps;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) ps.k[w] = sh.fkey[cur][0][w];
+        ps.slot = sh.fslot[cur][0];
+        ps.depth = sh.fdep[cur][0];
+        ps.status = 1u;
+        ps.pad = 0u;
+        md.pstate[c] = ps;
+        const uint32_t pos = atomicAdd(pq.n_yielded, 1u);
+        pq.yielded[pos] = make_uint2(model, c);
+      }
+      yielded = true;
+      break;
+    }
+    ++levels;
     const uint32_t nf = sh.fcount[cur] < (uint32_t)kFCap ? sh.fcount[cur] : (uint32_t)kFCap;
     for (uint32_t fi = 0; fi < nf; ++fi) {
       // ---- segments of this super-step (one thread builds them) ----
@@ -477,161 +603,133 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
         }
         __syncthreads();
       }
-      for (uint32_t base = 0; base < total; base += BLOCK) {
-        ++tl.chunks;
-        const uint32_t i = base + tid;
-        bool active = i < total;
-        uint32_t sgi = 0;
-        for (uint32_t k = 1; k < nseg; ++k)
-          if (i >= sh.seg[k].start) sgi = k;
-        const SegDesc& sg = sh.seg[sgi];
-        const uint32_t loc = i - sg.start;
-        const bool is_clos = loc < sg.nclos;
-        uint32_t rmask = 0, j = 0, dep = 0, clk = sg.fclock;
-        bool term = false;
-        unsigned long long key[W];
+      if (nseg && !sh.seg[nseg - 1].lock) {
+        // one ADVANCE from every leaf of a run that is not in lock step
+        const SegDesc& sg = sh.seg[nseg - 1];
+        if (tid < sg.nleaf && tid < (uint32_t)kMaxLeaves) {
+          const uint32_t rmask =
+              sg.kstar ? (sg.nleaf == 1u ? (1u << sg.nfree) - 1u : (uint32_t)sh.leaf[tid]) : 0u;
+          Key<W> fk;
 #pragma unroll
-        for (int w = 0; w < W; ++w) key[w] = 0ull;
-        if (active) {
-          if (is_clos) {
-            rmask = loc + 1u;
-            const uint32_t ns = (uint32_t)__popc(rmask);
-            if (ns > sg.kstar) active = false;
+          for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
+          St y = decode<W>(fk, L);
+          uint32_t t = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) key[w] = sg.fkey[w];
-            uint32_t t = 0;
-#pragma unroll
-            for (int u = 0; u < kMaxCU; ++u) {
-              if ((sg.freem >> u) & 1u) {
-                if ((rmask >> t) & 1u) field_add<W>(key, L, kFRem + u, r.d);
-                ++t;
-              }
+          for (int u = 0; u < kMaxCU; ++u) {
+            if ((sg.freem >> u) & 1u) {
+              if ((rmask >> t) & 1u) y.rem[u] = r.d;
+              ++t;
             }
-            field_add<W>(key, L, kFPending, (unsigned long long)(-(long long)ns));
-            dep = sg.fdep + ns;
-          } else {
-            const uint32_t qq = loc - sg.nclos;
-            const uint32_t leaf = qq / sg.len;
-            j = qq - leaf * sg.len;
-            rmask = sg.kstar ? (sg.nleaf == 1u ? (1u << sg.nfree) - 1u : (uint32_t)sh.leaf[leaf])
-                             : 0u;
-            dep = sg.fdep + sg.kstar + j + 1u;
-            if (sg.lock) {
-              const uint32_t e = e_lds ? sh.E[sg.idx0 + j] : end_at(r, sg.idx0 + j);
-              clk = sg.fclock + (e - sg.e0);
-              const unsigned long long rem = r.d - e;
-              unsigned long long Mv[W];
-#pragma unroll
-              for (int w = 0; w < W; ++w) Mv[w] = sg.M[w];
-              if (sg.kstar && sg.nleaf > 1u) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) Mv[w] = 0ull;
-                uint32_t t = 0;
-#pragma unroll
-                for (int u = 0; u < kMaxCU; ++u) {
-                  if ((sg.freem >> u) & 1u) {
-                    if ((rmask >> t) & 1u) field_add<W>(Mv, L, kFRem + u, 1ull);
-                    ++t;
-                  }
-                }
-              }
-#pragma unroll
-              for (int w = 0; w < W; ++w) key[w] = sg.base[w] + rem * Mv[w];
-              field_add<W>(key, L, kFClock, clk);
-              term = sg.pend == 0u && e == r.d;
-            } else {
-              Key<W> fk;
-#pragma unroll
-              for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
-              St y = decode<W>(fk, L);
-              uint32_t t = 0;
-#pragma unroll
-              for (int u = 0; u < kMaxCU; ++u) {
-                if ((sg.freem >> u) & 1u) {
-                  if ((rmask >> t) & 1u) y.rem[u] = r.d;
-                  ++t;
-                }
-              }
-              y.pending -= sg.kstar;
-              advance_once(y, r, m);
-              clk = y.clock;
-              term = is_terminal(y, m);
-              const Key<W> yk = encode<W>(y, L);
-#pragma unroll
-              for (int w = 0; w < W; ++w) key[w] = yk.w[w];
-            }
-            if (md.prune && clk > md.T) active = false;
           }
-        }
-        if (active && clk > md.max_clock) {
-          set_error(md.ctrl, kDevErrOverflow);
-          active = false;
-        }
-        uint32_t slot = kParentNone;
-        bool fresh = false;
-        if (active) {
-          Key<W> k;
+          y.pending -= sg.kstar;
+          advance_once(y, r, m);
+          const Key<W> yk = encode<W>(y, L);
 #pragma unroll
-          for (int w = 0; w < W; ++w) k.w[w] = key[w];
-          ++tl.edges;
-          const uint32_t p0 = tl.probes;
-          const int res = table_insert<W, kScopeWG>(md.table, md.mask, k, slot, tl.probes);
-          tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
-          if (res == kInsFail) {
-            set_error(md.ctrl, kDevErrTableFull);
-            sh.stop = 1u;
-            active = false;
-            slot = kParentNone;
-          } else if (res == kInsNew) {
-            fresh = true;
-            ++tl.states;
-            tl.depth = dep > tl.depth ? dep : tl.depth;
-            if (term) {
-              ++tl.terms;
-              atomicMin(&md.tc[c], clk);
-              if (md.prune) md.ctrl->violated = 1u;
-            }
-          } else {
-            ++tl.dups;
-          }
-          if (is_clos) sh.mslot[sgi][rmask] = slot;
-          else if (j + 1u == sg.len && sgi + 1u < nseg) sh.segfslot[sgi + 1u] = slot;
+          for (int w = 0; w < W; ++w) sh.gkey[tid][w] = yk.w[w];
+          sh.gclk[tid] = y.clock;
+          sh.gterm[tid] = is_terminal(y, m) ? 1u : 0u;
         }
-        sh.chunk_slot[tid] = slot;
         __syncthreads();
-        if (fresh) {
-          const uint32_t segf = sgi ? sh.segfslot[sgi] : sg.fslot;
+      }
+      for (uint32_t base = 0; base < total; base += NI * BLOCK) {
+        ++tl.chunks;
+        unsigned long long keys[NI][W];
+        bool act[NI];
+#pragma unroll
+        for (int n = 0; n < NI; ++n) {
+          Item<W> x;
+          gen_item<W, BLOCK, NI, true>(base + (uint32_t)n * BLOCK + tid, total, nseg, sh, r, e_lds,
+                                       md, m, x);
+          if (x.active && x.clk > md.max_clock) {
+            set_error(md.ctrl, kDevErrOverflow);
+            x.active = false;
+          }
+          act[n] = x.active;
+#pragma unroll
+          for (int w = 0; w < W; ++w) keys[n][w] = x.key[w];
+        }
+        uint32_t slot[NI];
+        int res[NI];
+        const uint32_t p0 = tl.probes;
+        table_insert_n<W, kScopeWG, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+        tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
+        bool fresh[NI];
+        Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
+#pragma unroll
+        for (int n = 0; n < NI; ++n) {
+          gen_item<W, BLOCK, NI, false>(base + (uint32_t)n * BLOCK + tid, total, nseg, sh, r,
+                                        e_lds, md, m, it[n]);
+          it[n].active = act[n];
+          fresh[n] = false;
+          if (it[n].active) {
+            ++tl.edges;
+            if (res[n] == kInsFail) {
+              set_error(md.ctrl, kDevErrTableFull);
+              sh.stop = 1u;
+              it[n].active = false;
+              slot[n] = kParentNone;
+            } else if (res[n] == kInsNew) {
+              fresh[n] = true;
+              ++tl.states;
+              tl.depth = it[n].dep > tl.depth ? it[n].dep : tl.depth;
+              if (it[n].term) {
+                ++tl.terms;
+                atomicMin(&md.tc[c], it[n].clk);
+                if (md.prune) md.ctrl->violated = 1u;
+              }
+            } else {
+              ++tl.dups;
+            }
+            const SegDesc& sg = sh.seg[it[n].sgi];
+            if (it[n].is_clos) sh.mslot[it[n].sgi][it[n].rmask] = slot[n];
+            else if (it[n].j + 1u == sg.len && it[n].sgi + 1u < nseg)
+              sh.segfslot[it[n].sgi + 1u] = slot[n];
+          }
+          sh.chunk_slot[n * BLOCK + tid] = it[n].active ? slot[n] : kParentNone;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int n = 0; n < NI; ++n) {
+          if (!fresh[n]) continue;
+          const Item<W>& x = it[n];
+          const SegDesc& sg = sh.seg[x.sgi];
+          const uint32_t segf = x.sgi ? sh.segfslot[x.sgi] : sg.fslot;
           uint32_t par, jmp = kParentNone;
-          if (is_clos) {
-            const uint32_t pm = rmask & ~(1u << (31 - __clz(rmask)));
-            par = pm ? sh.mslot[sgi][pm] : segf;
+          if (x.is_clos) {
+            const uint32_t pm = x.rmask & ~(1u << (31 - __clz(x.rmask)));
+            par = pm ? sh.mslot[x.sgi][pm] : segf;
           } else {
-            const uint32_t leaf_slot = rmask ? sh.mslot[sgi][rmask] : segf;
-            par = j == 0u ? leaf_slot : (tid ? sh.chunk_slot[tid - 1] : sh.carry);
+            const uint32_t leaf_slot = x.rmask ? sh.mslot[x.sgi][x.rmask] : segf;
+            const uint32_t li = (uint32_t)n * BLOCK + tid;  // local index of the item
+            par = x.j == 0u ? leaf_slot : (li ? sh.chunk_slot[li - 1] : sh.carry);
             if (sg.lock) jmp = leaf_slot;
           }
-          *slot_parent<W>(md.table, slot) = par;
-          if (jmp != kParentNone) *slot_jump<W>(md.table, slot) = jmp;
-          if (!is_clos && j + 1u == sg.len && !term && sgi + 1u == nseg) {
+          *slot_parent<W>(md.table, slot[n]) = par;
+          if (jmp != kParentNone) *slot_jump<W>(md.table, slot[n]) = jmp;
+          if (!x.is_clos && x.j + 1u == sg.len && !x.term && x.sgi + 1u == nseg) {
             const uint32_t pos = atomicAdd(&sh.fcount[cur ^ 1], 1u);
             if (pos < (uint32_t)kFCap) {
 #pragma unroll
-              for (int w = 0; w < W; ++w) sh.fkey[cur ^ 1][pos][w] = key[w];
-              sh.fslot[cur ^ 1][pos] = slot;
-              sh.fdep[cur ^ 1][pos] = dep;
+              for (int w = 0; w < W; ++w) sh.fkey[cur ^ 1][pos][w] = keys[n][w];
+              sh.fslot[cur ^ 1][pos] = slot[n];
+              sh.fdep[cur ^ 1][pos] = x.dep;
             } else {
               set_error(md.ctrl, kDevErrOverflow);
             }
           }
         }
         __syncthreads();
-        if (tid == BLOCK - 1) sh.carry = sh.chunk_slot[BLOCK - 1];
+        if (tid == BLOCK - 1) sh.carry = sh.chunk_slot[NI * BLOCK - 1];
         __syncthreads();
       }
     }
     if (tid == 0) sh.fcount[cur] = 0u;
     __syncthreads();
     cur ^= 1;
+  }
+  if (!yielded && tid == 0) {
+    if (md.pstate) md.pstate[c].status = 2u;
+    atomicAdd(&md.ctrl->parts_done, 1u);
   }
   flush_tally(md, tl);
 }
@@ -646,9 +744,9 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
   }
 }
 
-template <int BLOCK>
+template <int W, int BLOCK, int NI>
 __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
-  __shared__ SuperShared<BLOCK> sh;
+  __shared__ SuperShared<BLOCK, NI> sh;
   const uint32_t tid = threadIdx.x;
   for (;;) {
     if (tid == 0) {
@@ -665,13 +763,7 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     const uint32_t c = pc.y;
     const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
     const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
-    if (!skip) {
-      switch (md.L.W) {
-        case 1: explore_partition<1, BLOCK>(md, c, a.batch_items, sh); break;
-        case 2: explore_partition<2, BLOCK>(md, c, a.batch_items, sh); break;
-        default: explore_partition<4, BLOCK>(md, c, a.batch_items, sh); break;
-      }
-    }
+    if (!skip) explore_partition<W, BLOCK, NI>(md, c, a.batch_items, a.slice, a, pc.x, sh);
     if (tid == 0) {
       const unsigned long long dt = __builtin_amdgcn_s_memrealtime() - t_part;
       const unsigned long long prev = atomicMax(&md.ctrl->crit_ticks, dt);
@@ -735,13 +827,16 @@ __global__ __launch_bounds__(256) void k_seed_models(const ModelDev* models) {
   }
 }
 
-// Per-model counters and clocks of every model of a queue, and the queue head.
-__global__ void k_reset_models(const ModelDev* models, unsigned int* head) {
+// Per-model counters and clocks of every model of a queue, and the queue heads.
+__global__ void k_reset_models(const ModelDev* models, unsigned int* head, uint32_t n_heads) {
   const ModelDev md = models[blockIdx.x];
   unsigned int* cw = reinterpret_cast<unsigned int*>(md.ctrl);
   for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) cw[i] = 0u;
   for (uint32_t i = threadIdx.x; i < md.n_cfg; i += blockDim.x) md.tc[i] = kNoClock;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *head = 0u;
+  if (md.pstate)
+    for (uint32_t i = threadIdx.x; i < md.n_cfg; i += blockDim.x) md.pstate[i].status = 0u;
+  if (blockIdx.x == 0 && head)
+    for (uint32_t i = threadIdx.x; i < n_heads; i += blockDim.x) head[i] = 0u;
 }
 
 // ---- counterexample -----------------------------------------------------------------
@@ -907,19 +1002,53 @@ hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, cons
   return hipGetLastError();
 }
 
-hipError_t launch_super(hipStream_t st, uint32_t grid, uint32_t block, const PartQueue& pq) {
-  switch (block) {
-    case 256:
-      hipLaunchKernelGGL((k_superstep<256>), dim3(grid), dim3(256), 0, st, pq);
-      break;
-    case 512:
-      hipLaunchKernelGGL((k_superstep<512>), dim3(grid), dim3(512), 0, st, pq);
-      break;
-    default:
-      hipLaunchKernelGGL((k_superstep<1024>), dim3(grid), dim3(1024), 0, st, pq);
-      break;
+template <int W>
+static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32_t items,
+                           const PartQueue& pq) {
+#define MC_LAUNCH_SUPER(B, N) \
+  hipLaunchKernelGGL((k_superstep<W, B, N>), dim3(grid), dim3(B), 0, st, pq)
+  if (block == 256) {
+    if (items >= 2) MC_LAUNCH_SUPER(256, 2);
+    else MC_LAUNCH_SUPER(256, 1);
+  } else if (block == 1024) {
+    if (items >= 2) MC_LAUNCH_SUPER(1024, 2);
+    else MC_LAUNCH_SUPER(1024, 1);
+  } else {
+    if (items >= 2) MC_LAUNCH_SUPER(512, 2);
+    else MC_LAUNCH_SUPER(512, 1);
   }
+#undef MC_LAUNCH_SUPER
+}
+
+hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
+                        uint32_t items, const PartQueue& pq) {
+  if (W == 1) launch_super_w<1>(st, grid, block, items, pq);
+  else if (W == 2) launch_super_w<2>(st, grid, block, items, pq);
+  else launch_super_w<4>(st, grid, block, items, pq);
   return hipGetLastError();
+}
+
+hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)[3],
+                             const uint32_t (&grid)[3], uint32_t block, uint32_t items) {
+  static const uint32_t widths[3] = {1, 2, 4};
+  int used = 0, last = -1;
+  for (int w = 0; w < 3; ++w)
+    if (queue[w].n_parts) {
+      ++used;
+      last = w;
+    }
+  if (used == 0) return hipSuccess;
+  if (used == 1)  // no fork needed
+    return launch_super(main, widths[last], grid[last], block, items, queue[last]);
+  hipError_t e = hipEventRecord(f.fork, main);
+  for (int w = 0; w < 3 && e == hipSuccess; ++w) {
+    if (!queue[w].n_parts) continue;
+    e = hipStreamWaitEvent(f.sub[w], f.fork, 0);
+    if (e == hipSuccess) e = launch_super(f.sub[w], widths[w], grid[w], block, items, queue[w]);
+    if (e == hipSuccess) e = hipEventRecord(f.join[w], f.sub[w]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(main, f.join[w], 0);
+  }
+  return e;
 }
 
 hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n) {
@@ -928,8 +1057,8 @@ hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n
 }
 
 hipError_t launch_reset_models(hipStream_t st, const ModelDev* models, uint32_t n,
-                               unsigned int* head) {
-  hipLaunchKernelGGL(k_reset_models, dim3(n), dim3(256), 0, st, models, head);
+                               unsigned int* head, uint32_t n_heads) {
+  hipLaunchKernelGGL(k_reset_models, dim3(n), dim3(256), 0, st, models, head, n_heads);
   return hipGetLastError();
 }
 

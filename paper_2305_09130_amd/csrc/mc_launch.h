@@ -28,6 +28,15 @@ struct LevelArgs {
   uint32_t fcap;
 };
 
+// Saved frontier of a partition explored across several launches.
+struct PartState {
+  unsigned long long k[4];
+  uint32_t slot, depth;
+  uint32_t status;  // 0 not started, 1 in progress (one saved frontier state), 2 done
+  uint32_t pad;
+};
+static_assert(sizeof(PartState) == 48, "PartState layout");
+
 // One model of a persistent launch (device memory, written by the host).
 struct ModelDev {
   Ctrl* ctrl;
@@ -42,6 +51,8 @@ struct ModelDev {
   uint32_t T;
   uint32_t max_clock;
   uint32_t pad[2];
+  PartState* pstate;  // n_cfg entries when partitions may yield, else null
+  unsigned long long pad2;
 };
 
 // Partitions of a persistent launch: (model index, configuration), largest first.
@@ -51,6 +62,10 @@ struct PartQueue {
   uint32_t n_parts;
   uint32_t batch_items;  // states generated per super-step batch before waiting (target)
   unsigned int* head;
+  uint32_t slice;        // super-step levels per partition before it yields (0 = no limit)
+  uint32_t pad;
+  uint2* yielded;        // partitions that yielded, for the next launch
+  unsigned int* n_yielded;
 };
 
 template <int W>
@@ -58,10 +73,43 @@ hipError_t launch_seed(hipStream_t st, const QueryArgs& q, Seed* seeds, void* fr
 template <int W>
 hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, const void* fin,
                         void* fout);
-hipError_t launch_super(hipStream_t st, uint32_t grid, uint32_t block, const PartQueue& pq);
+// All models of the queue have key width W (1, 2, 4).  items: states per lane per
+// insert batch (1 or 2).
+hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
+                        uint32_t items, const PartQueue& pq);
+
+// Runs up to three launches (one per key width) concurrently on sub-streams forked from
+// and joined back into a main stream with events; usable inside stream capture.
+struct Fork {
+  hipStream_t sub[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+  hipError_t create() {
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&sub[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    }
+    return e;
+  }
+  void destroy() {
+    for (int i = 0; i < 3; ++i) {
+      if (sub[i]) (void)hipStreamDestroy(sub[i]);
+      if (join[i]) (void)hipEventDestroy(join[i]);
+      sub[i] = nullptr;
+      join[i] = nullptr;
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    fork = nullptr;
+  }
+};
+
+// queue[w] (w = 0, 1, 2 for key widths 1, 2, 4) with n_parts == 0 are skipped
+hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)[3],
+                             const uint32_t (&grid)[3], uint32_t block, uint32_t items);
 hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n);
 hipError_t launch_reset_models(hipStream_t st, const ModelDev* models, uint32_t n,
-                               unsigned int* head);
+                               unsigned int* head, uint32_t n_heads);
 template <int W>
 hipError_t launch_find(hipStream_t st, const QueryArgs& q, const unsigned long long* key);
 template <int W>

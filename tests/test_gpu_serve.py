@@ -1,0 +1,136 @@
+"""GPU tests of the continuous-batching server.
+
+Every query's result must equal the same query alone and the oracle's answer (closed
+forms pinned to the oracle for min_time; verdict and count of states with clock <= T for
+check), whatever the admission pressure, slice length and submission order.
+"""
+import random
+import sys
+
+import pytest
+
+import oracle
+import workloads
+from oracle import closed_form as cf
+
+pytestmark = pytest.mark.gpu
+BUDGET = 1 << 20
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2305_09130_amd as mc
+    return mc
+
+
+def _pool(mc, n=8, seed=4):
+    ms, _ = workloads.draw_batch(seed, n, lambda x: (mc.state_count(x) or BUDGET + 1) <= BUDGET)
+    return ms
+
+
+def _queries(pool, n, seed):
+    qs = []
+    for i, kind, u in workloads.query_mix(seed, n, len(pool)):
+        t_min = cf.summary(pool[i], with_E=False)["t_min"]
+        qs.append((i, kind, int(u * t_min)))
+    return qs
+
+
+def _expected(pool, q):
+    i, kind, T = q
+    s = cf.summary(pool[i], with_E=False)
+    if kind == "min_time":
+        return {"t_min": s["t_min"], "states": s["reachable"], "n_argmin": len(s["argmin"]),
+                "argmin_first": s["argmin"][0]}
+    return {"violated": int(T >= s["t_min"]), "states": cf.count_le(pool[i], T)}
+
+
+def _run(mc, pool, qs, order=None, **eng):
+    e = mc.Engine(**eng)
+    order = order if order is not None else list(range(len(qs)))
+    tickets = {}
+    for k in order:
+        i, kind, T = qs[k]
+        tickets[k] = e.mc_engine_submit(pool[i], mc.MC_QUERY_MIN_TIME if kind == "min_time"
+                                        else mc.MC_QUERY_CHECK, T)
+    e.drain()
+    out = {}
+    for k, t in tickets.items():
+        r = e.mc_engine_poll(t)
+        assert r is not None and r["done"] == 1 and r["status"] == 0, r
+        out[k] = r
+    e.close()
+    return out
+
+
+def _check(pool, qs, res):
+    for k, q in enumerate(qs):
+        exp = _expected(pool, q)
+        got = {key: res[k][key] for key in exp}
+        assert got == exp, (k, q, workloads.describe(pool[q[0]]), got, exp)
+
+
+def test_serve_results_equal_oracle_under_pressure(mc):
+    pool = _pool(mc)
+    qs = _queries(pool, 40, seed=1)
+    _say("40 queries, small arena, slice 4")
+    res = _run(mc, pool, qs, arena_bytes=256 << 20, max_active=6, slice=4)
+    _check(pool, qs, res)
+    assert max(r["steps"] for r in res.values()) > 1   # partitions really yielded
+
+
+def test_serve_alone_equals_mix(mc):
+    pool = _pool(mc)
+    qs = _queries(pool, 24, seed=2)
+    _say("mix vs alone")
+    mix = _run(mc, pool, qs, arena_bytes=1 << 30, max_active=32, slice=8)
+    alone = _run(mc, pool, qs, arena_bytes=1 << 30, max_active=1, slice=0)
+    keys = ("violated", "t_min", "n_argmin", "argmin_first", "states", "levels")
+    for k in range(len(qs)):
+        assert {x: mix[k][x] for x in keys} == {x: alone[k][x] for x in keys}, k
+    _check(pool, qs, mix)
+
+
+def test_serve_submission_order_does_not_matter(mc):
+    pool = _pool(mc)
+    qs = _queries(pool, 20, seed=3)
+    a = _run(mc, pool, qs, arena_bytes=512 << 20, max_active=8, slice=2)
+    order = list(range(len(qs)))
+    random.Random(7).shuffle(order)
+    b = _run(mc, pool, qs, order=order, arena_bytes=512 << 20, max_active=8, slice=2)
+    for k in range(len(qs)):
+        assert (a[k]["states"], a[k]["t_min"], a[k]["violated"]) == \
+            (b[k]["states"], b[k]["t_min"], b[k]["violated"])
+
+
+def test_serve_small_models_against_oracle(mc):
+    pool = workloads.tiny_models(77, 10, max_cu=8)
+    qs = []
+    for i, m in enumerate(pool):
+        r = oracle.explore(m, trace=False)
+        qs += [(i, "min_time", 0), (i, "check", r["t_min"] - 1), (i, "check", r["t_min"])]
+    res = _run(mc, pool, qs, arena_bytes=64 << 20, max_active=5, slice=1)
+    for k, (i, kind, T) in enumerate(qs):
+        r = oracle.explore(pool[i], T=None if kind == "min_time" else T, trace=False)
+        assert res[k]["states"] == r["reachable"]
+        if kind == "min_time":
+            assert (res[k]["t_min"], res[k]["n_argmin"]) == (r["t_min"], len(r["argmin"]))
+            assert res[k]["levels"] == r["levels"]
+        else:
+            assert res[k]["violated"] == int(r["violated"])
+
+
+def test_serve_admission_reject(mc):
+    big = workloads.matmul_64()
+    e = mc.Engine(arena_bytes=64 << 20, max_active=4)
+    t = e.mc_engine_submit(big, mc.MC_QUERY_MIN_TIME)
+    r = e.mc_engine_poll(t)
+    assert r is not None and r["status"] == mc.MC_E_ADMIT
+    e.close()
