@@ -60,6 +60,8 @@ extern "C" {
 #define MC_E_OVERFLOW (-7)   /* a frontier or a packed field exceeded its bound */
 #define MC_E_ADMIT (-8)      /* a query can never fit the engine's memory budget */
 #define MC_E_NOTFOUND (-9)   /* no such ticket / state */
+#define MC_E_INTERNAL (-10)  /* an internal consistency check failed (a round block of a
+                                configuration did not end on its predicted state) */
 
 /* ---- model descriptor ---------------------------------------------------------- */
 #define MC_KIND_REDUCTION 0u
@@ -97,7 +99,9 @@ typedef struct mc_opts {
                                 before waiting for the visited set (0 = 2 x lanes) */
     uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
                                 (any other value = 2) */
-    uint32_t reserved[1];
+    uint32_t part_states;    /* super-step engine: target states per partition when a
+                                configuration's subgraph is cut into blocks of whole
+                                rounds (0 = automatic, UINT32_MAX = never cut) */
 } mc_opts;
 
 /* ---- statistics of the last query ---------------------------------------------- */
@@ -117,8 +121,10 @@ typedef struct mc_stats {
     uint64_t supersteps;     /* super-steps of the persistent engine */
     uint64_t batches;        /* insert batches of the persistent engine */
     uint64_t max_probe;      /* longest probe sequence of one insert */
-    uint64_t critical_ns;    /* longest single-configuration exploration (device clock) */
-    uint64_t critical_cfg;   /* the configuration that took it */
+    uint64_t critical_ns;    /* longest single-partition exploration (device clock) */
+    uint64_t critical_cfg;   /* the configuration of that partition */
+    uint64_t parts;          /* partitions of the persistent launch (configurations, or
+                                blocks of whole rounds of them) */
 } mc_stats;
 
 typedef struct mc_model_info {
@@ -218,7 +224,10 @@ typedef struct mc_batch_opts {
                                 and replay it (needs a non-null stream: MC_E_INVAL) */
     uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
                                 (any other value = 2) */
-    uint32_t reserved[2];
+    uint32_t part_states;    /* target states per partition when a configuration's
+                                subgraph is cut into blocks of whole rounds
+                                (0 = automatic, UINT32_MAX = never cut) */
+    uint32_t reserved[1];
 } mc_batch_opts;
 
 /* Workspace bytes of a batch of n models (host array of n descriptors). */

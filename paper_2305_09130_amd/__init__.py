@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libmctune.so")
 MC_OK = 0
 MC_E_INVAL, MC_E_NOMEM, MC_E_DEVICE, MC_E_TABLE_FULL = -1, -2, -3, -4
 MC_E_BUFFER, MC_E_STATE, MC_E_OVERFLOW, MC_E_ADMIT, MC_E_NOTFOUND = -5, -6, -7, -8, -9
+MC_E_INTERNAL = -10
+NEVER_CUT = 0xFFFFFFFF
 MC_KIND_REDUCTION, MC_KIND_MATMUL = 0, 1
 MC_ENGINE_SUPERSTEP, MC_ENGINE_LEVEL = 0, 1
 MC_MAX_CU = 8
@@ -47,14 +49,14 @@ class McOpts(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_uint32), ("block", ctypes.c_uint32),
                 ("log2_slots", ctypes.c_uint32), ("load_factor", ctypes.c_float),
                 ("grid", ctypes.c_uint32), ("batch_items", ctypes.c_uint32),
-                ("lane_items", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 1)]
+                ("lane_items", ctypes.c_uint32), ("part_states", ctypes.c_uint32)]
 
 
 class McStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("states", "levels", "terminals", "edges", "dups", "probes", "launches",
                  "explore_ns", "total_ns", "clear_ns", "engine_ns", "supersteps",
-                 "batches", "max_probe", "critical_ns", "critical_cfg")]
+                 "batches", "max_probe", "critical_ns", "critical_cfg", "parts")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -71,12 +73,13 @@ class McBatchOpts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("load_factor", ctypes.c_float), ("chunk", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("lane_items", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("part_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 1)]
 
     def as_dict(self) -> dict:
         return {"block": int(self.block), "grid": int(self.grid),
                 "load_factor": float(self.load_factor), "chunk": int(self.chunk),
-                "use_graph": int(self.use_graph), "lane_items": int(self.lane_items)}
+                "use_graph": int(self.use_graph), "lane_items": int(self.lane_items),
+                "part_states": int(self.part_states)}
 
 
 class McEngineOpts(ctypes.Structure):
@@ -177,11 +180,11 @@ def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
 
 def make_opts(engine: int = MC_ENGINE_SUPERSTEP, block: int = 0, log2_slots: int = 0,
               load_factor: float = 0.0, grid: int = 0, batch_items: int = 0,
-              lane_items: int = 0) -> McOpts:
+              lane_items: int = 0, part_states: int = 0) -> McOpts:
     o = McOpts()
     o.engine, o.block, o.log2_slots, o.load_factor, o.grid = engine, block, log2_slots, \
         load_factor, grid
-    o.batch_items, o.lane_items = batch_items, lane_items
+    o.batch_items, o.lane_items, o.part_states = batch_items, lane_items, part_states
     return o
 
 
@@ -217,14 +220,14 @@ class Model:
     def __init__(self, model: dict, engine: int = MC_ENGINE_SUPERSTEP, block: int = 0,
                  log2_slots: int = 0, load_factor: float = 0.0, grid: int = 0,
                  device: str = "cuda:0", stream=None, workspace=None, batch_items: int = 0,
-                 lane_items: int = 0):
+                 lane_items: int = 0, part_states: int = 0):
         import torch
         self.model = model
         self.m = model["m"]
         self.n_cfg = len(model["params"])
         self._desc, self._params = make_desc(model)
         self._opts = make_opts(engine, block, log2_slots, load_factor, grid, batch_items,
-                               lane_items)
+                               lane_items, part_states)
         nbytes = mc_workspace_bytes(model, self._opts)
         self.device = torch.device(device)
         if workspace is None:
@@ -320,11 +323,12 @@ def _desc_array(models: list[dict]):
 
 
 def make_batch_opts(block: int = 0, grid: int = 0, load_factor: float = 0.0, chunk: int = 0,
-                    use_graph: bool = False, lane_items: int = 0) -> McBatchOpts:
+                    use_graph: bool = False, lane_items: int = 0,
+                    part_states: int = 0) -> McBatchOpts:
     o = McBatchOpts()
     o.block, o.grid, o.load_factor, o.chunk = block, grid, load_factor, chunk
     o.use_graph = 1 if use_graph else 0
-    o.lane_items = lane_items
+    o.lane_items, o.part_states = lane_items, part_states
     return o
 
 

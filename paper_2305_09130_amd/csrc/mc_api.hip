@@ -35,11 +35,12 @@ struct WsPlan {
   uint64_t fcap = 0;
   uint64_t trace_cap = 0;
   size_t table_bytes = 0;
+  uint64_t n_parts = 0;
 };
 
 uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
 
-int plan_ws(const ModelHost& mh, const mc_opts& o, WsPlan* p) {
+int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) {
   uint64_t slots;
   if (o.log2_slots) {
     if (o.log2_slots < 4 || o.log2_slots > 31) return MC_E_INVAL;
@@ -56,7 +57,8 @@ int plan_ws(const ModelHost& mh, const mc_opts& o, WsPlan* p) {
   p->ctrl = off;   off = align_up(off + sizeof(Ctrl));
   p->tc = off;     off = align_up(off + 4ull * mh.n_cfg);
   p->cfgs = off;   off = align_up(off + sizeof(CfgRec) * mh.n_cfg);
-  p->order = off;  off = align_up(off + 8ull * mh.n_cfg);
+  p->n_parts = n_parts;
+  p->order = off;  off = align_up(off + sizeof(Part) * n_parts);
   p->md = off;     off = align_up(off + sizeof(ModelDev));
   p->head = off;   off = align_up(off + 4);
   p->seeds = off;  off = align_up(off + sizeof(Seed) * mh.n_cfg);
@@ -84,6 +86,21 @@ mc_opts default_opts(const mc_opts* o) {
   return r;
 }
 
+// Partitions of a single-model query, largest expected block first.
+std::vector<Part> model_parts(const ModelHost& mh, const mc_opts& o) {
+  const uint64_t target = o.part_states == 0xFFFFFFFFu ? 0u
+                          : o.part_states              ? o.part_states
+                                                       : auto_part_states(mh.states);
+  std::vector<PartPlan> plan;
+  plan_parts(mh, target, &plan);
+  std::stable_sort(plan.begin(), plan.end(),
+                   [](const PartPlan& a, const PartPlan& b) { return a.states > b.states; });
+  std::vector<Part> parts(plan.size());
+  for (size_t i = 0; i < plan.size(); ++i)
+    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1};
+  return parts;
+}
+
 void host_encode(const Layout& L, const uint32_t* fields, uint64_t* words) {
   for (int j = 0; j < 4; ++j) words[j] = 0;
   for (int f = 0; f < 3 + L.m; ++f) words[L.word[f]] |= (uint64_t)fields[f] << L.shift[f];
@@ -94,14 +111,6 @@ void host_decode(const Layout& L, const uint64_t* words, uint32_t* fields) {
     fields[f] = (uint32_t)((words[L.word[f]] >> L.shift[f]) & ((1ull << L.width[f]) - 1ull));
 }
 
-int dev_err(unsigned int e) {
-  switch (e) {
-    case 0: return MC_OK;
-    case kDevErrTableFull: return MC_E_TABLE_FULL;
-    case kDevErrOverflow: return MC_E_OVERFLOW;
-    default: return MC_E_DEVICE;
-  }
-}
 
 #define HIPCHK(x)                      \
   do {                                 \
@@ -125,7 +134,8 @@ struct mc_model {
   Ctrl* ctrl = nullptr;
   uint32_t* tc = nullptr;
   CfgRec* cfgs = nullptr;
-  uint2* parts = nullptr;
+  Part* parts = nullptr;
+  uint32_t n_parts = 0;
   ModelDev* dmd = nullptr;
   unsigned int* head = nullptr;
   ModelDev* hmd = nullptr;  // pinned host staging of the device descriptor
@@ -244,7 +254,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     PartQueue pq;
     pq.models = h->dmd;
     pq.parts = h->parts;
-    pq.n_parts = h->mh.n_cfg;
+    pq.n_parts = h->n_parts;
     const uint32_t li = h->opts.lane_items ? h->opts.lane_items : 2u;
     pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
     pq.head = h->head;
@@ -252,7 +262,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     pq.pad = 0u;
     pq.yielded = nullptr;
     pq.n_yielded = nullptr;
-    const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->mh.n_cfg, 4096u);
+    const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
     HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq));
     HIPCHK(hipEventRecord(h->ev[5], s));
     launches = 2;
@@ -274,7 +284,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
   HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(h->tc_host.data(), h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int derr = dev_err(h->hctrl->error);
+  const int derr = dev_error_code(h->hctrl->error);
   if (derr != MC_OK) return derr;
   float ms_explore = 0.f, ms_clear = 0.f, ms_engine = 0.f;
   HIPCHK(hipEventElapsedTime(&ms_explore, h->ev[2], h->ev[3]));
@@ -297,6 +307,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     st->max_probe = h->hctrl->max_probe;
     st->critical_ns = h->hctrl->crit_ticks * 10ull;  // 100 MHz device clock
     st->critical_cfg = h->hctrl->crit_part;
+    st->parts = h->opts.engine == MC_ENGINE_SUPERSTEP ? h->n_parts : 0u;
     st->total_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                        std::chrono::steady_clock::now() - t0)
                        .count();
@@ -357,6 +368,7 @@ const char* mc_strerror(int code) {
     case MC_E_OVERFLOW: return "frontier or packed field overflow";
     case MC_E_ADMIT: return "query cannot fit the memory budget";
     case MC_E_NOTFOUND: return "not found";
+    case MC_E_INTERNAL: return "internal consistency check failed";
     default: return "unknown error";
   }
 }
@@ -384,7 +396,8 @@ int mc_workspace_bytes(const mc_desc* d, const mc_opts* o, size_t* bytes) {
     int rc = build_model(d, &mh, &err);
     if (rc) return rc;
     WsPlan p;
-    rc = plan_ws(mh, default_opts(o), &p);
+    const mc_opts oo = default_opts(o);
+    rc = plan_ws(mh, oo, model_parts(mh, oo).size(), &p);
     if (rc) return rc;
     *bytes = p.total;
     return MC_OK;
@@ -418,7 +431,7 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
       return rc;
     }
     h->opts = default_opts(o);
-    rc = plan_ws(h->mh, h->opts, &h->plan);
+    rc = plan_ws(h->mh, h->opts, model_parts(h->mh, h->opts).size(), &h->plan);
     if (rc) {
       delete h;
       return rc;
@@ -432,7 +445,7 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     h->ctrl = reinterpret_cast<Ctrl*>(h->ws + h->plan.ctrl);
     h->tc = reinterpret_cast<uint32_t*>(h->ws + h->plan.tc);
     h->cfgs = reinterpret_cast<CfgRec*>(h->ws + h->plan.cfgs);
-    h->parts = reinterpret_cast<uint2*>(h->ws + h->plan.order);
+    h->parts = reinterpret_cast<Part*>(h->ws + h->plan.order);
     h->dmd = reinterpret_cast<ModelDev*>(h->ws + h->plan.md);
     h->head = reinterpret_cast<unsigned int*>(h->ws + h->plan.head);
     h->seeds = reinterpret_cast<Seed*>(h->ws + h->plan.seeds);
@@ -457,19 +470,13 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
         return MC_E_DEVICE;
       }
     }
-    // partitions, largest subgraph first
-    std::vector<uint32_t> order(h->mh.n_cfg);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-      return h->mh.cfg_states[a] > h->mh.cfg_states[b];
-    });
-    std::vector<uint2> parts(h->mh.n_cfg);
-    for (uint32_t i = 0; i < h->mh.n_cfg; ++i) parts[i] = make_uint2(0u, order[i]);
+    const std::vector<Part> parts = model_parts(h->mh, h->opts);
+    h->n_parts = (uint32_t)parts.size();
     hipStream_t s = h->stream;
     if (hipMemcpyAsync(h->cfgs, h->mh.cfgs.data(), sizeof(CfgRec) * h->mh.n_cfg,
                        hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(h->parts, parts.data(), 8ull * h->mh.n_cfg, hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
+        hipMemcpyAsync(h->parts, parts.data(), sizeof(Part) * parts.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       (void)hipGetLastError();
       mc_model_free(h);

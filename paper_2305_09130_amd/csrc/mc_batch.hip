@@ -48,7 +48,37 @@ mc_batch_opts default_bopts(const mc_batch_opts* o) {
   return r;
 }
 
-int plan_batch(const std::vector<ModelHost>& ms, const mc_batch_opts& o, BatchPlan* p) {
+// Partitions of a batch: every model's configurations, cut into blocks of whole rounds,
+// grouped by key width (one launch each) and largest first within a group.
+struct BPart {
+  uint64_t size;
+  uint32_t model, cfg, r0, r1;
+};
+
+int width_group(uint32_t W) { return W == 1 ? 0 : W == 2 ? 1 : 2; }
+
+std::vector<BPart> batch_parts(const std::vector<ModelHost>& ms, const mc_batch_opts& o) {
+  uint64_t total = 0;
+  for (const auto& m : ms) total += m.states;
+  const uint64_t target = o.part_states == 0xFFFFFFFFu ? 0u
+                          : o.part_states              ? o.part_states
+                                                       : auto_part_states(total);
+  std::vector<BPart> ps;
+  std::vector<PartPlan> plan;
+  for (uint32_t i = 0; i < (uint32_t)ms.size(); ++i) {
+    plan.clear();
+    plan_parts(ms[i], target, &plan);
+    for (const auto& q : plan) ps.push_back({q.states, i, q.cfg, q.r0, q.r1});
+  }
+  std::stable_sort(ps.begin(), ps.end(), [&](const BPart& a, const BPart& c) {
+    const int ga = width_group(ms[a.model].W), gc = width_group(ms[c.model].W);
+    return ga != gc ? ga < gc : a.size > c.size;
+  });
+  return ps;
+}
+
+int plan_batch(const std::vector<ModelHost>& ms, const mc_batch_opts& o, uint64_t n_parts,
+               BatchPlan* p) {
   const size_t n = ms.size();
   size_t off = 0;
   p->ctrl = off;
@@ -76,10 +106,9 @@ int plan_batch(const std::vector<ModelHost>& ms, const mc_batch_opts& o, BatchPl
   off = align_up(off);
   p->md = off;
   off = align_up(off + sizeof(ModelDev) * n);
-  p->n_parts = 0;
-  for (const auto& m : ms) p->n_parts += m.n_cfg;
+  p->n_parts = n_parts;
   p->parts = off;
-  off = align_up(off + 8ull * p->n_parts);
+  off = align_up(off + sizeof(Part) * p->n_parts);
   p->head = off;
   off = align_up(off + 16);
   p->tables = off;
@@ -127,7 +156,7 @@ struct mc_batch {
   hipStream_t stream = nullptr;
   unsigned char* ws = nullptr;
   ModelDev* dmd = nullptr;
-  uint2* parts = nullptr;
+  Part* parts = nullptr;
   unsigned int* head = nullptr;
   unsigned char* hctrl = nullptr;  // pinned: n * kCtrlStride
   uint32_t* htc = nullptr;         // pinned: all clocks
@@ -219,7 +248,8 @@ int mc_batch_workspace_bytes(const mc_desc* models, uint32_t n, const mc_batch_o
     int rc = build_models(models, n, &ms);
     if (rc) return rc;
     BatchPlan p;
-    rc = plan_batch(ms, default_bopts(o), &p);
+    const mc_batch_opts oo = default_bopts(o);
+    rc = plan_batch(ms, oo, batch_parts(ms, oo).size(), &p);
     if (rc) return rc;
     *bytes = p.total;
     return MC_OK;
@@ -241,7 +271,8 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
       return rc;
     }
     b->opts = default_bopts(o);
-    rc = plan_batch(b->ms, b->opts, &b->plan);
+    const std::vector<BPart> ps = batch_parts(b->ms, b->opts);
+    rc = plan_batch(b->ms, b->opts, ps.size(), &b->plan);
     if (rc) {
       delete b;
       return rc;
@@ -253,7 +284,7 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
     b->stream = reinterpret_cast<hipStream_t>(stream);
     b->ws = reinterpret_cast<unsigned char*>(dev_ws);
     b->dmd = reinterpret_cast<ModelDev*>(b->ws + b->plan.md);
-    b->parts = reinterpret_cast<uint2*>(b->ws + b->plan.parts);
+    b->parts = reinterpret_cast<Part*>(b->ws + b->plan.parts);
     b->head = reinterpret_cast<unsigned int*>(b->ws + b->plan.head);
     for (const auto& m : b->ms) b->tc_words += m.n_cfg;
     if (hipHostMalloc(reinterpret_cast<void**>(&b->hctrl), kCtrlStride * n, hipHostMallocDefault) !=
@@ -268,13 +299,6 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
     }
     // descriptors, configuration tables and the partition queue (largest first)
     std::vector<ModelDev> md(n);
-    std::vector<CfgRec> cfgs;
-    struct P {
-      uint64_t size;
-      uint32_t model, cfg;
-    };
-    std::vector<P> ps;
-    ps.reserve(b->plan.n_parts);
     for (uint32_t i = 0; i < n; ++i) {
       const ModelHost& m = b->ms[i];
       ModelDev& d = md[i];
@@ -288,18 +312,11 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
       d.L = m.layout;
       d.n_cfg = m.n_cfg;
       d.max_clock = m.max_clock;
-      for (uint32_t c = 0; c < m.n_cfg; ++c) ps.push_back({m.cfg_states[c], i, c});
     }
-    // group by key width (one launch each), largest partition first within a group
-    auto wgroup = [&](const P& p) { const uint32_t W = b->ms[p.model].W; return W == 1 ? 0 : W == 2 ? 1 : 2; };
-    std::stable_sort(ps.begin(), ps.end(), [&](const P& a, const P& c) {
-      const int ga = wgroup(a), gc = wgroup(c);
-      return ga != gc ? ga < gc : a.size > c.size;
-    });
-    std::vector<uint2> parts(ps.size());
+    std::vector<Part> parts(ps.size());
     for (size_t k = 0; k < ps.size(); ++k) {
-      parts[k] = make_uint2(ps[k].model, ps[k].cfg);
-      ++b->group_n[wgroup(ps[k])];
+      parts[k] = Part{ps[k].model, ps[k].cfg, ps[k].r0, ps[k].r1};
+      ++b->group_n[width_group(b->ms[ps[k].model].W)];
     }
     b->group_off[0] = 0;
     b->group_off[1] = b->group_n[0];
@@ -314,8 +331,8 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
       }
     if (hipMemcpyAsync(b->dmd, md.data(), sizeof(ModelDev) * n, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipMemcpyAsync(b->parts, parts.data(), 8ull * parts.size(), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
+        hipMemcpyAsync(b->parts, parts.data(), sizeof(Part) * parts.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       (void)hipGetLastError();
       free_batch(b);
@@ -381,7 +398,7 @@ int mc_batch_min_time(mc_batch* b, uint32_t* t_min, uint64_t* states, mc_stats* 
   for (uint32_t i = 0; i < n; ++i) {
     const Ctrl* c = reinterpret_cast<const Ctrl*>(b->hctrl + kCtrlStride * i);
     if (c->error && rc == MC_OK)
-      rc = c->error == 1u ? MC_E_TABLE_FULL : c->error == 2u ? MC_E_OVERFLOW : MC_E_DEVICE;
+      rc = dev_error_code(c->error);
     uint32_t best = kNoClock;
     for (uint32_t k = 0; k < b->ms[i].n_cfg; ++k) best = std::min(best, b->htc[tcpos + k]);
     tcpos += b->ms[i].n_cfg;
@@ -401,6 +418,7 @@ int mc_batch_min_time(mc_batch* b, uint32_t* t_min, uint64_t* states, mc_stats* 
       acc.critical_cfg = c->crit_part;
     }
   }
+  acc.parts = b->plan.n_parts;
   acc.launches = b->exec ? 1 : 4;
   acc.explore_ns = (uint64_t)(ms * 1e6);
   acc.engine_ns = acc.explore_ns;

@@ -40,6 +40,7 @@ constexpr unsigned int kDevErrTableFull = 1;
 constexpr unsigned int kDevErrOverflow = 2;
 constexpr unsigned int kDevErrPublish = 3;
 constexpr unsigned int kDevErrTrace = 4;
+constexpr unsigned int kDevErrSplit = 5;  // a round block did not end on its predicted state
 
 constexpr uint32_t kMaxProbeIters = 1u << 16;
 

@@ -150,7 +150,7 @@ struct mc_engine {
   std::deque<Query*> waiting;
   std::vector<Query*> slots;  // model slot -> active query
   std::unordered_map<uint64_t, Query*> all;
-  std::vector<uint2> pending_parts;  // partitions of the next launch (host side)
+  std::vector<Part> pending_parts;  // partitions of the next launch (host side)
   uint32_t n_cur = 0;                // partitions in parts buffer `cur`
   int cur = 0;
   unsigned char* hctrl = nullptr;  // pinned
@@ -206,8 +206,8 @@ int mc_engine_bytes(const mc_engine_opts* o, size_t arena_bytes, size_t* bytes) 
   off = align_up(off + sizeof(ModelDev) * o->max_active);
   off = align_up(off + sizeof(ModelDev) * o->max_active);
   const size_t maxparts = (size_t)o->max_cfg * o->max_active;
-  off = align_up(off + 8ull * maxparts);
-  off = align_up(off + 8ull * maxparts);
+  off = align_up(off + sizeof(Part) * maxparts);
+  off = align_up(off + sizeof(Part) * maxparts);
   off = align_up(off + 4);
   off = align_up(off + 16);
   *bytes = off + align_up(arena_bytes);
@@ -241,9 +241,9 @@ int mc_engine_create(const mc_engine_opts* o, void* dev_buf, size_t buf_bytes, v
     e->stage_off = off;
     off = align_up(off + sizeof(ModelDev) * A);
     e->parts_off[0] = off;
-    off = align_up(off + 8ull * maxparts);
+    off = align_up(off + sizeof(Part) * maxparts);
     e->parts_off[1] = off;
-    off = align_up(off + 8ull * maxparts);
+    off = align_up(off + sizeof(Part) * maxparts);
     e->nyield_off = off;
     off = align_up(off + 4);
     e->head_off = off;
@@ -375,7 +375,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
         return q->mh.cfg_states[a] > q->mh.cfg_states[b];
       });
-      for (uint32_t c : order) e->pending_parts.push_back(make_uint2((uint32_t)q->slot_idx, c));
+      for (uint32_t c : order) e->pending_parts.push_back(Part{(uint32_t)q->slot_idx, c, 0u, kRoundsToEnd});
     }
     // the host must not overwrite the pinned staging before the copy ran
     HIPCHK(hipStreamSynchronize(s));
@@ -385,21 +385,22 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
   for (Query* q : e->slots) any_active |= q != nullptr;
   if (any_active && !e->pending_parts.empty()) {
     const int cur = e->cur;
-    uint2* parts = reinterpret_cast<uint2*>(e->base + e->parts_off[cur]);
-    uint2* next = reinterpret_cast<uint2*>(e->base + e->parts_off[cur ^ 1]);
+    Part* parts = reinterpret_cast<Part*>(e->base + e->parts_off[cur]);
+    Part* next = reinterpret_cast<Part*>(e->base + e->parts_off[cur ^ 1]);
     // one launch per key width: group the partitions, keeping their order within a group
-    std::vector<uint2> grouped;
+    std::vector<Part> grouped;
     grouped.reserve(e->pending_parts.size());
     uint32_t gn[3] = {0, 0, 0};
     for (int g = 0; g < 3; ++g)
-      for (const uint2& p : e->pending_parts) {
-        const uint32_t W = e->slots[p.x]->mh.W;
+      for (const Part& p : e->pending_parts) {
+        const uint32_t W = e->slots[p.model]->mh.W;
         if ((W == 1 ? 0 : W == 2 ? 1 : 2) == g) {
           grouped.push_back(p);
           ++gn[g];
         }
       }
-    HIPCHK(hipMemcpyAsync(parts, grouped.data(), 8ull * grouped.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(parts, grouped.data(), sizeof(Part) * grouped.size(),
+                          hipMemcpyHostToDevice, s));
     unsigned int* head = reinterpret_cast<unsigned int*>(e->base + e->head_off);
     unsigned int* ny = reinterpret_cast<unsigned int*>(e->base + e->nyield_off);
     HIPCHK(hipMemsetAsync(head, 0, 16, s));
@@ -436,7 +437,8 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
     const uint32_t nyield = *e->hny;
     e->pending_parts.resize(nyield);
     if (nyield)
-      HIPCHK(hipMemcpy(e->pending_parts.data(), next, 8ull * nyield, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(e->pending_parts.data(), next, sizeof(Part) * nyield,
+                       hipMemcpyDeviceToHost));
     // ---- retire finished queries ----
     for (size_t i = 0; i < e->slots.size(); ++i) {
       Query* q = e->slots[i];
@@ -446,9 +448,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       if (c->parts_done < q->mh.n_cfg && !failed) continue;
       const uint32_t* tc = e->htc + (size_t)e->opts.max_cfg * i;
       mc_query_result& r = q->res;
-      r.status = failed ? (c->error == 1u ? MC_E_TABLE_FULL
-                           : c->error == 2u ? MC_E_OVERFLOW : MC_E_DEVICE)
-                        : MC_OK;
+      r.status = dev_error_code(c->error);
       r.states = c->states;
       r.levels = c->max_depth + 1;
       uint32_t best = kNoClock, first = kNoClock, n = 0;
@@ -465,9 +465,9 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       finish(e, q);
       // drop any partition of a failed query still queued
       if (failed) {
-        std::vector<uint2> keep;
-        for (const uint2& p : e->pending_parts)
-          if (p.x != (uint32_t)i) keep.push_back(p);
+        std::vector<Part> keep;
+        for (const Part& p : e->pending_parts)
+          if (p.model != (uint32_t)i) keep.push_back(p);
         e->pending_parts.swap(keep);
       }
     }

@@ -279,7 +279,22 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
 // are inserted, and the visited set alone decides which are new: a run end found to be
 // a duplicate was expanded by whoever inserted it first, and its re-expansion only
 // produces duplicates.  Run ends that are new and non-terminal form the next frontier.
+//
+// Blocks of rounds.  A full round (every unit idle, at least m workgroups pending)
+// starts all m units at one clock; they stay in lock step and the round ends with every
+// unit idle again, at clock + d with m fewer pending.  Every path of the configuration
+// therefore passes through the state B_r reached after r full rounds, and a partition
+// may cover rounds [r0, r1) only.  Such a block inserts B_r0 itself (it may find it
+// already inserted by the block before), explores from it, and stops at B_r1: that
+// state is inserted, given its parent and jump, and left to the next block.  B_r0 and
+// B_r1 are the only states a block shares with another workgroup, and, the
+// configuration, pending count and clock being in key word 0, the only word-0 values it
+// shares; they are inserted with agent-scope ordering, every other key with
+// workgroup-scope ordering as in a whole subgraph.  A block checks that its last run
+// ends exactly on B_r1 with the depth r1 rounds give, so that the union of the blocks
+// is the configuration's whole subgraph.
 constexpr int kSegMax = 8;
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;
 constexpr int kEMax = 4096;  // operation ends kept in LDS
 constexpr int kFCap = 256;   // frontier states per super-step level (LDS)
 constexpr int kMaxLeaves = 72;  // C(8, 4) = 70 leaves at most
@@ -307,6 +322,10 @@ struct SuperShared {
   uint32_t fdep[2][kFCap];
   uint32_t fcount[2];
   uint32_t part, carry, stop, nseg, total;
+  // end of a block of rounds: the state B_r1, its clock and depth, the batch item that
+  // generates it, and whether it was reached
+  unsigned long long stopkey[4];
+  uint32_t has_stop, stop_clock, stop_dep, stop_item, stop_slot, handed;
   ModelDev md;  // descriptor of the model being explored
   // successors of the leaves of a segment whose run is not in lock step (one ADVANCE
   // each), computed once per super-step outside the batch loop
@@ -425,19 +444,24 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
 __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
 
 template <int W, int BLOCK, int NI>
-__device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch_items,
-                                  uint32_t slice, const PartQueue& pq, uint32_t model,
+__device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t batch_items,
+                                  uint32_t slice, const PartQueue& pq,
                                   SuperShared<BLOCK, NI>& sh) {
   Tally tl;
   const Layout& L = md.L;
   const int m = L.m;
   const uint32_t tid = threadIdx.x;
+  const uint32_t c = pt.cfg;
+  const bool whole = pt.r0 == 0u && pt.r1 == kRoundsToEnd;
   const CfgRec r = md.cfgs[c];
   const bool e_lds = r.b <= (uint32_t)kEMax;
   if (e_lds)
     for (uint32_t k = tid; k < r.b; k += BLOCK) sh.E[k] = end_at(r, k);
   if (tid == 0) {
-    if (md.pstate && md.pstate[c].status == 1u) {  // resume a partition that yielded
+    sh.has_stop = 0u;
+    sh.handed = 0u;
+    sh.stop_item = kNoItem;
+    if (whole && md.pstate && md.pstate[c].status == 1u) {  // resume a partition that yielded
       const PartState ps = md.pstate[c];
 #pragma unroll
       for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = ps.k[w];
@@ -446,11 +470,49 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
       sh.fcount[0] = 1u;
     } else {
       const Seed sd = md.seeds[c];
+      unsigned long long k0[W];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = sd.k[w];
-      sh.fslot[0][0] = sd.slot;
-      sh.fdep[0][0] = sd.depth;
+      for (int w = 0; w < W; ++w) k0[w] = sd.k[w];
+      uint32_t slot0 = sd.slot, dep0 = sd.depth;
       sh.fcount[0] = sd.slot == kParentNone ? 0u : 1u;
+      const uint32_t round_dep = (uint32_t)m + r.b;  // m dispatches, b advances
+      if (pt.r0 != 0u && sh.fcount[0]) {
+        // B_r0: r0 full rounds after the configuration's SELECT state
+        field_add<W>(k0, L, kFClock, (unsigned long long)pt.r0 * r.d);
+        field_add<W>(k0, L, kFPending, (unsigned long long)(-(long long)pt.r0 * m));
+        dep0 = sd.depth + pt.r0 * round_dep;
+        if (md.prune && (unsigned long long)pt.r0 * r.d > md.T) {
+          sh.fcount[0] = 0u;
+        } else {
+          Key<W> k;
+#pragma unroll
+          for (int w = 0; w < W; ++w) k.w[w] = k0[w];
+          const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot0, tl.probes);
+          if (res == kInsFail) {
+            set_error(md.ctrl, kDevErrTableFull);
+            sh.fcount[0] = 0u;
+          } else if (res == kInsNew) {
+            ++tl.states;
+            tl.depth = dep0 > tl.depth ? dep0 : tl.depth;
+          }
+        }
+      }
+      if (pt.r1 != kRoundsToEnd) {
+        unsigned long long k1[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) k1[w] = sd.k[w];
+        field_add<W>(k1, L, kFClock, (unsigned long long)pt.r1 * r.d);
+        field_add<W>(k1, L, kFPending, (unsigned long long)(-(long long)pt.r1 * m));
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sh.stopkey[w] = w < W ? k1[w] : 0ull;
+        sh.stop_clock = pt.r1 * r.d;
+        sh.stop_dep = sd.depth + pt.r1 * round_dep;
+        sh.has_stop = 1u;
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = w < W ? k0[w] : 0ull;
+      sh.fslot[0][0] = slot0;
+      sh.fdep[0][0] = dep0;
     }
     sh.fcount[1] = 0u;
   }
@@ -459,7 +521,7 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
   uint32_t levels = 0;
   bool yielded = false;
   while (sh.fcount[cur] > 0u && !sh.stop) {
-    if (slice && md.pstate && levels >= slice && sh.fcount[cur] == 1u) {
+    if (slice && whole && md.pstate && levels >= slice && sh.fcount[cur] == 1u) {
       // out of budget for this launch: save the single frontier state and yield
       if (tid == 0) {
         PartState ps;
@@ -471,7 +533,7 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
         ps.pad = 0u;
         md.pstate[c] = ps;
         const uint32_t pos = atomicAdd(pq.n_yielded, 1u);
-        pq.yielded[pos] = make_uint2(model, c);
+        pq.yielded[pos] = pt;
       }
       yielded = true;
       break;
@@ -486,6 +548,7 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
         for (int w = 0; w < W; ++w) ck.w[w] = sh.fkey[cur][fi][w];
         uint32_t fslot = sh.fslot[cur][fi], fdep = sh.fdep[cur][fi];
         uint32_t total = 0, nseg = 0;
+        sh.stop_item = kNoItem;
         bool decoded = false;  // sh.seg[nseg] already derived from the previous segment
         for (;;) {
           SegDesc& sg = sh.seg[nseg];
@@ -550,6 +613,54 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
           ++nseg;
           // continue with the run end: a single lock-step run ending with work pending
           const uint32_t end_clock = sg.fclock + (r.d - sg.e0);
+          if (sh.has_stop) {
+            // inside a block every segment is a full round, and the block ends on B_r1
+            if (!sg.aux || end_clock > sh.stop_clock) {
+              set_error(md.ctrl, kDevErrSplit);
+              sh.stop = 1u;
+              break;
+            }
+            if (end_clock == sh.stop_clock) {
+              // the run end is B_r1: generated by the same arithmetic as every run end,
+              // it must be the state r1 full rounds give, at the depth they give
+              sh.stop_item = total - 1u;  // the last run state of this segment
+              sh.stop_slot = kParentNone;
+              unsigned long long ek[W];
+#pragma unroll
+              for (int w = 0; w < W; ++w) ek[w] = sg.base[w];
+              field_add<W>(ek, L, kFClock, end_clock);
+              bool ok = fdep + sg.kstar + sg.len == sh.stop_dep;
+              Key<W> k;
+#pragma unroll
+              for (int w = 0; w < W; ++w) {
+                ok = ok && ek[w] == sh.stopkey[w];
+                k.w[w] = ek[w];
+              }
+              if (!ok) {
+                set_error(md.ctrl, kDevErrSplit);
+                sh.stop = 1u;
+              } else if (!(md.prune && end_clock > md.T)) {
+                // shared with the next block: agent-scope ordering
+                uint32_t slot = kParentNone;
+                const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, tl.probes);
+                ++tl.edges;
+                if (res == kInsFail) {
+                  set_error(md.ctrl, kDevErrTableFull);
+                  sh.stop = 1u;
+                } else {
+                  if (res == kInsNew) {
+                    ++tl.states;
+                    tl.depth = sh.stop_dep > tl.depth ? sh.stop_dep : tl.depth;
+                  } else {
+                    ++tl.dups;
+                  }
+                  sh.stop_slot = slot;
+                  sh.handed = 1u;
+                }
+              }
+              break;
+            }
+          }
           const bool more = sg.lock && sg.nleaf == 1u && sg.pend > 0u &&
                             nseg < (uint32_t)kSegMax && total < batch_items &&
                             !(md.prune && end_clock > md.T) && end_clock <= md.max_clock;
@@ -586,6 +697,9 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
       __syncthreads();
       const uint32_t nseg = sh.nseg;
       const uint32_t total = sh.total;
+      const uint32_t stop_item = sh.stop_item;
+      // B_r1, the end of a block, is left out of the batch and inserted below
+      const uint32_t n_items = stop_item == kNoItem ? total : total - 1u;
       tl.super += nseg;
       // leaf list of a segment with several leaves (a partial round); only the last
       // segment of a batch can have several
@@ -631,15 +745,15 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
         }
         __syncthreads();
       }
-      for (uint32_t base = 0; base < total; base += NI * BLOCK) {
+      for (uint32_t base = 0; base < n_items; base += NI * BLOCK) {
         ++tl.chunks;
         unsigned long long keys[NI][W];
         bool act[NI];
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
           Item<W> x;
-          gen_item<W, BLOCK, NI, true>(base + (uint32_t)n * BLOCK + tid, total, nseg, sh, r, e_lds,
-                                       md, m, x);
+          gen_item<W, BLOCK, NI, true>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+                                       e_lds, md, m, x);
           if (x.active && x.clk > md.max_clock) {
             set_error(md.ctrl, kDevErrOverflow);
             x.active = false;
@@ -657,7 +771,7 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
         Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
-          gen_item<W, BLOCK, NI, false>(base + (uint32_t)n * BLOCK + tid, total, nseg, sh, r,
+          gen_item<W, BLOCK, NI, false>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                         e_lds, md, m, it[n]);
           it[n].active = act[n];
           fresh[n] = false;
@@ -722,13 +836,29 @@ __device__ void explore_partition(const ModelDev& md, uint32_t c, uint32_t batch
         if (tid == BLOCK - 1) sh.carry = sh.chunk_slot[NI * BLOCK - 1];
         __syncthreads();
       }
+      if (stop_item != kNoItem && tid == 0 && sh.stop_slot != kParentNone) {
+        // B_r1 (claimed by the builder) gets its parent and jump from this block even if
+        // the next block inserted it first: that block knows only its key.  Its parent
+        // is the run's previous state, the last item of the batch's last chunk.
+        const SegDesc& sg = sh.seg[nseg - 1u];
+        const uint32_t leaf_slot = sh.mslot[nseg - 1u][(1u << sg.nfree) - 1u];
+        const uint32_t par =
+            sg.len > 1u ? sh.chunk_slot[(stop_item - 1u) % (NI * BLOCK)] : leaf_slot;
+        *slot_parent<W>(md.table, sh.stop_slot) = par;
+        *slot_jump<W>(md.table, sh.stop_slot) = leaf_slot;
+      }
     }
     if (tid == 0) sh.fcount[cur] = 0u;
     __syncthreads();
     cur ^= 1;
   }
   if (!yielded && tid == 0) {
-    if (md.pstate) md.pstate[c].status = 2u;
+    // a block that did not reach B_r1 (unless pruned away or stopped by an error) would
+    // leave part of the subgraph unexplored
+    if (sh.has_stop && !sh.handed && !sh.stop && !(md.prune && sh.stop_clock > md.T) &&
+        __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) == 0u)
+      set_error(md.ctrl, kDevErrSplit);
+    if (whole && md.pstate) md.pstate[c].status = 2u;
     atomicAdd(&md.ctrl->parts_done, 1u);
   }
   flush_tally(md, tl);
@@ -756,18 +886,17 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     __syncthreads();
     const uint32_t part = sh.part;
     if (part >= a.n_parts) break;
-    const uint2 pc = a.parts[part];
-    if (tid == 0) sh.md = a.models[pc.x];
+    const Part pc = a.parts[part];
+    if (tid == 0) sh.md = a.models[pc.model];
     __syncthreads();
     const ModelDev& md = sh.md;
-    const uint32_t c = pc.y;
     const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
     const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
-    if (!skip) explore_partition<W, BLOCK, NI>(md, c, a.batch_items, a.slice, a, pc.x, sh);
+    if (!skip) explore_partition<W, BLOCK, NI>(md, pc, a.batch_items, a.slice, a, sh);
     if (tid == 0) {
       const unsigned long long dt = __builtin_amdgcn_s_memrealtime() - t_part;
       const unsigned long long prev = atomicMax(&md.ctrl->crit_ticks, dt);
-      if (dt > prev) md.ctrl->crit_part = c;
+      if (dt > prev) md.ctrl->crit_part = pc.cfg;
     }
     __syncthreads();
   }

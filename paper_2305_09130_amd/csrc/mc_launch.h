@@ -22,6 +22,17 @@ struct QueryArgs {
   uint32_t max_clock;       // bound of the packed clock field
 };
 
+// Library error code (MC_E_*) of a device error flag (kDevErr*).
+inline int dev_error_code(unsigned int e) {
+  switch (e) {
+    case 0: return MC_OK;
+    case kDevErrTableFull: return MC_E_TABLE_FULL;
+    case kDevErrOverflow: return MC_E_OVERFLOW;
+    case kDevErrSplit: return MC_E_INTERNAL;
+    default: return MC_E_DEVICE;
+  }
+}
+
 struct LevelArgs {
   QueryArgs q;
   uint32_t in_idx, out_idx, clr_idx;  // rotating frontier counters
@@ -55,16 +66,25 @@ struct ModelDev {
   unsigned long long pad2;
 };
 
-// Partitions of a persistent launch: (model index, configuration), largest first.
+// One partition of a persistent launch: rounds [r0, r1) of one configuration's subgraph
+// (r1 = kRoundsToEnd: through its terminal).  After r full rounds the subgraph of a
+// configuration passes through the single state (c, r*d, n - r*m, every unit idle), so a
+// block of whole rounds can be explored from that state on its own.
+struct Part {
+  uint32_t model, cfg, r0, r1;
+};
+static_assert(sizeof(Part) == 16, "Part layout");
+
+// Partitions of a persistent launch, largest first.
 struct PartQueue {
   const ModelDev* models;
-  const uint2* parts;
+  const Part* parts;
   uint32_t n_parts;
   uint32_t batch_items;  // states generated per super-step batch before waiting (target)
   unsigned int* head;
   uint32_t slice;        // super-step levels per partition before it yields (0 = no limit)
   uint32_t pad;
-  uint2* yielded;        // partitions that yielded, for the next launch
+  Part* yielded;         // partitions that yielded, for the next launch
   unsigned int* n_yielded;
 };
 

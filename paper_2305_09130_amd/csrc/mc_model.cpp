@@ -176,4 +176,28 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   return MC_OK;
 }
 
+void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out) {
+  const Layout& L = h.layout;
+  const bool cuttable = target > 0 && L.word[kFPending] == 0 && L.word[kFClock] == 0;
+  for (uint32_t c = 0; c < h.n_cfg; ++c) {
+    const CfgRec& r = h.cfgs[c];
+    const uint64_t q = r.n / h.m;
+    const uint64_t per_round = ((1ull << h.m) - 1) + r.b;
+    uint64_t R = cuttable ? std::max<uint64_t>(kMinBlockRounds, target / per_round) : q;
+    const uint64_t K = R ? (q + R - 1) / R : 1;
+    if (!cuttable || K < 2) {
+      out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
+      continue;
+    }
+    for (uint64_t k = 0; k + 1 < K; ++k)
+      out->push_back(PartPlan{c, (uint32_t)(k * R), (uint32_t)((k + 1) * R), R * per_round});
+    const uint64_t r0 = (K - 1) * R;
+    out->push_back(PartPlan{c, (uint32_t)r0, kRoundsToEnd, h.cfg_states[c] - r0 * per_round});
+  }
+}
+
+uint64_t auto_part_states(uint64_t states) {
+  return std::max<uint64_t>(1ull << 14, states / 1024);
+}
+
 }  // namespace mc

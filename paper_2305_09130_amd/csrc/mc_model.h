@@ -70,6 +70,26 @@ struct ModelHost {
 // Validates d and fills h.  Returns MC_OK or MC_E_INVAL with a message in err.
 int build_model(const mc_desc* d, ModelHost* h, std::string* err);
 
+// One partition of a model's exploration: rounds [r0, r1) of configuration cfg
+// (r1 = kRoundsToEnd: through the terminal), with its expected state count.
+constexpr uint32_t kRoundsToEnd = 0xFFFFFFFFu;
+constexpr uint32_t kMinBlockRounds = 8;  // shortest block worth a partition of its own
+struct PartPlan {
+  uint32_t cfg, r0, r1;
+  uint64_t states;
+};
+
+// Partitions of a model.  Each configuration's subgraph is cut into blocks of whole
+// rounds of about `target` states each (target 0: never cut).  Block k starts at the
+// state reached after r0 full rounds, (c, r0 d, n - r0 m, all units idle), which every
+// path of the configuration passes through.  A cut needs the configuration index, the
+// pending count and the clock in key word 0: two blocks then share no word-0 value
+// except their common boundary state.
+void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
+
+// Default target states per partition for a launch exploring `states` states in total.
+uint64_t auto_part_states(uint64_t states);
+
 uint64_t binom(uint32_t n, uint32_t k);
 uint32_t bit_length(uint64_t x);
 

@@ -50,6 +50,27 @@ def test_batch_small_models_vs_oracle(mc):
     b.close()
 
 
+def test_batch_round_blocks_vs_oracle(mc):
+    """Models with many rounds per configuration, every subgraph cut into 8-round blocks,
+    in one batch (three key widths, so three concurrent launches) against the oracle."""
+    models = [
+        workloads.reduction_model(256, 2, [1, 2, 4, 8], [1, 2], 5, 2, Lb=1),
+        workloads.matmul_model(16, 16, 16, 4, [1, 2], [1, 2], [1, 4], [1, 2], 3, 2),
+        workloads.reduction_model(64, 3, [1, 2], [1, 2], 4, 3),
+        workloads.matmul_model(16, 16, 8, 8, [1], [1], [1, 2], [1], 2, 1),
+        workloads.matmul_64(),
+    ]
+    _say("batch of round-block models")
+    b = mc.Batch(models, mc.make_batch_opts(block=512, part_states=1))
+    t_min, states = b.mc_batch_min_time()
+    assert b.last_stats["parts"] > sum(len(m["params"]) for m in models)
+    for i, m in enumerate(models):
+        r = oracle.explore(m, trace=False)
+        assert (t_min[i], states[i]) == (r["t_min"], r["reachable"]), workloads.describe(m)
+        assert b.mc_batch_terminal_clocks(i) == r["tc"]
+    b.close()
+
+
 @pytest.mark.parametrize("block", [256, 512, 1024])
 def test_batch_equals_alone(mc, block):
     models = _mix(24)

@@ -140,6 +140,62 @@ def test_matmul64(mc, engine):
     g.close()
 
 
+def _block_cases():
+    """Models with many full rounds per configuration, so that 8-round blocks cut every
+    subgraph several times; partial last rounds (m = 3), one unit (m = 1), eight units
+    and a nonzero barrier latency included."""
+    return [
+        workloads.reduction_model(256, 2, [1, 2, 4, 8], [1, 2], 5, 2, Lb=1),
+        workloads.matmul_model(16, 16, 16, 4, [1, 2], [1, 2], [1, 4], [1, 2], 3, 2),
+        workloads.reduction_model(64, 3, [1, 2], [1, 2], 4, 3),
+        workloads.reduction_model(32, 1, [1, 2], [1], 3, 2),
+        workloads.matmul_model(16, 16, 8, 8, [1], [1], [1, 2], [1], 2, 1),
+    ]
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_round_blocks_equal_oracle(mc, case):
+    """Each configuration cut into blocks of 8 rounds (the shortest block) gives the
+    oracle's results exactly, for min_time, its trace, and check(T) at thresholds on,
+    just before and just after block boundaries."""
+    model = _block_cases()[case]
+    _say(f"blocks case {case}: {workloads.describe(model)}")
+    r = ref(model)
+    g = mc.Model(model, engine=0, part_states=1)
+    check_min_time(mc, g, model, r)
+    assert g.last_stats["parts"] > len(model["params"])
+    d0 = cf.per_config(model, with_E=False)[0]["d"]
+    Ts = {r["t_min"] - 1, r["t_min"], 0}
+    for k in (1, 2, 3):
+        Ts |= {8 * k * d0 - 1, 8 * k * d0, 8 * k * d0 + 1}
+    for T in sorted(t for t in Ts if t >= 0):
+        check_threshold(mc, g, model, T)
+    whole = mc.Model(model, engine=0, part_states=mc.NEVER_CUT)
+    assert whole.mc_min_time() == g.mc_min_time()
+    assert whole.last_stats["parts"] == len(model["params"])
+    g.close()
+    whole.close()
+
+
+@pytest.mark.parametrize("part_states", [1, 4096, 0])
+def test_matmul64_block_sizes(mc, part_states):
+    """The 5.15M-state workload at several block sizes (0 = automatic)."""
+    model = workloads.matmul_64()
+    s = cf.summary(model, with_E=False)
+    g = mc.Model(model, engine=0, part_states=part_states)
+    t_min, argmin = g.mc_min_time()
+    st = g.last_stats
+    _say(f"matmul64 part_states={part_states}: {st['parts']} partitions")
+    assert (t_min, argmin) == (s["t_min"], s["argmin"])
+    assert (st["states"], st["levels"]) == (s["reachable"], s["levels"])
+    assert g.mc_terminal_clocks() == s["tc"]
+    tr = g.mc_trace()
+    oracle.check_trace(model, tr, target_clock=s["t_min"], cfgs=s["argmin"])
+    assert g.mc_check(t_min - 1) == 0
+    assert g.last_stats["states"] == cf.count_le(model, t_min - 1)
+    g.close()
+
+
 def test_matmul128_vw_full_size(mc):
     """The large workload: closed forms (pinned to the oracle) give the counts, the
     per-configuration clocks and the argmin; the trace is replayed through the oracle."""
