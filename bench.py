@@ -52,17 +52,27 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
     t0 = time.perf_counter()
     g = mc.Model(model, engine=engine, block=block, workspace=workspace,
                  load_factor=load_factor)
+    t1 = time.perf_counter()
     t_min, argmin = g.mc_min_time()
     st_min = dict(g.last_stats)
+    t2 = time.perf_counter()
     trace = g.mc_trace()
+    t3 = time.perf_counter()
     holds = not g.mc_check(t_min - 1)
     st_chk = dict(g.last_stats)
     g.close()
-    dt = time.perf_counter() - t0
+    t4 = time.perf_counter()
     return {"t_min": t_min, "argmin": argmin, "trace_len": len(trace), "minimal": holds,
             "states": st_min["states"] + st_chk["states"], "min_states": st_min["states"],
             "engine_ns": st_min["engine_ns"] + st_chk["engine_ns"],
-            "engine_ns_min": st_min["engine_ns"], "seconds": dt, "levels": st_min["levels"]}
+            "engine_ns_min": st_min["engine_ns"], "seconds": t4 - t0, "levels": st_min["levels"],
+            "parts": st_min["parts"],
+            "breakdown_ms": {"load": 1e3 * (t1 - t0), "min_time": 1e3 * (t2 - t1),
+                             "min_time_engine": st_min["engine_ns"] / 1e6,
+                             "min_time_clear": st_min["clear_ns"] / 1e6,
+                             "trace": 1e3 * (t3 - t2), "check": 1e3 * (t4 - t3),
+                             "check_engine": st_chk["engine_ns"] / 1e6,
+                             "check_clear": st_chk["clear_ns"] / 1e6}}
 
 
 def cpu_baseline(model, t_min, budget_s: float = 30.0):
@@ -325,6 +335,9 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "tuning_queries_per_s": args.steps / elapsed,
+        "step_breakdown_ms": {k: sum(s["breakdown_ms"][k] for s in steps) / len(steps)
+                              for k in steps[0]["breakdown_ms"]},
+        "partitions": steps[0]["parts"],
         "latency_ms": {"p50": 1e3 * pct(0.5), "p99": 1e3 * pct(0.99)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -211,17 +211,10 @@ template <int W>
 __device__ __forceinline__ uint32_t* slot_parent(unsigned char* base, unsigned long long s) {
   return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W);
 }
-// publish word of a wide key: 0xFFFFFFFF until the claimer has written every key word
-template <int W>
-__device__ __forceinline__ uint32_t* slot_pub(unsigned char* base, unsigned long long s) {
-  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W + 4u);
-}
-constexpr uint32_t kPublished = 1u;
-// jump word: first predecessor of the lock-step run a state belongs to (else 0xFFFFFFFF);
-// one-word keys never publish, so they keep it in the publish word
+// jump word: first predecessor of the lock-step run a state belongs to (else 0xFFFFFFFF)
 template <int W>
 __device__ __forceinline__ uint32_t* slot_jump(unsigned char* base, unsigned long long s) {
-  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + (W == 1 ? 12u : 8u * W + 8u));
+  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W + 4u);
 }
 
 constexpr int kScopeWG = __HIP_MEMORY_SCOPE_WORKGROUP;
@@ -229,27 +222,40 @@ constexpr int kScopeAgent = __HIP_MEMORY_SCOPE_AGENT;
 
 enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 
-// Open addressing in windows of kWin consecutive slots; windows are visited in a
-// double-hashing sequence (odd step, so every window is reached).  A probe reads the
-// window's word 0 as hints (one round trip), then claims the first empty slot with a
-// 64-bit compare-and-swap on word 0 (a second round trip).  Hints can only be stale in
-// one direction (a slot never returns to empty within a query), and a failed CAS
-// returns the slot's actual word, so hints never cause a wrong verdict.
-// Wider keys are claimed on word 0; the winner then writes the other words and
-// publishes them (release) through the slot's publish word; a lane that finds its own
-// word 0 in a slot waits for the publish and compares the rest.  One slot is handled
-// per loop iteration and waiting never spins inside an iteration: every lane of the
-// wavefront runs the same loop, and a winner publishes in the iteration it won, so a
-// waiting lane cannot starve a winner of its own wavefront.  SCOPE is the widest set of
+// Open addressing in windows of consecutive slots that share one 64-byte line (4, 2 or
+// 1 slots for 1-, 2- and 4-word keys); windows are visited in a double-hashing sequence
+// (odd step, so every window is reached) and the slots of a window in order.  A key
+// first claims its home slot (slot 0 of its first window) with a 64-bit
+// compare-and-swap on word 0, without looking: most home slots are empty at the load
+// factors used, so most inserts take one round trip.  If that fails the window's word-0
+// low halves are read as hints (one round trip) and the first slot they show empty is
+// claimed the same way; later windows are read before they are claimed.  Hints can only
+// be stale in one direction (a slot never returns to empty within a query), and a
+// failed CAS returns the slot's actual word, so hints never cause a wrong verdict.
+// Wider keys are claimed on word 0; the winner then stores the other words.  No valid
+// key has a word equal to the all-ones of a cleared slot (the key layout keeps a zero
+// bit in every word), and every word is stored once, so a lane that finds its own word 0
+// in a slot waits until none of the other words reads all-ones and then compares them:
+// each word is read and written as an atomic at the insert's scope, which makes it
+// coherent by itself, and no release/acquire pair (on gfx950 an L2 writeback at agent
+// scope) is needed.  One slot is handled per loop iteration and waiting never spins
+// inside an iteration: every lane of the wavefront runs the same loop, and a winner
+// stores its words in the iteration it won, so a waiting lane cannot starve a winner of
+// its own wavefront.  SCOPE is the widest set of
 // threads that may insert the same key: the workgroup in the super-step engine (one
-// configuration's subgraph per workgroup, configuration index in word 0), the device
-// in the level engine.  Empty slots never precede a key in its probe sequence, so a
-// lookup stops at the first empty slot.
-constexpr int kWin = 4;
+// configuration's subgraph, or a block of its rounds, per workgroup; the configuration
+// index in word 0), the device in the level engine.  The slot claimed is always the
+// first empty one of the key's sequence, so a lookup stops at the first empty slot.
+template <int W>
+struct Win {
+  static constexpr int n = 64 / SlotBytes<W>::v;  // slots per window (one 64-byte line)
+};
+static_assert(Win<1>::n == 4 && Win<2>::n == 2 && Win<4>::n == 1, "window sizes");
 
+template <int W>
 __device__ __forceinline__ void probe_start(unsigned long long h, unsigned long long mask,
                                             unsigned long long& wi, unsigned long long& step) {
-  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  const unsigned long long nwin_mask = (mask + 1ull) / Win<W>::n - 1ull;
   wi = h & nwin_mask;
   step = ((h >> 33) | 1ull) & nwin_mask;
   step |= 1ull;
@@ -259,33 +265,40 @@ template <int W, int SCOPE>
 __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long long mask,
                                             const Key<W>& k, uint32_t& slot_out,
                                             uint32_t& probes) {
+  constexpr int KW = Win<W>::n;
   unsigned long long wi, step;
-  probe_start(key_hash<W>(k), mask, wi, step);
-  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  probe_start<W>(key_hash<W>(k), mask, wi, step);
+  const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   const unsigned long long max_iters =
       (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
-  unsigned long long h0 = 0, h1 = 0, h2 = 0, h3 = 0;  // window hints (word 0)
-  int j = kWin;  // slot within the window; kWin = load the next window
-  bool waiting = false;
+  unsigned long long hint[KW];  // window word 0s
+#pragma unroll
+  for (int q = 0; q < KW; ++q) hint[q] = kEmptyWord;  // the home slot is tried unread
+  int j = 0;  // slot within the window
+  bool loaded = false, need = false, waiting = false;
+  ++probes;
   for (unsigned long long it = 0; it < max_iters; ++it) {
-    if (j == kWin) {
+    if (need) {
       ++probes;
-      const unsigned long long s0 = wi * kWin;
-      h0 = __hip_atomic_load(slot_key<W>(base, s0 + 0), __ATOMIC_RELAXED, SCOPE);
-      h1 = __hip_atomic_load(slot_key<W>(base, s0 + 1), __ATOMIC_RELAXED, SCOPE);
-      h2 = __hip_atomic_load(slot_key<W>(base, s0 + 2), __ATOMIC_RELAXED, SCOPE);
-      h3 = __hip_atomic_load(slot_key<W>(base, s0 + 3), __ATOMIC_RELAXED, SCOPE);
-      j = 0;
+      const unsigned long long s0 = wi * KW;
+#pragma unroll
+      for (int q = 0; q < KW; ++q)
+        hint[q] = __hip_atomic_load(slot_key<W>(base, s0 + q), __ATOMIC_RELAXED, SCOPE);
+      loaded = true;
+      need = false;
     }
-    const unsigned long long s = wi * kWin + (unsigned long long)j;
+    const unsigned long long s = wi * KW + (unsigned long long)j;
     unsigned long long* p = slot_key<W>(base, s);
     bool advance = false;
     if (waiting) {
-      const uint32_t pub = __hip_atomic_load(slot_pub<W>(base, s), __ATOMIC_ACQUIRE, SCOPE);
-      if (pub == kPublished) {
-        bool eq = true;
+      bool ready = true, eq = true;
 #pragma unroll
-        for (int q = 1; q < W; ++q) eq &= __hip_atomic_load(p + q, __ATOMIC_RELAXED, SCOPE) == k.w[q];
+      for (int q = 1; q < W; ++q) {
+        const unsigned long long v = __hip_atomic_load(p + q, __ATOMIC_RELAXED, SCOPE);
+        ready &= v != kEmptyWord;
+        eq &= v == k.w[q];
+      }
+      if (ready) {
         if (eq) {
           slot_out = (uint32_t)s;
           return kInsDup;
@@ -294,19 +307,18 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
         advance = true;
       }
     } else {
-      unsigned long long v = j == 0 ? h0 : j == 1 ? h1 : j == 2 ? h2 : h3;
+      unsigned long long v = kEmptyWord;
+#pragma unroll
+      for (int q = 0; q < KW; ++q)
+        if (q == j) v = hint[q];
       if (v == kEmptyWord) {
         const unsigned long long old = atomicCAS(p, kEmptyWord, k.w[0]);
         if (old == kEmptyWord) {
-          if (W > 1) {
 #pragma unroll
-            for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, k.w[q], __ATOMIC_RELAXED, SCOPE);
-            __hip_atomic_store(slot_pub<W>(base, s), kPublished, __ATOMIC_RELEASE, SCOPE);
-          }
+          for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, k.w[q], __ATOMIC_RELAXED, SCOPE);
           slot_out = (uint32_t)s;
           return kInsNew;
         }
-        ++probes;
         v = old;
       }
       if (v == k.w[0]) {
@@ -321,7 +333,12 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
     }
     if (advance) {
       ++j;
-      if (j == kWin) wi = (wi + step) & nwin_mask;
+      if (j == KW) {
+        j = 0;
+        wi = (wi + step) & nwin_mask;
+        loaded = false;
+      }
+      if (!loaded) need = KW > 1;  // a one-slot window is claimed unread
     }
   }
   return kInsFail;
@@ -329,86 +346,98 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
 
 // N independent inserts per lane, stepped together so that their round trips overlap:
 // every iteration first issues the window loads of all keys that need one, then the
-// compare-and-swaps of all keys whose current slot looks empty, then the publish checks
-// of waiting keys, and only then looks at the results.  Same protocol and guarantees as
-// table_insert, one state machine per key.  A window hint is the low half of word 0:
-// the configuration field sits in the low bits and is never all-ones in a valid key, so
-// the low half alone tells an empty slot; a slot whose low half equals the key's is
-// resolved by the compare-and-swap's return value or the full compare.
+// compare-and-swaps of all keys whose current slot looks empty, then the reads of the
+// other words of the slots waited on, and only then looks at the results.  Same protocol, sequence and
+// guarantees as table_insert, one state machine per key.  A window hint is the low half
+// of word 0: the configuration field sits in the low bits and is never all-ones in a
+// valid key, so the low half alone tells an empty slot; a slot whose low half equals
+// the key's is resolved by the compare-and-swap's return value or the full compare.
 template <int W, int SCOPE, int N>
 __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned long long mask,
                                                const unsigned long long (&key)[N][W],
                                                const bool (&act)[N], uint32_t (&slot)[N],
                                                int (&res)[N], uint32_t& probes) {
-  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  constexpr int KW = Win<W>::n;
+  const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   const unsigned long long max_iters =
       (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
   constexpr uint32_t kLoEmpty = 0xFFFFFFFFu;
   unsigned long long wi[N], step[N], old[N];
-  uint32_t h[N][kWin];
+  uint32_t h[N][KW];
   int j[N];
-  bool waiting[N], done[N], cas[N];
-  uint32_t pub[N];
+  bool waiting[N], done[N], cas[N], loaded[N], need[N];
+  bool ready[N], eq[N];
 #pragma unroll
   for (int n = 0; n < N; ++n) {
     res[n] = kInsFail;
     slot[n] = kParentNone;
     done[n] = !act[n];
     waiting[n] = false;
-    j[n] = kWin;
+    loaded[n] = false;
+    need[n] = false;
+    j[n] = 0;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) h[n][q] = kLoEmpty;  // the home slot is tried unread
     wi[n] = step[n] = 0ull;
     if (act[n]) {
+      ++probes;
       Key<W> k;
 #pragma unroll
       for (int q = 0; q < W; ++q) k.w[q] = key[n][q];
-      probe_start(key_hash<W>(k), mask, wi[n], step[n]);
+      probe_start<W>(key_hash<W>(k), mask, wi[n], step[n]);
     }
   }
   for (unsigned long long it = 0; it < max_iters; ++it) {
     bool any = false;
 #pragma unroll
     for (int n = 0; n < N; ++n) {  // window loads
-      if (done[n] || j[n] != kWin) continue;
+      if (done[n] || !need[n]) continue;
       ++probes;
-      const unsigned long long s0 = wi[n] * kWin;
+      const unsigned long long s0 = wi[n] * KW;
 #pragma unroll
-      for (int q = 0; q < kWin; ++q)
+      for (int q = 0; q < KW; ++q)
         h[n][q] = __hip_atomic_load(reinterpret_cast<uint32_t*>(slot_key<W>(base, s0 + q)),
                                     __ATOMIC_RELAXED, SCOPE);
-      j[n] = 0;
+      loaded[n] = true;
+      need[n] = false;
     }
 #pragma unroll
     for (int n = 0; n < N; ++n) {  // claims
       cas[n] = false;
       if (done[n] || waiting[n]) continue;
-      const uint32_t v = j[n] == 0 ? h[n][0] : j[n] == 1 ? h[n][1] : j[n] == 2 ? h[n][2] : h[n][3];
+      uint32_t v = kLoEmpty;
+#pragma unroll
+      for (int q = 0; q < KW; ++q)
+        if (q == j[n]) v = h[n][q];
       if (v == kLoEmpty || v == (uint32_t)key[n][0]) {
         // empty: claim it; same low half: the CAS returns the slot's word 0 either way
         cas[n] = true;
-        old[n] = atomicCAS(slot_key<W>(base, wi[n] * kWin + (unsigned long long)j[n]), kEmptyWord,
+        old[n] = atomicCAS(slot_key<W>(base, wi[n] * KW + (unsigned long long)j[n]), kEmptyWord,
                            key[n][0]);
       }
     }
 #pragma unroll
-    for (int n = 0; n < N; ++n) {  // publish checks
+    for (int n = 0; n < N; ++n) {  // other words of the slots waited on
+      ready[n] = eq[n] = true;
       if (done[n] || !waiting[n]) continue;
-      pub[n] = __hip_atomic_load(slot_pub<W>(base, wi[n] * kWin + (unsigned long long)j[n]),
-                                 __ATOMIC_ACQUIRE, SCOPE);
+      const unsigned long long* p = slot_key<W>(base, wi[n] * KW + (unsigned long long)j[n]);
+#pragma unroll
+      for (int q = 1; q < W; ++q) {
+        const unsigned long long v = __hip_atomic_load(p + q, __ATOMIC_RELAXED, SCOPE);
+        ready[n] &= v != kEmptyWord;
+        eq[n] &= v == key[n][q];
+      }
     }
 #pragma unroll
     for (int n = 0; n < N; ++n) {  // results
       if (done[n]) continue;
       any = true;
-      const unsigned long long s = wi[n] * kWin + (unsigned long long)j[n];
+      const unsigned long long s = wi[n] * KW + (unsigned long long)j[n];
       unsigned long long* p = slot_key<W>(base, s);
       bool advance = false;
       if (waiting[n]) {
-        if (pub[n] == kPublished) {
-          bool eq = true;
-#pragma unroll
-          for (int q = 1; q < W; ++q)
-            eq &= __hip_atomic_load(p + q, __ATOMIC_RELAXED, SCOPE) == key[n][q];
-          if (eq) {
+        if (ready[n]) {
+          if (eq[n]) {
             slot[n] = (uint32_t)s;
             res[n] = kInsDup;
             done[n] = true;
@@ -419,18 +448,13 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
         }
       } else if (cas[n]) {
         if (old[n] == kEmptyWord) {
-          if (W > 1) {
 #pragma unroll
-            for (int q = 1; q < W; ++q)
-              __hip_atomic_store(p + q, key[n][q], __ATOMIC_RELAXED, SCOPE);
-            __hip_atomic_store(slot_pub<W>(base, s), kPublished, __ATOMIC_RELEASE, SCOPE);
-          }
+          for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, key[n][q], __ATOMIC_RELAXED, SCOPE);
           slot[n] = (uint32_t)s;
           res[n] = kInsNew;
           done[n] = true;
           continue;
         }
-        ++probes;
         if (old[n] == key[n][0]) {
           if (W == 1) {
             slot[n] = (uint32_t)s;
@@ -447,7 +471,12 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
       }
       if (advance) {
         ++j[n];
-        if (j[n] == kWin) wi[n] = (wi[n] + step[n]) & nwin_mask;
+        if (j[n] == KW) {
+          j[n] = 0;
+          wi[n] = (wi[n] + step[n]) & nwin_mask;
+          loaded[n] = false;
+        }
+        if (!loaded[n]) need[n] = KW > 1;  // a one-slot window is claimed unread
       }
     }
     if (!any) break;
@@ -458,12 +487,13 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
 template <int W>
 __device__ __forceinline__ uint32_t table_find(unsigned char* base, unsigned long long mask,
                                                const Key<W>& k) {
+  constexpr int KW = Win<W>::n;
   unsigned long long wi, step;
-  probe_start(key_hash<W>(k), mask, wi, step);
-  const unsigned long long nwin_mask = (mask + 1ull) / kWin - 1ull;
+  probe_start<W>(key_hash<W>(k), mask, wi, step);
+  const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   for (unsigned long long it = 0; it <= nwin_mask; ++it) {
-    for (int j = 0; j < kWin; ++j) {
-      const unsigned long long s = wi * kWin + (unsigned long long)j;
+    for (int j = 0; j < KW; ++j) {
+      const unsigned long long s = wi * KW + (unsigned long long)j;
       const unsigned long long* p = slot_key<W>(base, s);
       if (p[0] == kEmptyWord) return kParentNone;
       bool eq = true;

@@ -154,9 +154,12 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   for (uint32_t i = 0; i < m; ++i) widths[kFRem + i] = std::max<uint32_t>(1, bit_length(max_d));
   Layout L;
   std::memset(&L, 0, sizeof(L));
+  // every word after the first keeps its top bit clear, so that no valid key has a word
+  // equal to the all-ones of a cleared slot (word 0 cannot be: its configuration field
+  // is never all-ones); a reader of a wide key can then tell a word not yet written
   uint32_t word = 0, off = 0, used = 0;
   for (uint32_t f = 0; f < 3 + m; ++f) {
-    if (off + widths[f] > 64) {
+    if (off + widths[f] > (word == 0 ? 64u : 63u)) {
       ++word;
       off = 0;
     }
