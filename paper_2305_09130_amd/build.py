@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmctune.so")
-SOURCES = ["mc_model.cpp", "mc_kernels.hip", "mc_api.hip", "mc_batch.hip", "mc_engine.hip"]
+SOURCES = ["mc_model.cpp", "mc_host_pool.cpp", "mc_kernels.hip", "mc_api.hip", "mc_batch.hip", "mc_engine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/mctune.h"
+#include "mc_host_pool.h"
 #include "mc_launch.h"
 #include "mc_model.h"
 
@@ -138,6 +139,8 @@ struct mc_model {
   uint32_t n_parts = 0;
   ModelDev* dmd = nullptr;
   unsigned int* head = nullptr;
+  unsigned char* pin = nullptr;  // pooled pinned block: hctrl, hpoll, hmd, tc_host, uploads
+  size_t pin_bytes = 0;
   ModelDev* hmd = nullptr;  // pinned host staging of the device descriptor
   Seed* seeds = nullptr;
   unsigned char* front[2] = {nullptr, nullptr};
@@ -150,7 +153,8 @@ struct mc_model {
   int last = kQueryNone;
   uint32_t last_T = 0;
   int last_violated = 0;
-  std::vector<uint32_t> tc_host;
+  uint32_t* tc_host = nullptr;  // pinned, n_cfg entries
+  uint64_t q_slots = 0;          // visited-set slots of the last query (a prefix of the table)
   bool trace_ready = false;
   std::vector<uint32_t> trace_rows;
 };
@@ -163,7 +167,7 @@ QueryArgs make_args(mc_model* h, bool prune, uint32_t T) {
   q.tc = h->tc;
   q.cfgs = h->cfgs;
   q.table = h->table;
-  q.mask = h->plan.slots - 1;
+  q.mask = h->q_slots - 1;
   q.L = h->mh.layout;
   q.n_cfg = h->mh.n_cfg;
   q.prune = prune ? 1u : 0u;
@@ -222,10 +226,21 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
   hipStream_t s = h->stream;
   h->trace_ready = false;
   h->last = kQueryNone;
+  // a check(T) inserts only the states with clock <= T: its visited set is the prefix of
+  // the table sized for their number at the same load factor
+  uint64_t q_slots = h->plan.slots;
+  if (prune && !h->opts.log2_slots) {
+    const double lf =
+        (h->opts.load_factor > 0.f && h->opts.load_factor < 1.f) ? h->opts.load_factor : 0.5;
+    const uint64_t need = count_le_bound(h->mh, T);
+    q_slots = std::min<uint64_t>(
+        h->plan.slots, std::max<uint64_t>(1024, next_pow2((uint64_t)((double)need / lf) + 1)));
+  }
+  h->q_slots = q_slots;
   bool cleared = false;
   if (h->dirty) {
     HIPCHK(hipEventRecord(h->ev[0], s));
-    HIPCHK(launch_clear(s, h->table, h->plan.table_bytes));
+    HIPCHK(launch_clear(s, h->table, h->q_slots * h->plan.slot_bytes));
     HIPCHK(hipEventRecord(h->ev[1], s));
     cleared = true;
   }
@@ -239,7 +254,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     md.cfgs = h->cfgs;
     md.seeds = h->seeds;
     md.table = h->table;
-    md.mask = h->plan.slots - 1;
+    md.mask = h->q_slots - 1;
     md.L = h->mh.layout;
     md.n_cfg = h->mh.n_cfg;
     md.prune = prune ? 1u : 0u;
@@ -282,7 +297,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
   }
   HIPCHK(hipEventRecord(h->ev[3], s));
   HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(h->tc_host.data(), h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(h->tc_host, h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int derr = dev_error_code(h->hctrl->error);
   if (derr != MC_OK) return derr;
@@ -408,11 +423,8 @@ int mc_workspace_bytes(const mc_desc* d, const mc_opts* o, size_t* bytes) {
 
 int mc_model_free(mc_model* h) {
   if (!h) return MC_E_INVAL;
-  for (auto& e : h->ev)
-    if (e) (void)hipEventDestroy(e);
-  if (h->hctrl) (void)hipHostFree(h->hctrl);
-  if (h->hpoll) (void)hipHostFree(h->hpoll);
-  if (h->hmd) (void)hipHostFree(h->hmd);
+  for (auto& e : h->ev) event_put(e);
+  pinned_put(h->pin, h->pin_bytes);
   delete h;
   return MC_OK;
 }
@@ -453,30 +465,42 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     h->front[1] = h->ws + h->plan.front1;
     h->trace_buf = reinterpret_cast<unsigned long long*>(h->ws + h->plan.trace);
     h->table = h->ws + h->plan.table;
-    h->tc_host.assign(h->mh.n_cfg, kNoClock);
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->hctrl), sizeof(Ctrl), hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 64, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->hmd), sizeof(ModelDev), hipHostMallocDefault) !=
-            hipSuccess) {
-      (void)hipGetLastError();
+    h->q_slots = h->plan.slots;
+    const std::vector<Part> parts = model_parts(h->mh, h->opts);
+    h->n_parts = (uint32_t)parts.size();
+    // one pooled pinned block: counters, poll words, descriptor, clocks and, when small,
+    // the staging of the uploads below
+    static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "pinned block layout");
+    const size_t tc_off = 768, up_off = align_up(tc_off + 4ull * h->mh.n_cfg);
+    const size_t cfg_bytes = sizeof(CfgRec) * h->mh.n_cfg, part_bytes = sizeof(Part) * parts.size();
+    const bool stage = cfg_bytes + part_bytes <= (4u << 20);
+    h->pin_bytes = stage ? up_off + cfg_bytes + part_bytes : up_off;
+    h->pin = static_cast<unsigned char*>(pinned_get(h->pin_bytes));
+    bool ok = h->pin != nullptr;
+    for (auto& e : h->ev) {
+      e = event_get();
+      ok = ok && e != nullptr;
+    }
+    if (!ok) {
       mc_model_free(h);
       return MC_E_DEVICE;
     }
-    for (auto& e : h->ev) {
-      if (hipEventCreate(&e) != hipSuccess) {
-        (void)hipGetLastError();
-        mc_model_free(h);
-        return MC_E_DEVICE;
-      }
+    h->hctrl = reinterpret_cast<Ctrl*>(h->pin);
+    h->hpoll = reinterpret_cast<uint32_t*>(h->pin + 256);
+    h->hmd = reinterpret_cast<ModelDev*>(h->pin + 512);
+    h->tc_host = reinterpret_cast<uint32_t*>(h->pin + tc_off);
+    for (uint32_t c = 0; c < h->mh.n_cfg; ++c) h->tc_host[c] = kNoClock;
+    const void* up_cfg = h->mh.cfgs.data();
+    const void* up_part = parts.data();
+    if (stage) {
+      std::memcpy(h->pin + up_off, up_cfg, cfg_bytes);
+      std::memcpy(h->pin + up_off + cfg_bytes, up_part, part_bytes);
+      up_cfg = h->pin + up_off;
+      up_part = h->pin + up_off + cfg_bytes;
     }
-    const std::vector<Part> parts = model_parts(h->mh, h->opts);
-    h->n_parts = (uint32_t)parts.size();
     hipStream_t s = h->stream;
-    if (hipMemcpyAsync(h->cfgs, h->mh.cfgs.data(), sizeof(CfgRec) * h->mh.n_cfg,
-                       hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(h->parts, parts.data(), sizeof(Part) * parts.size(),
-                       hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (hipMemcpyAsync(h->cfgs, up_cfg, cfg_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->parts, up_part, part_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       (void)hipGetLastError();
       mc_model_free(h);
@@ -521,7 +545,7 @@ int mc_min_time(mc_model* h, uint32_t* t_min, uint32_t* argmin, size_t cap, size
     const int rc = run_query(h, false, 0, st);
     if (rc) return rc;
     uint32_t best = kNoClock;
-    for (uint32_t v : h->tc_host) best = std::min(best, v);
+    for (uint32_t c = 0; c < h->mh.n_cfg; ++c) best = std::min(best, h->tc_host[c]);
     if (best == kNoClock) return MC_E_STATE;
     size_t n = 0;
     for (uint32_t c = 0; c < h->mh.n_cfg; ++c) {
@@ -558,7 +582,7 @@ int mc_terminal_clocks(const mc_model* h, uint32_t* tc, size_t cap) {
   if (!h || !tc) return MC_E_INVAL;
   if (h->last == kQueryNone) return MC_E_STATE;
   if (cap < h->mh.n_cfg) return MC_E_BUFFER;
-  std::memcpy(tc, h->tc_host.data(), 4ull * h->mh.n_cfg);
+  std::memcpy(tc, h->tc_host, 4ull * h->mh.n_cfg);
   return MC_OK;
 }
 

@@ -224,14 +224,10 @@ enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 
 // Open addressing in windows of consecutive slots that share one 64-byte line (4, 2 or
 // 1 slots for 1-, 2- and 4-word keys); windows are visited in a double-hashing sequence
-// (odd step, so every window is reached) and the slots of a window in order.  A key
-// first claims its home slot (slot 0 of its first window) with a 64-bit
-// compare-and-swap on word 0, without looking: most home slots are empty at the load
-// factors used, so most inserts take one round trip.  If that fails the window's word-0
-// low halves are read as hints (one round trip) and the first slot they show empty is
-// claimed the same way; later windows are read before they are claimed.  Hints can only
-// be stale in one direction (a slot never returns to empty within a query), and a
-// failed CAS returns the slot's actual word, so hints never cause a wrong verdict.
+// (odd step, so every window is reached) and the slots of a window in order.  Every
+// probe is a 64-bit compare-and-swap of word 0 from empty to the key's word 0, issued
+// without reading the slot first: a probe of an empty slot claims it in one round trip,
+// and a failed one returns the slot's word 0, which is all a read would have told.
 // Wider keys are claimed on word 0; the winner then stores the other words.  No valid
 // key has a word equal to the all-ones of a cleared slot (the key layout keeps a zero
 // bit in every word), and every word is stored once, so a lane that finds its own word 0
@@ -241,11 +237,11 @@ enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 // scope) is needed.  One slot is handled per loop iteration and waiting never spins
 // inside an iteration: every lane of the wavefront runs the same loop, and a winner
 // stores its words in the iteration it won, so a waiting lane cannot starve a winner of
-// its own wavefront.  SCOPE is the widest set of
-// threads that may insert the same key: the workgroup in the super-step engine (one
-// configuration's subgraph, or a block of its rounds, per workgroup; the configuration
-// index in word 0), the device in the level engine.  The slot claimed is always the
-// first empty one of the key's sequence, so a lookup stops at the first empty slot.
+// its own wavefront.  SCOPE is the widest set of threads that may insert the same key:
+// the workgroup in the super-step engine (one configuration's subgraph, or a block of
+// its rounds, per workgroup; the configuration index in word 0), the device in the
+// level engine.  The slot claimed is always the first empty one of the key's sequence,
+// so a lookup stops at the first empty slot.
 template <int W>
 struct Win {
   static constexpr int n = 64 / SlotBytes<W>::v;  // slots per window (one 64-byte line)
@@ -271,22 +267,9 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
   const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   const unsigned long long max_iters =
       (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
-  unsigned long long hint[KW];  // window word 0s
-#pragma unroll
-  for (int q = 0; q < KW; ++q) hint[q] = kEmptyWord;  // the home slot is tried unread
   int j = 0;  // slot within the window
-  bool loaded = false, need = false, waiting = false;
-  ++probes;
+  bool waiting = false;
   for (unsigned long long it = 0; it < max_iters; ++it) {
-    if (need) {
-      ++probes;
-      const unsigned long long s0 = wi * KW;
-#pragma unroll
-      for (int q = 0; q < KW; ++q)
-        hint[q] = __hip_atomic_load(slot_key<W>(base, s0 + q), __ATOMIC_RELAXED, SCOPE);
-      loaded = true;
-      need = false;
-    }
     const unsigned long long s = wi * KW + (unsigned long long)j;
     unsigned long long* p = slot_key<W>(base, s);
     bool advance = false;
@@ -307,21 +290,15 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
         advance = true;
       }
     } else {
-      unsigned long long v = kEmptyWord;
+      ++probes;
+      const unsigned long long old = atomicCAS(p, kEmptyWord, k.w[0]);
+      if (old == kEmptyWord) {
 #pragma unroll
-      for (int q = 0; q < KW; ++q)
-        if (q == j) v = hint[q];
-      if (v == kEmptyWord) {
-        const unsigned long long old = atomicCAS(p, kEmptyWord, k.w[0]);
-        if (old == kEmptyWord) {
-#pragma unroll
-          for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, k.w[q], __ATOMIC_RELAXED, SCOPE);
-          slot_out = (uint32_t)s;
-          return kInsNew;
-        }
-        v = old;
+        for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, k.w[q], __ATOMIC_RELAXED, SCOPE);
+        slot_out = (uint32_t)s;
+        return kInsNew;
       }
-      if (v == k.w[0]) {
+      if (old == k.w[0]) {
         if (W == 1) {
           slot_out = (uint32_t)s;
           return kInsDup;
@@ -331,27 +308,18 @@ __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long l
         advance = true;
       }
     }
-    if (advance) {
-      ++j;
-      if (j == KW) {
-        j = 0;
-        wi = (wi + step) & nwin_mask;
-        loaded = false;
-      }
-      if (!loaded) need = KW > 1;  // a one-slot window is claimed unread
+    if (advance && ++j == KW) {
+      j = 0;
+      wi = (wi + step) & nwin_mask;
     }
   }
   return kInsFail;
 }
 
 // N independent inserts per lane, stepped together so that their round trips overlap:
-// every iteration first issues the window loads of all keys that need one, then the
-// compare-and-swaps of all keys whose current slot looks empty, then the reads of the
-// other words of the slots waited on, and only then looks at the results.  Same protocol, sequence and
-// guarantees as table_insert, one state machine per key.  A window hint is the low half
-// of word 0: the configuration field sits in the low bits and is never all-ones in a
-// valid key, so the low half alone tells an empty slot; a slot whose low half equals
-// the key's is resolved by the compare-and-swap's return value or the full compare.
+// every iteration first issues the compare-and-swaps of all keys not waiting, then the
+// reads of the other words of the slots waited on, and only then looks at the results.
+// Same protocol, sequence and guarantees as table_insert, one state machine per key.
 template <int W, int SCOPE, int N>
 __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned long long mask,
                                                const unsigned long long (&key)[N][W],
@@ -361,26 +329,18 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
   const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   const unsigned long long max_iters =
       (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
-  constexpr uint32_t kLoEmpty = 0xFFFFFFFFu;
   unsigned long long wi[N], step[N], old[N];
-  uint32_t h[N][KW];
   int j[N];
-  bool waiting[N], done[N], cas[N], loaded[N], need[N];
-  bool ready[N], eq[N];
+  bool waiting[N], done[N], ready[N], eq[N];
 #pragma unroll
   for (int n = 0; n < N; ++n) {
     res[n] = kInsFail;
     slot[n] = kParentNone;
     done[n] = !act[n];
     waiting[n] = false;
-    loaded[n] = false;
-    need[n] = false;
     j[n] = 0;
-#pragma unroll
-    for (int q = 0; q < KW; ++q) h[n][q] = kLoEmpty;  // the home slot is tried unread
     wi[n] = step[n] = 0ull;
     if (act[n]) {
-      ++probes;
       Key<W> k;
 #pragma unroll
       for (int q = 0; q < W; ++q) k.w[q] = key[n][q];
@@ -390,31 +350,11 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
   for (unsigned long long it = 0; it < max_iters; ++it) {
     bool any = false;
 #pragma unroll
-    for (int n = 0; n < N; ++n) {  // window loads
-      if (done[n] || !need[n]) continue;
-      ++probes;
-      const unsigned long long s0 = wi[n] * KW;
-#pragma unroll
-      for (int q = 0; q < KW; ++q)
-        h[n][q] = __hip_atomic_load(reinterpret_cast<uint32_t*>(slot_key<W>(base, s0 + q)),
-                                    __ATOMIC_RELAXED, SCOPE);
-      loaded[n] = true;
-      need[n] = false;
-    }
-#pragma unroll
     for (int n = 0; n < N; ++n) {  // claims
-      cas[n] = false;
       if (done[n] || waiting[n]) continue;
-      uint32_t v = kLoEmpty;
-#pragma unroll
-      for (int q = 0; q < KW; ++q)
-        if (q == j[n]) v = h[n][q];
-      if (v == kLoEmpty || v == (uint32_t)key[n][0]) {
-        // empty: claim it; same low half: the CAS returns the slot's word 0 either way
-        cas[n] = true;
-        old[n] = atomicCAS(slot_key<W>(base, wi[n] * KW + (unsigned long long)j[n]), kEmptyWord,
-                           key[n][0]);
-      }
+      ++probes;
+      old[n] = atomicCAS(slot_key<W>(base, wi[n] * KW + (unsigned long long)j[n]), kEmptyWord,
+                         key[n][0]);
     }
 #pragma unroll
     for (int n = 0; n < N; ++n) {  // other words of the slots waited on
@@ -433,7 +373,6 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
       if (done[n]) continue;
       any = true;
       const unsigned long long s = wi[n] * KW + (unsigned long long)j[n];
-      unsigned long long* p = slot_key<W>(base, s);
       bool advance = false;
       if (waiting[n]) {
         if (ready[n]) {
@@ -446,37 +385,28 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
           waiting[n] = false;
           advance = true;
         }
-      } else if (cas[n]) {
-        if (old[n] == kEmptyWord) {
+      } else if (old[n] == kEmptyWord) {
+        unsigned long long* p = slot_key<W>(base, s);
 #pragma unroll
-          for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, key[n][q], __ATOMIC_RELAXED, SCOPE);
+        for (int q = 1; q < W; ++q) __hip_atomic_store(p + q, key[n][q], __ATOMIC_RELAXED, SCOPE);
+        slot[n] = (uint32_t)s;
+        res[n] = kInsNew;
+        done[n] = true;
+        continue;
+      } else if (old[n] == key[n][0]) {
+        if (W == 1) {
           slot[n] = (uint32_t)s;
-          res[n] = kInsNew;
+          res[n] = kInsDup;
           done[n] = true;
           continue;
         }
-        if (old[n] == key[n][0]) {
-          if (W == 1) {
-            slot[n] = (uint32_t)s;
-            res[n] = kInsDup;
-            done[n] = true;
-            continue;
-          }
-          waiting[n] = true;
-        } else {
-          advance = true;
-        }
+        waiting[n] = true;
       } else {
-        advance = true;  // another key's slot
+        advance = true;
       }
-      if (advance) {
-        ++j[n];
-        if (j[n] == KW) {
-          j[n] = 0;
-          wi[n] = (wi[n] + step[n]) & nwin_mask;
-          loaded[n] = false;
-        }
-        if (!loaded[n]) need[n] = KW > 1;  // a one-slot window is claimed unread
+      if (advance && ++j[n] == KW) {
+        j[n] = 0;
+        wi[n] = (wi[n] + step[n]) & nwin_mask;
       }
     }
     if (!any) break;

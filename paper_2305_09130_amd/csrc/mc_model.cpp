@@ -200,7 +200,43 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
 }
 
 uint64_t auto_part_states(uint64_t states) {
-  return std::max<uint64_t>(1ull << 14, states / 1024);
+  // about 256 partitions for small models (down to blocks of kMinBlockRounds rounds),
+  // blocks of at most 2^14 states for large ones
+  return std::min<uint64_t>(1ull << 14, std::max<uint64_t>(1, states / 256));
+}
+
+// operation ends of one workgroup at or before time x
+static uint64_t ends_le(const CfgRec& r, uint64_t x) {
+  uint64_t c = 0;
+  for (uint32_t j = 0; j < r.nph; ++j)
+    if (x >= (uint64_t)r.t0[j] + r.lat[j])
+      c += std::min<uint64_t>(r.cnt[j], (x - r.t0[j]) / r.lat[j]);
+  return c;
+}
+
+uint64_t count_le_bound(const ModelHost& h, uint64_t T) {
+  const uint32_t m = h.m;
+  const uint64_t closure = (1ull << m) - 1;
+  uint64_t total = 1;  // the root
+  for (uint32_t c = 0; c < h.n_cfg; ++c) {
+    const CfgRec& r = h.cfgs[c];
+    if (T >= r.tc) {
+      total += h.cfg_states[c];
+      continue;
+    }
+    const uint64_t q = r.n / m, p = r.n % m;
+    const uint64_t full = std::min<uint64_t>(q, T / r.d);  // rounds ended by T
+    uint64_t cnt = 1 + full * (closure + r.b);             // SELECT state, whole rounds
+    const uint64_t x = T - full * r.d;                     // time into the next round
+    if (full < q) {
+      cnt += closure + ends_le(r, x);
+    } else if (p) {
+      for (uint32_t j = 1; j <= p; ++j) cnt += binom(m, j);
+      cnt += binom(m, (uint32_t)p) * ends_le(r, x);
+    }
+    total += std::min<uint64_t>(cnt, h.cfg_states[c]);
+  }
+  return total;
 }
 
 }  // namespace mc

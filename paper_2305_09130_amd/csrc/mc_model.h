@@ -90,6 +90,11 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
 // Default target states per partition for a launch exploring `states` states in total.
 uint64_t auto_part_states(uint64_t states);
 
+// An upper bound (exact for every configuration whose last round is not partial) on the
+// number of states with clock <= T, root included: what a check(T) inserts.  Sizes its
+// visited set only.
+uint64_t count_le_bound(const ModelHost& h, uint64_t T);
+
 uint64_t binom(uint32_t n, uint32_t k);
 uint32_t bit_length(uint64_t x);
 
