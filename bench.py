@@ -27,6 +27,10 @@ LINE_BYTES = 64          # HBM access granule assumed per random visited-set tou
 ALGO_BYTES_PER_STATE = 2 * LINE_BYTES   # one slot line read for the claim, one written
 
 
+def _progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("mc_kernels.hip", "mc_device.h", "mc_launch.h"):
@@ -103,6 +107,7 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
     need = mc.mc_batch_workspace_bytes(models, mc.make_batch_opts(load_factor=0.25))
     ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
     t0 = time.perf_counter()
+    _progress(f"autotuning the batch of {n_inst} ({len(models)} drawn, {rejected} redrawn)")
     best, best_ms = mc.mc_batch_autotune(models, ws)
     tune_s = time.perf_counter() - t0
     best.use_graph = 1
@@ -175,6 +180,7 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
         return xs[min(len(xs) - 1, int(p * len(xs)))]
 
     for f in qps_factors:
+        _progress(f"served run at {f}x the FIFO capacity")
         qps = f * fifo_capacity
         arr = workloads.poisson_arrivals(4, n_queries, qps)
         # FIFO one at a time: exact single-server simulation from measured service times
@@ -287,6 +293,7 @@ def main():
     traffic = read_traffic(args.workload, "k_superstep", src_hash)
 
     legs = set(x for x in args.legs.split(",") if x)
+    _progress(f"timed step done: {1e3 * elapsed / args.steps:.3f} ms/step")
     plain = None
     if args.plain_steps > 0 and "plain" in legs:
         ps = [run_step(mc, model, mc.MC_ENGINE_LEVEL, workspace, args.block, args.load_factor)
@@ -300,13 +307,16 @@ def main():
                  "speedup": (states / elapsed) / (p_states / p_time)}
         assert all(s["t_min"] == steps[0]["t_min"] for s in ps)
 
+    _progress("plain BFS leg done" if plain else "plain BFS leg skipped")
     cpu = None
     if not args.no_cpu and "cpu" in legs:
         cpu = cpu_baseline(model, steps[0]["t_min"])
     batched = served = None
     if "batch" in legs:
+        _progress("cpu leg done; batched leg")
         batched = batched_leg(mc, torch, workloads, args.batch_instances, 5, 16)
     if "serve" in legs:
+        _progress("batched leg done; served leg")
         served = served_leg(mc, torch, workloads, args.serve_queries, (0.5, 1.0, 2.0))
 
     cfg = {"workload": args.workload, "kind": model["kind"], "cu": model["m"],
