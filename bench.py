@@ -196,7 +196,8 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
         tickets = []
         t0 = time.perf_counter()
         nxt = 0
-        while nxt < n_queries or any(e.mc_engine_poll(t) is None for t in tickets[-64:]):
+        busy = True
+        while nxt < n_queries or busy:
             now = time.perf_counter() - t0
             while nxt < n_queries and arr[nxt] <= now:
                 i, kind, T = qs[nxt]
@@ -205,7 +206,8 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
                     T))
                 nxt += 1
             a_, w_ = e.mc_engine_step()
-            if a_ == 0 and w_ == 0 and nxt < n_queries:
+            busy = a_ + w_ > 0
+            if not busy and nxt < n_queries:
                 time.sleep(max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.001)))
         e.drain()
         wall = time.perf_counter() - t0

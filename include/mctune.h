@@ -257,8 +257,8 @@ int mc_batch_autotune(const mc_desc *models, uint32_t n, void *dev_ws, size_t ws
  *   1. admits waiting queries in arrival order while their footprint (visited set,
  *      tables, saved frontiers) fits the engine's arena and a model slot is free;
  *   2. runs one persistent launch over the unfinished partitions of every active
- *      query, where a partition explores at most `slice` super-step levels, then saves
- *      its frontier and yields;
+ *      query; while queries wait for admission, a partition explores at most `slice`
+ *      super-step levels, then saves its frontier and yields;
  *   3. retires the queries whose partitions are all explored, freeing their memory.
  * Queries admitted later therefore share the device with queries already running.
  * Every query owns its visited set, so its result is the same alone and in the mix. */
@@ -271,13 +271,19 @@ typedef struct mc_engine_opts {
     uint32_t max_active;     /* model slots: queries on the device at once (>= 1) */
     uint32_t max_cfg;        /* largest configuration count a query may have (>= 1) */
     uint32_t block;          /* threads per workgroup: 256, 512, 1024 (0 = 512) */
-    uint32_t slice;          /* super-step levels per partition per step (0 = no limit) */
+    uint32_t slice;          /* super-step levels per partition per step while queries
+                                wait for admission (0 = no limit); with none waiting a
+                                step runs its partitions to the end */
     uint32_t chunk;          /* states per super-step batch (0 = 2 x block x lane_items) */
     uint32_t grid;           /* persistent workgroups per step (0 = up to 1024) */
     float load_factor;       /* visited-set load factor (0 = 0.5) */
     uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
                                 (any other value = 2) */
-    uint32_t reserved[4];
+    uint32_t part_states;    /* target states per partition when a query's configurations
+                                are cut into blocks of whole rounds (0 = automatic: about
+                                states/256, at most 256 more partitions than
+                                configurations; UINT32_MAX = never cut) */
+    uint32_t reserved[3];
 } mc_engine_opts;
 
 typedef struct mc_query_result {

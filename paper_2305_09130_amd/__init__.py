@@ -87,7 +87,7 @@ class McEngineOpts(ctypes.Structure):
                 ("block", ctypes.c_uint32), ("slice", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("load_factor", ctypes.c_float), ("lane_items", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("part_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class McQueryResult(ctypes.Structure):
@@ -423,12 +423,12 @@ class Engine:
     def __init__(self, arena_bytes: int, max_active: int = 64, max_cfg: int = 512,
                  block: int = 512, slice: int = 16, chunk: int = 0, grid: int = 0,
                  load_factor: float = 0.5, device: str = "cuda:0", stream=None,
-                 lane_items: int = 0):
+                 lane_items: int = 0, part_states: int = 0):
         import torch
         o = McEngineOpts()
         o.max_active, o.max_cfg, o.block, o.slice = max_active, max_cfg, block, slice
         o.chunk, o.grid, o.load_factor = chunk, grid, load_factor
-        o.lane_items = lane_items
+        o.lane_items, o.part_states = lane_items, part_states
         self._o = o
         n = ctypes.c_size_t()
         _check("mc_engine_bytes", _lib.mc_engine_bytes(ctypes.byref(o), arena_bytes,

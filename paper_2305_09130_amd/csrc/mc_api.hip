@@ -98,7 +98,7 @@ std::vector<Part> model_parts(const ModelHost& mh, const mc_opts& o) {
                    [](const PartPlan& a, const PartPlan& b) { return a.states > b.states; });
   std::vector<Part> parts(plan.size());
   for (size_t i = 0; i < plan.size(); ++i)
-    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1};
+    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1, (uint32_t)i, {0u, 0u, 0u}};
   return parts;
 }
 
@@ -260,6 +260,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     md.prune = prune ? 1u : 0u;
     md.T = T;
     md.max_clock = h->mh.max_clock;
+    md.n_parts = h->n_parts;
     md.pstate = nullptr;
     HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
     HIPCHK(launch_reset_models(s, h->dmd, 1, h->head, 1));

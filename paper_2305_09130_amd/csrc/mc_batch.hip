@@ -313,9 +313,11 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
       d.n_cfg = m.n_cfg;
       d.max_clock = m.max_clock;
     }
+    for (const BPart& q : ps) ++md[q.model].n_parts;
     std::vector<Part> parts(ps.size());
+    std::vector<uint32_t> pidx(n, 0u);  // partitions of each model so far
     for (size_t k = 0; k < ps.size(); ++k) {
-      parts[k] = Part{ps[k].model, ps[k].cfg, ps[k].r0, ps[k].r1};
+      parts[k] = Part{ps[k].model, ps[k].cfg, ps[k].r0, ps[k].r1, pidx[ps[k].model]++, {0u, 0u, 0u}};
       ++b->group_n[width_group(b->ms[ps[k].model].W)];
     }
     b->group_off[0] = 0;

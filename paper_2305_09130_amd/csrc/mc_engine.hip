@@ -103,15 +103,21 @@ struct Query {
   size_t off = 0, bytes = 0;  // arena region
   size_t cfg_off = 0, seed_off = 0, pstate_off = 0, table_off = 0;
   uint64_t slots = 0;
+  std::vector<PartPlan> parts;  // configurations cut into blocks of whole rounds
   int slot_idx = -1;  // model slot
   uint64_t submit_ns = 0, admit_ns = 0, done_ns = 0;
   uint32_t steps = 0;
   mc_query_result res{};
 };
 
-size_t footprint(const ModelHost& mh, float lf, uint64_t* slots, size_t* cfg_off, size_t* seed_off,
-                 size_t* pstate_off, size_t* table_off) {
-  uint64_t s = next_pow2((uint64_t)((double)mh.states / lf) + 1);
+// Arena bytes of a query: tables, one PartState per partition and a visited set sized for
+// the states it can insert (all of them for min_time, those with clock <= T for check).
+// a query's configurations are cut into at most this many more partitions
+constexpr size_t kExtraParts = 256;
+
+size_t footprint(const ModelHost& mh, uint64_t states, size_t n_parts, float lf, uint64_t* slots,
+                 size_t* cfg_off, size_t* seed_off, size_t* pstate_off, size_t* table_off) {
+  uint64_t s = next_pow2((uint64_t)((double)states / lf) + 1);
   s = std::max<uint64_t>(s, 1024);
   size_t off = 0;
   *cfg_off = off;
@@ -119,7 +125,7 @@ size_t footprint(const ModelHost& mh, float lf, uint64_t* slots, size_t* cfg_off
   *seed_off = off;
   off = align_up(off + sizeof(Seed) * mh.n_cfg);
   *pstate_off = off;
-  off = align_up(off + sizeof(PartState) * mh.n_cfg);
+  off = align_up(off + sizeof(PartState) * n_parts);
   *table_off = off;
   off = align_up(off + s * slot_bytes_for(mh.W));
   *slots = s;
@@ -178,6 +184,7 @@ ModelDev make_dev(mc_engine* e, Query* q) {
   d.prune = q->kind == MC_QUERY_CHECK ? 1u : 0u;
   d.T = q->T;
   d.max_clock = q->mh.max_clock;
+  d.n_parts = (uint32_t)q->parts.size();
   d.pstate = reinterpret_cast<PartState*>(r + q->pstate_off);
   return d;
 }
@@ -205,7 +212,7 @@ int mc_engine_bytes(const mc_engine_opts* o, size_t arena_bytes, size_t* bytes) 
   off = align_up(off + 4ull * o->max_cfg * o->max_active);
   off = align_up(off + sizeof(ModelDev) * o->max_active);
   off = align_up(off + sizeof(ModelDev) * o->max_active);
-  const size_t maxparts = (size_t)o->max_cfg * o->max_active;
+  const size_t maxparts = ((size_t)o->max_cfg + kExtraParts) * o->max_active;
   off = align_up(off + sizeof(Part) * maxparts);
   off = align_up(off + sizeof(Part) * maxparts);
   off = align_up(off + 4);
@@ -230,7 +237,7 @@ int mc_engine_create(const mc_engine_opts* o, void* dev_buf, size_t buf_bytes, v
     e->base = reinterpret_cast<unsigned char*>(dev_buf);
     e->bytes = buf_bytes;
     const uint32_t A = e->opts.max_active;
-    const size_t maxparts = (size_t)e->opts.max_cfg * A;
+    const size_t maxparts = ((size_t)e->opts.max_cfg + kExtraParts) * A;
     size_t off = 0;
     e->ctrl_off = off;
     off = align_up(off + kCtrlStride * A);
@@ -302,8 +309,21 @@ int mc_engine_submit(mc_engine* e, const mc_desc* model, uint32_t kind, uint32_t
     }
     q->kind = kind;
     q->T = T;
-    q->bytes = footprint(q->mh, e->opts.load_factor, &q->slots, &q->cfg_off, &q->seed_off,
-                         &q->pstate_off, &q->table_off);
+    // blocks of about states/256 (at most kExtraParts more partitions than
+    // configurations), whole configurations if that bound is still exceeded
+    const uint32_t ps = e->opts.part_states;
+    plan_parts(q->mh,
+               ps == 0xFFFFFFFFu ? 0u : ps ? ps : std::max<uint64_t>(1, q->mh.states / kExtraParts),
+               &q->parts);
+    if (q->parts.size() > (size_t)q->mh.n_cfg + kExtraParts) {
+      q->parts.clear();
+      plan_parts(q->mh, 0, &q->parts);
+    }
+    std::stable_sort(q->parts.begin(), q->parts.end(),
+                     [](const PartPlan& a, const PartPlan& b) { return a.states > b.states; });
+    const uint64_t need = kind == MC_QUERY_CHECK ? count_le_bound(q->mh, T) : q->mh.states;
+    q->bytes = footprint(q->mh, need, q->parts.size(), e->opts.load_factor, &q->slots,
+                         &q->cfg_off, &q->seed_off, &q->pstate_off, &q->table_off);
     q->ticket = e->next_ticket++;
     q->submit_ns = now_ns();
     q->res.kind = kind;
@@ -369,20 +389,26 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
     HIPCHK(launch_reset_models(s, stage, (uint32_t)admitted.size(), nullptr, 0));
     HIPCHK(launch_seed_models(s, stage, (uint32_t)admitted.size()));
     // new partitions, largest first within each query
-    for (Query* q : admitted) {
-      std::vector<uint32_t> order(q->mh.n_cfg);
-      std::iota(order.begin(), order.end(), 0u);
-      std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        return q->mh.cfg_states[a] > q->mh.cfg_states[b];
-      });
-      for (uint32_t c : order) e->pending_parts.push_back(Part{(uint32_t)q->slot_idx, c, 0u, kRoundsToEnd});
-    }
+    for (Query* q : admitted)
+      for (size_t k = 0; k < q->parts.size(); ++k) {
+        const PartPlan& pp = q->parts[k];
+        e->pending_parts.push_back(
+            Part{(uint32_t)q->slot_idx, pp.cfg, pp.r0, pp.r1, (uint32_t)k, {0u, 0u, 0u}});
+      }
     // the host must not overwrite the pinned staging before the copy ran
     HIPCHK(hipStreamSynchronize(s));
   }
   // ---- one persistent launch over every unfinished partition ----
   bool any_active = false;
-  for (Query* q : e->slots) any_active |= q != nullptr;
+  uint32_t hi = 0;  // one past the highest slot in use
+  for (size_t i = 0; i < e->slots.size(); ++i)
+    if (e->slots[i]) {
+      any_active = true;
+      hi = (uint32_t)i + 1u;
+    }
+  // partitions are cut into slices only while queries wait for admission: otherwise the
+  // launch runs everything admitted to the end, with no host round trip per slice
+  const uint32_t slice = e->waiting.empty() ? 0u : e->opts.slice;
   if (any_active && !e->pending_parts.empty()) {
     const int cur = e->cur;
     Part* parts = reinterpret_cast<Part*>(e->base + e->parts_off[cur]);
@@ -415,7 +441,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       pq[g].n_parts = gn[g];
       pq[g].batch_items = e->opts.chunk ? e->opts.chunk : 2u * li * e->opts.block;
       pq[g].head = head + g;
-      pq[g].slice = e->opts.slice;
+      pq[g].slice = slice;
       pq[g].pad = 0;
       pq[g].yielded = next;
       pq[g].n_yielded = ny;
@@ -424,11 +450,10 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
     }
     HIPCHK(launch_super_fork(s, e->fork, pq, grid, e->opts.block, li));
     ++e->launches;
-    const uint32_t A = e->opts.max_active;
     HIPCHK(hipMemcpyAsync(e->hny, ny, 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(e->hctrl, e->base + e->ctrl_off, kCtrlStride * A, hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(e->hctrl, e->base + e->ctrl_off, kCtrlStride * hi, hipMemcpyDeviceToHost,
                           s));
-    HIPCHK(hipMemcpyAsync(e->htc, e->base + e->tc_off, 4ull * e->opts.max_cfg * A,
+    HIPCHK(hipMemcpyAsync(e->htc, e->base + e->tc_off, 4ull * e->opts.max_cfg * hi,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (Query* q : e->slots)
@@ -445,7 +470,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       if (!q) continue;
       const Ctrl* c = reinterpret_cast<const Ctrl*>(e->hctrl + kCtrlStride * i);
       const bool failed = c->error != 0u;
-      if (c->parts_done < q->mh.n_cfg && !failed) continue;
+      if (c->parts_done < q->parts.size() && !failed) continue;
       const uint32_t* tc = e->htc + (size_t)e->opts.max_cfg * i;
       mc_query_result& r = q->res;
       r.status = dev_error_code(c->error);

@@ -452,7 +452,6 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
   const int m = L.m;
   const uint32_t tid = threadIdx.x;
   const uint32_t c = pt.cfg;
-  const bool whole = pt.r0 == 0u && pt.r1 == kRoundsToEnd;
   const CfgRec r = md.cfgs[c];
   const bool e_lds = r.b <= (uint32_t)kEMax;
   if (e_lds)
@@ -461,21 +460,33 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     sh.has_stop = 0u;
     sh.handed = 0u;
     sh.stop_item = kNoItem;
-    if (whole && md.pstate && md.pstate[c].status == 1u) {  // resume a partition that yielded
-      const PartState ps = md.pstate[c];
+    const Seed sd = md.seeds[c];
+    const uint32_t round_dep = (uint32_t)m + r.b;  // m dispatches, b advances
+    if (pt.r1 != kRoundsToEnd) {
+      unsigned long long k1[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) k1[w] = sd.k[w];
+      field_add<W>(k1, L, kFClock, (unsigned long long)pt.r1 * r.d);
+      field_add<W>(k1, L, kFPending, (unsigned long long)(-(long long)pt.r1 * m));
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sh.stopkey[w] = w < W ? k1[w] : 0ull;
+      sh.stop_clock = pt.r1 * r.d;
+      sh.stop_dep = sd.depth + pt.r1 * round_dep;
+      sh.has_stop = 1u;
+    }
+    if (md.pstate && md.pstate[pt.pidx].status == 1u) {  // resume a partition that yielded
+      const PartState ps = md.pstate[pt.pidx];
 #pragma unroll
       for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = ps.k[w];
       sh.fslot[0][0] = ps.slot;
       sh.fdep[0][0] = ps.depth;
       sh.fcount[0] = 1u;
     } else {
-      const Seed sd = md.seeds[c];
       unsigned long long k0[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) k0[w] = sd.k[w];
       uint32_t slot0 = sd.slot, dep0 = sd.depth;
       sh.fcount[0] = sd.slot == kParentNone ? 0u : 1u;
-      const uint32_t round_dep = (uint32_t)m + r.b;  // m dispatches, b advances
       if (pt.r0 != 0u && sh.fcount[0]) {
         // B_r0: r0 full rounds after the configuration's SELECT state
         field_add<W>(k0, L, kFClock, (unsigned long long)pt.r0 * r.d);
@@ -497,18 +508,6 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           }
         }
       }
-      if (pt.r1 != kRoundsToEnd) {
-        unsigned long long k1[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) k1[w] = sd.k[w];
-        field_add<W>(k1, L, kFClock, (unsigned long long)pt.r1 * r.d);
-        field_add<W>(k1, L, kFPending, (unsigned long long)(-(long long)pt.r1 * m));
-#pragma unroll
-        for (int w = 0; w < 4; ++w) sh.stopkey[w] = w < W ? k1[w] : 0ull;
-        sh.stop_clock = pt.r1 * r.d;
-        sh.stop_dep = sd.depth + pt.r1 * round_dep;
-        sh.has_stop = 1u;
-      }
 #pragma unroll
       for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = w < W ? k0[w] : 0ull;
       sh.fslot[0][0] = slot0;
@@ -521,7 +520,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
   uint32_t levels = 0;
   bool yielded = false;
   while (sh.fcount[cur] > 0u && !sh.stop) {
-    if (slice && whole && md.pstate && levels >= slice && sh.fcount[cur] == 1u) {
+    if (slice && md.pstate && levels >= slice && sh.fcount[cur] == 1u) {
       // out of budget for this launch: save the single frontier state and yield
       if (tid == 0) {
         PartState ps;
@@ -531,7 +530,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         ps.depth = sh.fdep[cur][0];
         ps.status = 1u;
         ps.pad = 0u;
-        md.pstate[c] = ps;
+        md.pstate[pt.pidx] = ps;
         const uint32_t pos = atomicAdd(pq.n_yielded, 1u);
         pq.yielded[pos] = pt;
       }
@@ -858,7 +857,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     if (sh.has_stop && !sh.handed && !sh.stop && !(md.prune && sh.stop_clock > md.T) &&
         __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) == 0u)
       set_error(md.ctrl, kDevErrSplit);
-    if (whole && md.pstate) md.pstate[c].status = 2u;
+    if (md.pstate) md.pstate[pt.pidx].status = 2u;
     atomicAdd(&md.ctrl->parts_done, 1u);
   }
   flush_tally(md, tl);
@@ -963,7 +962,7 @@ __global__ void k_reset_models(const ModelDev* models, unsigned int* head, uint3
   for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) cw[i] = 0u;
   for (uint32_t i = threadIdx.x; i < md.n_cfg; i += blockDim.x) md.tc[i] = kNoClock;
   if (md.pstate)
-    for (uint32_t i = threadIdx.x; i < md.n_cfg; i += blockDim.x) md.pstate[i].status = 0u;
+    for (uint32_t i = threadIdx.x; i < md.n_parts; i += blockDim.x) md.pstate[i].status = 0u;
   if (blockIdx.x == 0 && head)
     for (uint32_t i = threadIdx.x; i < n_heads; i += blockDim.x) head[i] = 0u;
 }

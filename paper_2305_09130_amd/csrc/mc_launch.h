@@ -61,8 +61,9 @@ struct ModelDev {
   uint32_t prune;
   uint32_t T;
   uint32_t max_clock;
-  uint32_t pad[2];
-  PartState* pstate;  // n_cfg entries when partitions may yield, else null
+  uint32_t n_parts;   // partitions of the model (entries of pstate)
+  uint32_t pad;
+  PartState* pstate;  // one per partition when partitions may yield, else null
   unsigned long long pad2;
 };
 
@@ -72,8 +73,10 @@ struct ModelDev {
 // block of whole rounds can be explored from that state on its own.
 struct Part {
   uint32_t model, cfg, r0, r1;
+  uint32_t pidx;  // index of the partition within its model (its PartState)
+  uint32_t pad[3];
 };
-static_assert(sizeof(Part) == 16, "Part layout");
+static_assert(sizeof(Part) == 32, "Part layout");
 
 // Partitions of a persistent launch, largest first.
 struct PartQueue {

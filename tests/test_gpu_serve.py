@@ -77,11 +77,15 @@ def _check(pool, qs, res):
         assert got == exp, (k, q, workloads.describe(pool[q[0]]), got, exp)
 
 
-def test_serve_results_equal_oracle_under_pressure(mc):
+@pytest.mark.parametrize("part_states", [0, 0xFFFFFFFF])
+def test_serve_results_equal_oracle_under_pressure(mc, part_states):
+    """Queries wait for admission, so partitions are cut into 2-level slices that yield
+    and resume; with configurations cut into blocks of rounds (automatic) or whole."""
     pool = _pool(mc)
     qs = _queries(pool, 40, seed=1)
-    _say("40 queries, small arena, slice 4")
-    res = _run(mc, pool, qs, arena_bytes=256 << 20, max_active=6, slice=4)
+    _say(f"40 queries, small arena, slice 2, part_states {part_states:#x}")
+    res = _run(mc, pool, qs, arena_bytes=256 << 20, max_active=6, slice=2,
+               part_states=part_states)
     _check(pool, qs, res)
     assert max(r["steps"] for r in res.values()) > 1   # partitions really yielded
 
