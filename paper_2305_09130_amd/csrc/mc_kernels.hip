@@ -808,6 +808,9 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           const SegDesc& sg = sh.seg[x.sgi];
           const uint32_t segf = x.sgi ? sh.segfslot[x.sgi] : sg.fslot;
           uint32_t par, jmp = kParentNone;
+          // the interior states of a lock-step run from a dispatch leaf store no links:
+          // the trace derives the leaf from such a state's key (busy units back at d)
+          const bool linkless = !x.is_clos && sg.lock && sg.kstar && x.j + 1u < sg.len;
           if (x.is_clos) {
             const uint32_t pm = x.rmask & ~(1u << (31 - __clz(x.rmask)));
             par = pm ? sh.mslot[x.sgi][pm] : segf;
@@ -817,8 +820,10 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             par = x.j == 0u ? leaf_slot : (li ? sh.chunk_slot[li - 1] : sh.carry);
             if (sg.lock) jmp = leaf_slot;
           }
-          *slot_parent<W>(md.table, slot[n]) = par;
-          if (jmp != kParentNone) *slot_jump<W>(md.table, slot[n]) = jmp;
+          if (!linkless) {
+            *slot_parent<W>(md.table, slot[n]) = par;
+            if (jmp != kParentNone) *slot_jump<W>(md.table, slot[n]) = jmp;
+          }
           if (!x.is_clos && x.j + 1u == sg.len && !x.term && x.sgi + 1u == nseg) {
             const uint32_t pos = atomicAdd(&sh.fcount[cur ^ 1], 1u);
             if (pos < (uint32_t)kFCap) {
@@ -974,10 +979,12 @@ __global__ void k_find(QueryArgs a, Key<W> k) {
   if (threadIdx.x == 0 && blockIdx.x == 0) a.ctrl->target_slot = table_find<W>(a.table, a.mask, k);
 }
 
-// Follows parent slots from the target to the root, writing keys terminal-first.  A
-// state of a lock-step run carries a jump to the run's first predecessor (the leaf);
-// the run's states are regenerated lane-parallel from the leaf (operation end E[i0+j]
-// on every busy unit) instead of being chased one parent at a time.
+// Follows parent slots from the target to the root, writing keys terminal-first.  The
+// end of a lock-step run carries a jump to the run's first predecessor (the leaf), and
+// an interior state of a run from a dispatch leaf carries no link at all: its leaf is
+// the same state with every busy unit back at d and the clock of the run's start, found
+// by a lookup.  The run's states are regenerated lane-parallel from the leaf (operation
+// end E[i0+j] on every busy unit) instead of being chased one parent at a time.
 template <int W>
 __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* out, uint32_t cap) {
   if (blockIdx.x != 0) return;
@@ -997,7 +1004,26 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
 #pragma unroll
     for (int w = 0; w < W; ++w) k.w[w] = p[w];
     const uint32_t par = *slot_parent<W>(a.table, s);
-    const uint32_t jmp = *slot_jump<W>(a.table, s);
+    uint32_t jmp = *slot_jump<W>(a.table, s);
+    if (par == kParentNone && jmp == kParentNone) {
+      // an interior state of a lock-step run from a dispatch leaf (it stores no links):
+      // the leaf has the same busy units, each at d, and the clock of the run's start
+      const St x = decode<W>(k, L);
+      const CfgRec r = a.cfgs[x.cfg];
+      St leaf = x;
+      uint32_t rem = 0;
+      for (int u = 0; u < m; ++u)
+        if (x.rem[u]) {
+          rem = x.rem[u];
+          leaf.rem[u] = r.d;
+        }
+      leaf.clock = x.clock - (r.d - rem);
+      jmp = rem ? table_find<W>(a.table, a.mask, encode<W>(leaf, L)) : kParentNone;
+      if (jmp == kParentNone) {
+        bad = true;
+        break;
+      }
+    }
     if (jmp == kParentNone || (unsigned long long)jmp > a.mask) {
       if (lane == 0) {
 #pragma unroll
