@@ -98,7 +98,8 @@ typedef struct mc_opts {
     uint32_t batch_items;    /* super-step engine: states generated from one frontier state
                                 before waiting for the visited set (0 = 2 x lanes) */
     uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
-                                (any other value = 2) */
+                                (else automatic: 2 for keys of up to 128 bits,
+                                1 for wider keys) */
     uint32_t part_states;    /* super-step engine: target states per partition when a
                                 configuration's subgraph is cut into blocks of whole
                                 rounds (0 = automatic, UINT32_MAX = never cut) */
@@ -223,7 +224,8 @@ typedef struct mc_batch_opts {
     uint32_t use_graph;      /* 1: capture the query's launch sequence once in a hipGraph
                                 and replay it (needs a non-null stream: MC_E_INVAL) */
     uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
-                                (any other value = 2) */
+                                (else automatic: 2 for keys of up to 128 bits,
+                                1 for wider keys) */
     uint32_t part_states;    /* target states per partition when a configuration's
                                 subgraph is cut into blocks of whole rounds
                                 (0 = automatic, UINT32_MAX = never cut) */
@@ -278,7 +280,8 @@ typedef struct mc_engine_opts {
     uint32_t grid;           /* persistent workgroups per step (0 = up to 1024) */
     float load_factor;       /* visited-set load factor (0 = 0.5) */
     uint32_t lane_items;     /* keys each thread inserts per round trip: 1 or 2
-                                (any other value = 2) */
+                                (else automatic: 2 for keys of up to 128 bits,
+                                1 for wider keys) */
     uint32_t part_states;    /* target states per partition when a query's configurations
                                 are cut into blocks of whole rounds (0 = automatic: about
                                 states/256, at most 256 more partitions than

@@ -83,7 +83,7 @@ mc_opts default_opts(const mc_opts* o) {
   if (o) r = *o;
   if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 256;
   if (r.engine > MC_ENGINE_LEVEL) r.engine = MC_ENGINE_SUPERSTEP;
-  if (r.lane_items != 1) r.lane_items = 2;
+  if (r.lane_items > 2) r.lane_items = 0;
   return r;
 }
 
@@ -271,7 +271,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     pq.models = h->dmd;
     pq.parts = h->parts;
     pq.n_parts = h->n_parts;
-    const uint32_t li = h->opts.lane_items ? h->opts.lane_items : 2u;
+    const uint32_t li = lane_items_for(h->opts.lane_items, h->mh.W);
     pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
     pq.head = h->head;
     pq.slice = 0u;

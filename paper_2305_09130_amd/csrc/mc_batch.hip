@@ -44,7 +44,7 @@ mc_batch_opts default_bopts(const mc_batch_opts* o) {
   if (o) r = *o;
   if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 512;
   if (!(r.load_factor > 0.f && r.load_factor < 1.f)) r.load_factor = 0.5f;
-  if (r.lane_items != 1) r.lane_items = 2;
+  if (r.lane_items > 2) r.lane_items = 0;
   return r;
 }
 
@@ -178,13 +178,14 @@ int enqueue_query(mc_batch* b) {
   HIPCHK(launch_clear(s, b->ws + b->plan.tables, b->plan.tables_bytes));
   HIPCHK(launch_reset_models(s, b->dmd, n, b->head, 3));
   HIPCHK(launch_seed_models(s, b->dmd, n));
-  const uint32_t li = b->opts.lane_items ? b->opts.lane_items : 2u;
+  const uint32_t li = b->opts.lane_items;  // 0: per key width
   PartQueue pq[3];
   for (int w = 0; w < 3; ++w) {
     pq[w].models = b->dmd;
     pq[w].parts = b->parts + b->group_off[w];
     pq[w].n_parts = b->group_n[w];
-    pq[w].batch_items = b->opts.chunk ? b->opts.chunk : 2u * li * b->opts.block;
+    pq[w].batch_items =
+        b->opts.chunk ? b->opts.chunk : 2u * lane_items_for(li, 1u << w) * b->opts.block;
     pq[w].head = b->head + w;
     pq[w].slice = 0u;
     pq[w].pad = 0u;

@@ -231,7 +231,7 @@ int mc_engine_create(const mc_engine_opts* o, void* dev_buf, size_t buf_bytes, v
     e = new mc_engine();
     e->opts = *o;
     if (e->opts.block != 256 && e->opts.block != 512 && e->opts.block != 1024) e->opts.block = 512;
-    if (e->opts.lane_items != 1) e->opts.lane_items = 2;
+    if (e->opts.lane_items > 2) e->opts.lane_items = 0;
     if (!(e->opts.load_factor > 0.f && e->opts.load_factor < 1.f)) e->opts.load_factor = 0.5f;
     e->stream = reinterpret_cast<hipStream_t>(stream);
     e->base = reinterpret_cast<unsigned char*>(dev_buf);
@@ -431,7 +431,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
     unsigned int* ny = reinterpret_cast<unsigned int*>(e->base + e->nyield_off);
     HIPCHK(hipMemsetAsync(head, 0, 16, s));
     HIPCHK(hipMemsetAsync(ny, 0, 4, s));
-    const uint32_t li = e->opts.lane_items ? e->opts.lane_items : 2u;
+    const uint32_t li = e->opts.lane_items;  // 0: per key width
     PartQueue pq[3];
     uint32_t grid[3];
     uint32_t off = 0;
@@ -439,7 +439,8 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       pq[g].models = reinterpret_cast<const ModelDev*>(e->base + e->md_off);
       pq[g].parts = parts + off;
       pq[g].n_parts = gn[g];
-      pq[g].batch_items = e->opts.chunk ? e->opts.chunk : 2u * li * e->opts.block;
+      pq[g].batch_items =
+          e->opts.chunk ? e->opts.chunk : 2u * lane_items_for(li, 1u << g) * e->opts.block;
       pq[g].head = head + g;
       pq[g].slice = slice;
       pq[g].pad = 0;

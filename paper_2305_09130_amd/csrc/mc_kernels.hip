@@ -1176,6 +1176,7 @@ static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32
 
 hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
                         uint32_t items, const PartQueue& pq) {
+  items = lane_items_for(items, W);
   if (W == 1) launch_super_w<1>(st, grid, block, items, pq);
   else if (W == 2) launch_super_w<2>(st, grid, block, items, pq);
   else launch_super_w<4>(st, grid, block, items, pq);

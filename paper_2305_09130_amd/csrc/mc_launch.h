@@ -22,6 +22,13 @@ struct QueryArgs {
   uint32_t max_clock;       // bound of the packed clock field
 };
 
+// Keys each thread of the persistent kernel inserts per round trip: 1 or 2 as asked,
+// else (0) 2 for keys of one or two words and 1 for four-word keys, whose two-key
+// kernel needs more registers than three wavefronts per SIMD allow.
+inline uint32_t lane_items_for(uint32_t asked, uint32_t W) {
+  return asked == 1u || asked == 2u ? asked : (W == 4u ? 1u : 2u);
+}
+
 // Library error code (MC_E_*) of a device error flag (kDevErr*).
 inline int dev_error_code(unsigned int e) {
   switch (e) {
@@ -96,8 +103,8 @@ hipError_t launch_seed(hipStream_t st, const QueryArgs& q, Seed* seeds, void* fr
 template <int W>
 hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, const void* fin,
                         void* fout);
-// All models of the queue have key width W (1, 2, 4).  items: states per lane per
-// insert batch (1 or 2).
+// All models of the queue have key width W (1, 2, 4).  items: keys per lane per insert
+// round trip, as for lane_items_for.
 hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
                         uint32_t items, const PartQueue& pq);
 
