@@ -208,6 +208,71 @@ int mc_config(const mc_model *h, uint32_t cfg, uint32_t *params4);
 
 const char *mc_strerror(int code);
 
+/* ---- swarm search (Sec. 5) ------------------------------------------------------ */
+/* Swarm model checking: many independent, incomplete searches at once, each keeping a
+ * bit array of its own (bitstate hashing) instead of storing states and reporting the
+ * counterexamples (trails) it meets within a bounded number of model steps.  Against
+ * the non-termination property G(!FIN) every run reaching a terminal is a trail whose
+ * clock is a model time; against the over-time property with threshold T (prune = 1)
+ * only terminals with clock <= T are.  Member i (one GPU lane) uses seed
+ * splitmix64(seed + i) and makes random walks from the root: at its step t (counted
+ * over all its walks) it takes successor number splitmix64(seed_i ^ splitmix64(t)) mod
+ * k of the k successors (configurations in order at the root, free units in index
+ * order for DISPATCH); with a threshold a walk ends at the first state with clock > T;
+ * at every state it reaches (not the root) with other than exactly one successor it
+ * hashes (cfg, clock, pending, rem_0..rem_{m-1}) by a splitmix64 chain to two bit
+ * positions h mod 2^bits_log2 and (h >> 32) mod 2^bits_log2: both set, the walk ends;
+ * else both are set; a new terminal ends the walk as a trail; a new walk starts only
+ * while t < budget.  The swarm uses the model's visited-set memory (its bit arrays,
+ * member records and a replay buffer); it invalidates the last query's trace. */
+typedef struct mc_swarm_opts {
+    uint32_t members;        /* searchers, >= 1 */
+    uint32_t bits_log2;      /* bits per member = 2^bits_log2, 10..30 */
+    uint64_t budget;         /* member steps after which no new walk starts */
+    uint64_t seed;           /* base seed */
+    uint32_t prune;          /* 1: over-time property with threshold T; 0: G(!FIN) */
+    uint32_t T;
+} mc_swarm_opts;
+
+typedef struct mc_swarm_result {
+    uint32_t best_clock;     /* least trail clock (UINT32_MAX: no trail) */
+    uint32_t best_cfg;       /* its configuration */
+    uint32_t best_member;    /* smallest member index that found it */
+    uint32_t first_clock;    /* the trail found first on the device clock */
+    uint32_t first_cfg;
+    uint32_t pad;
+    uint64_t trails, walks, steps;   /* totals over members */
+    uint64_t first_trail_ns; /* device time from the swarm's start to its first trail */
+    uint64_t swarm_ns;       /* GPU time of the swarm launch (HIP events) */
+} mc_swarm_result;
+
+/* Per-member record of the last swarm (80 bytes, as returned by mc_swarm_members). */
+typedef struct mc_swarm_member {
+    uint64_t walks, trails, steps;
+    uint64_t best_walk_start;    /* member step at which the best trail's walk began */
+    uint64_t first_step;         /* member step at which its first trail ended (~0: none) */
+    uint64_t start_ticks, first_ticks;   /* device clock, 100 MHz */
+    uint32_t best_clock, best_cfg;       /* UINT32_MAX without trails */
+    uint32_t first_clock, first_cfg;
+    uint32_t pad[2];
+} mc_swarm_member;
+
+/* One swarm.  MC_E_NOMEM if the model's visited set is smaller than the swarm needs:
+ * members x (80 B + 2^bits_log2 / 8 B) plus one trail of the longest path. */
+int mc_swarm(mc_model *h, const mc_swarm_opts *o, mc_swarm_result *r);
+/* The last swarm's member records; out: host array of cap >= members records. */
+int mc_swarm_members(const mc_model *h, mc_swarm_member *out, size_t cap);
+/* The swarm search of Sec. 5: a swarm against G(!FIN) gives a time T; then swarms
+ * against the over-time property with threshold T - 1 (new seeds, the same budget)
+ * while one finds a trail, whose least clock becomes T.  Returns the last T found,
+ * the number of swarms run, and that swarm's result.  MC_E_STATE if the first swarm
+ * finds no trail. */
+int mc_swarm_tune(mc_model *h, const mc_swarm_opts *o, uint32_t *t_found, uint32_t *rounds,
+                  mc_swarm_result *best);
+/* The trail of the best trail of the last mc_swarm or mc_swarm_tune (the walk replayed
+ * from its seed), rows as mc_trace, root first.  MC_E_STATE if there is none. */
+int mc_swarm_trace(mc_model *h, uint32_t *rows, size_t cap, size_t *len);
+
 /* ---- batched exploration: many models in one persistent launch ----------------- */
 /* The models of a batch are disjoint state graphs, and so are the configurations of a
  * model after SELECT: every (model, configuration) subgraph becomes one partition of a

@@ -57,6 +57,14 @@ class _Result(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class _SwarmMember(ctypes.Structure):
+    _fields_ = [("walks", ctypes.c_uint64), ("trails", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("best_walk_start", ctypes.c_uint64),
+                ("first_step", ctypes.c_uint64), ("best_clock", ctypes.c_uint32),
+                ("best_cfg", ctypes.c_uint32), ("first_clock", ctypes.c_uint32),
+                ("first_cfg", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -75,6 +83,9 @@ def _load():
                                   ctypes.c_uint64]
         lib.or_successors.argtypes = [P(_Model), u32p, u32p, ctypes.c_uint64]
         lib.or_simulate.argtypes = [P(_Model), ctypes.c_uint64, u32p, u32p]
+        lib.or_swarm.argtypes = [P(_Model), ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                 ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
+                                 P(_SwarmMember)]
         _lib = lib
     return _lib
 
@@ -229,3 +240,20 @@ def bisect_t_min(model: dict, t_ini: int) -> tuple[int, int]:
         else:
             lo = mid
     return hi, n
+
+
+def swarm(model: dict, seed: int, members: int, budget: int, bits_log2: int,
+          T: int | None = None) -> list[dict]:
+    """Swarm search members (Sec. 5): independent random walks from the root with a
+    bitstate array per member, against G(!FIN) (T None) or the over-time property with
+    threshold T.  One dict per member: walks, trails, steps, best/first trail clock and
+    configuration (NONE without trails), the member step where the best walk began and
+    where the first trail ended."""
+    lib = _load()
+    mo, keep = _model(model)
+    out = (_SwarmMember * members)()
+    rc = lib.or_swarm(ctypes.byref(mo), seed, members, budget, bits_log2,
+                      0 if T is None else 1, 0 if T is None else T, out)
+    if rc != 0:
+        raise OracleError(f"or_swarm failed: {rc}")
+    return [{n: int(getattr(r, n)) for n, _ in _SwarmMember._fields_} for r in out]

@@ -540,3 +540,112 @@ int or_simulate(const or_model *mo, uint64_t seed, uint32_t *t_end, uint32_t *cf
     free_cfgs(cfs, mo->n_cfg);
     return OR_OK;
 }
+
+/*
+ * Swarm search (Sec. 5).  Swarm model checking runs many independent, incomplete
+ * searches at once: each member hashes states into a bit array of its own (bitstate
+ * hashing) instead of storing them, and reports the counterexamples it meets within a
+ * bounded number of model steps.  Against the non-termination property G(!FIN) every
+ * run reaching a terminal is a counterexample whose terminal clock is a model time;
+ * against the over-time property with threshold T only terminals with clock <= T are.
+ *
+ * One member, read as follows:
+ *   seed_i   = splitmix64(base_seed + i)
+ *   a walk   starts at the root and, at member step t (counted over all its walks),
+ *            takes successor number splitmix64(seed_i ^ splitmix64(t)) mod k of the k
+ *            successors (configurations in order at the root, free units in index
+ *            order for DISPATCH), t += 1;
+ *   pruning  with a threshold, a walk ends at the first state with clock > T;
+ *   bitstate at every state it reaches (not the root) with other than exactly one
+ *            successor, the walk computes h = a splitmix64 chain over (cfg, clock,
+ *            pending, rem_0..rem_{m-1}) and bit positions h mod B and (h >> 32) mod B
+ *            of its B = 2^bits_log2 bits; both set: the state was visited and the walk
+ *            ends; else both are set;
+ *   trail    a new terminal state ends the walk as a counterexample;
+ *   budget   a new walk starts only while t < budget (a walk in progress finishes).
+ */
+typedef struct {
+    uint64_t walks, trails, steps;
+    uint64_t best_walk_start;  /* member step at which the walk of the best trail began */
+    uint64_t first_step;       /* member step at which its first trail ended (or ~0) */
+    uint32_t best_clock, best_cfg;   /* OR_NONE without trails */
+    uint32_t first_clock, first_cfg; /* the first trail */
+} or_swarm_member;
+
+static uint64_t state_hash(const uint32_t *x, uint32_t m) {
+    uint64_t h = splitmix64((uint64_t)x[0]);
+    h = splitmix64(h ^ x[1]);
+    h = splitmix64(h ^ x[2]);
+    for (uint32_t i = 0; i < m; i++) h = splitmix64(h ^ x[3 + i]);
+    return h;
+}
+
+int or_swarm(const or_model *mo, uint64_t base_seed, uint32_t members, uint64_t budget,
+             uint32_t bits_log2, int prune, uint32_t T, or_swarm_member *out) {
+    if (bits_log2 < 6 || bits_log2 > 34) return OR_E_INVAL;
+    or_cfg *cfs;
+    int rc = load_cfgs(mo, &cfs);
+    if (rc != OR_OK) return rc;
+    const uint32_t m = mo->m, S = 3 + m;
+    const uint32_t need = mo->n_cfg > m ? mo->n_cfg : m;
+    const uint64_t B = 1ull << bits_log2;
+    uint32_t *succ = (uint32_t *)malloc(sizeof(uint32_t) * S * need);
+    uint32_t *next = (uint32_t *)malloc(sizeof(uint32_t) * S * need);
+    uint32_t *x = (uint32_t *)calloc(S, sizeof(uint32_t));
+    uint8_t *bits = (uint8_t *)malloc(B / 8);
+    if (!succ || !next || !x || !bits) {
+        free(succ); free(next); free(x); free(bits);
+        free_cfgs(cfs, mo->n_cfg);
+        return OR_E_NOMEM;
+    }
+    for (uint32_t i = 0; i < members; i++) {
+        or_swarm_member *r = &out[i];
+        memset(r, 0, sizeof(*r));
+        r->first_step = ~0ull;
+        r->best_clock = r->best_cfg = r->first_clock = r->first_cfg = OR_NONE;
+        memset(bits, 0, B / 8);
+        const uint64_t seed = splitmix64(base_seed + i);
+        uint64_t t = 0;
+        while (t < budget) {
+            r->walks++;
+            const uint64_t start = t;
+            memset(x, 0, sizeof(uint32_t) * S);
+            x[0] = OR_ROOT;
+            uint32_t k = successors(mo, cfs, x, succ);
+            for (;;) {
+                const uint64_t pick = splitmix64(seed ^ splitmix64(t)) % k;
+                memcpy(x, succ + pick * S, sizeof(uint32_t) * S);
+                t++;
+                if (prune && x[1] > T) break;
+                k = successors(mo, cfs, x, next);
+                if (k != 1) {
+                    const uint64_t h = state_hash(x, m);
+                    const uint64_t p0 = h & (B - 1), p1 = (h >> 32) & (B - 1);
+                    const int b0 = (bits[p0 >> 3] >> (p0 & 7)) & 1, b1 = (bits[p1 >> 3] >> (p1 & 7)) & 1;
+                    if (b0 && b1) break;
+                    bits[p0 >> 3] |= (uint8_t)(1u << (p0 & 7));
+                    bits[p1 >> 3] |= (uint8_t)(1u << (p1 & 7));
+                }
+                if (k == 0) {
+                    r->trails++;
+                    if (r->first_step == ~0ull) {
+                        r->first_step = t;
+                        r->first_clock = x[1];
+                        r->first_cfg = x[0];
+                    }
+                    if (r->best_clock == OR_NONE || x[1] < r->best_clock) {
+                        r->best_clock = x[1];
+                        r->best_cfg = x[0];
+                        r->best_walk_start = start;
+                    }
+                    break;
+                }
+                uint32_t *tmp = succ; succ = next; next = tmp;
+            }
+        }
+        r->steps = t;
+    }
+    free(succ); free(next); free(x); free(bits);
+    free_cfgs(cfs, mo->n_cfg);
+    return OR_OK;
+}

@@ -90,6 +90,36 @@ class McEngineOpts(ctypes.Structure):
                 ("part_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
+class McSwarmOpts(ctypes.Structure):
+    _fields_ = [("members", ctypes.c_uint32), ("bits_log2", ctypes.c_uint32),
+                ("budget", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("prune", ctypes.c_uint32), ("T", ctypes.c_uint32)]
+
+
+class McSwarmResult(ctypes.Structure):
+    _fields_ = [("best_clock", ctypes.c_uint32), ("best_cfg", ctypes.c_uint32),
+                ("best_member", ctypes.c_uint32), ("first_clock", ctypes.c_uint32),
+                ("first_cfg", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("trails", ctypes.c_uint64), ("walks", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("first_trail_ns", ctypes.c_uint64),
+                ("swarm_ns", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "pad"}
+
+
+class McSwarmMember(ctypes.Structure):
+    _fields_ = [("walks", ctypes.c_uint64), ("trails", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("best_walk_start", ctypes.c_uint64),
+                ("first_step", ctypes.c_uint64), ("start_ticks", ctypes.c_uint64),
+                ("first_ticks", ctypes.c_uint64), ("best_clock", ctypes.c_uint32),
+                ("best_cfg", ctypes.c_uint32), ("first_clock", ctypes.c_uint32),
+                ("first_cfg", ctypes.c_uint32), ("pad", ctypes.c_uint32 * 2)]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "pad"}
+
+
 class McQueryResult(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("T", ctypes.c_uint32), ("status", ctypes.c_int),
                 ("done", ctypes.c_int), ("violated", ctypes.c_int), ("t_min", ctypes.c_uint32),
@@ -138,6 +168,10 @@ _SIGS = {
     "mc_engine_poll": ([_vp, ctypes.c_uint64, _P(McQueryResult)], ctypes.c_int),
     "mc_engine_release": ([_vp, ctypes.c_uint64], ctypes.c_int),
     "mc_engine_destroy": ([_vp], ctypes.c_int),
+    "mc_swarm": ([_vp, _P(McSwarmOpts), _P(McSwarmResult)], ctypes.c_int),
+    "mc_swarm_members": ([_vp, _P(McSwarmMember), ctypes.c_size_t], ctypes.c_int),
+    "mc_swarm_tune": ([_vp, _P(McSwarmOpts), _u32p, _u32p, _P(McSwarmResult)], ctypes.c_int),
+    "mc_swarm_trace": ([_vp, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -305,6 +339,45 @@ class Model:
                                                      ctypes.byref(n), ctypes.byref(st)))
         self.last_stats = st.as_dict()
         return t.value, n.value
+
+    def _swarm_opts(self, members, bits_log2, budget, seed, T):
+        o = McSwarmOpts()
+        o.members, o.bits_log2, o.budget, o.seed = members, bits_log2, budget, seed
+        o.prune, o.T = (0, 0) if T is None else (1, T)
+        return o
+
+    def mc_swarm(self, members: int, bits_log2: int, budget: int, seed: int,
+                 T: int | None = None) -> dict:
+        """One swarm against G(!FIN) (T None) or the over-time property with threshold
+        T; the aggregate result (see mc_swarm_result)."""
+        r = McSwarmResult()
+        _check("mc_swarm", _lib.mc_swarm(self._h, ctypes.byref(
+            self._swarm_opts(members, bits_log2, budget, seed, T)), ctypes.byref(r)))
+        return r.as_dict()
+
+    def mc_swarm_members(self, members: int) -> list[dict]:
+        out = (McSwarmMember * members)()
+        _check("mc_swarm_members", _lib.mc_swarm_members(self._h, out, members))
+        return [x.as_dict() for x in out]
+
+    def mc_swarm_tune(self, members: int, bits_log2: int, budget: int,
+                      seed: int) -> tuple[int, int, dict]:
+        """The swarm search of Sec. 5: (T found, swarms run, the result of the last swarm
+        that found a trail)."""
+        t, n = ctypes.c_uint32(), ctypes.c_uint32()
+        r = McSwarmResult()
+        _check("mc_swarm_tune", _lib.mc_swarm_tune(
+            self._h, ctypes.byref(self._swarm_opts(members, bits_log2, budget, seed, None)),
+            ctypes.byref(t), ctypes.byref(n), ctypes.byref(r)))
+        return t.value, n.value, r.as_dict()
+
+    def mc_swarm_trace(self) -> np.ndarray:
+        n = ctypes.c_size_t()
+        _check("mc_swarm_trace", _lib.mc_swarm_trace(self._h, None, 0, ctypes.byref(n)))
+        rows = np.zeros((n.value, 3 + self.m), dtype=np.uint32)
+        _check("mc_swarm_trace", _lib.mc_swarm_trace(self._h, rows.ctypes.data_as(_u32p),
+                                                     n.value, ctypes.byref(n)))
+        return rows
 
     def mc_config(self, cfg: int) -> list[int]:
         p = np.zeros(4, dtype=np.uint32)

@@ -154,6 +154,10 @@ struct mc_model {
   uint32_t last_T = 0;
   int last_violated = 0;
   uint32_t* tc_host = nullptr;  // pinned, n_cfg entries
+  // last swarm: member records in the visited-set region, the best trail's walk
+  uint32_t swarm_members = 0, swarm_bits_log2 = 10;
+  bool swarm_best = false;
+  unsigned long long swarm_best_seed = 0, swarm_best_start = 0;
   uint64_t q_slots = 0;          // visited-set slots of the last query (a prefix of the table)
   bool trace_ready = false;
   std::vector<uint32_t> trace_rows;
@@ -226,6 +230,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
   hipStream_t s = h->stream;
   h->trace_ready = false;
   h->last = kQueryNone;
+  h->swarm_members = 0;  // the visited set overwrites a swarm's records
   // a check(T) inserts only the states with clock <= T: its visited set is the prefix of
   // the table sized for their number at the same load factor
   uint64_t q_slots = h->plan.slots;
@@ -631,6 +636,178 @@ int mc_simulate(mc_model* h, uint64_t seed, uint32_t* t_end, uint32_t* cfg) {
   HIPCHK(hipStreamSynchronize(s));
   *t_end = h->hpoll[0];
   *cfg = h->hpoll[1];
+  return MC_OK;
+}
+
+namespace {
+
+uint64_t splitmix64_host(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Layout of a swarm in the visited-set region: member records, replay rows, bit arrays.
+struct SwarmPlan {
+  size_t rec = 0, rows = 0, bits = 0, total = 0;
+};
+SwarmPlan swarm_plan(const mc_model* h, uint32_t members, uint32_t bits_log2) {
+  SwarmPlan p;
+  size_t off = 0;
+  p.rec = off;
+  off = align_up(off + sizeof(SwarmMember) * members);
+  p.rows = off;
+  off = align_up(off + 4ull * (3 + h->mh.m) * h->plan.trace_cap);
+  p.bits = off;
+  off = align_up(off + (size_t)members * ((1ull << bits_log2) / 8));
+  p.total = off;
+  return p;
+}
+
+SwarmArgs swarm_args(mc_model* h, const mc_swarm_opts& o, const SwarmPlan& p) {
+  SwarmArgs a;
+  a.cfgs = h->cfgs;
+  a.n_cfg = h->mh.n_cfg;
+  a.m = h->mh.m;
+  a.seed = o.seed;
+  a.budget = o.budget;
+  a.members = o.members;
+  a.bits_log2 = o.bits_log2;
+  a.prune = o.prune ? 1u : 0u;
+  a.T = o.T;
+  a.bits = reinterpret_cast<uint32_t*>(h->table + p.bits);
+  a.out = reinterpret_cast<SwarmMember*>(h->table + p.rec);
+  return a;
+}
+
+}  // namespace
+
+int mc_swarm(mc_model* h, const mc_swarm_opts* o, mc_swarm_result* r) {
+  if (!h || !o || !r || o->members == 0 || o->bits_log2 < 10 || o->bits_log2 > 30)
+    return MC_E_INVAL;
+  const SwarmPlan p = swarm_plan(h, o->members, o->bits_log2);
+  if (p.total > h->plan.table_bytes) return MC_E_NOMEM;
+  hipStream_t s = h->stream;
+  // the region is no longer a visited set
+  h->dirty = true;
+  h->trace_ready = false;
+  h->last = kQueryNone;
+  h->swarm_members = 0;
+  h->swarm_best = false;
+  const SwarmArgs a = swarm_args(h, *o, p);
+  HIPCHK(hipMemsetAsync(a.bits, 0, p.total - p.bits, s));
+  HIPCHK(hipEventRecord(h->ev[4], s));
+  HIPCHK(launch_swarm(s, a));
+  HIPCHK(hipEventRecord(h->ev[5], s));
+  std::vector<SwarmMember> rec(o->members);
+  HIPCHK(hipMemcpyAsync(rec.data(), a.out, sizeof(SwarmMember) * o->members,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, h->ev[4], h->ev[5]));
+  std::memset(r, 0, sizeof(*r));
+  r->best_clock = r->first_clock = kNoClock;
+  r->best_cfg = r->first_cfg = r->best_member = kParentNone;
+  unsigned long long start = ~0ull, first = ~0ull;
+  for (uint32_t i = 0; i < o->members; ++i) {
+    const SwarmMember& x = rec[i];
+    r->trails += x.trails;
+    r->walks += x.walks;
+    r->steps += x.steps;
+    start = std::min(start, x.start_ticks);
+    if (x.trails && x.best_clock < r->best_clock) {
+      r->best_clock = x.best_clock;
+      r->best_cfg = x.best_cfg;
+      r->best_member = i;
+    }
+    if (x.trails && x.first_ticks < first) {
+      first = x.first_ticks;
+      r->first_clock = x.first_clock;
+      r->first_cfg = x.first_cfg;
+    }
+  }
+  r->first_trail_ns = first != ~0ull ? (first - start) * 10ull : 0ull;  // 100 MHz clock
+  r->swarm_ns = (uint64_t)(ms * 1e6);
+  h->swarm_members = o->members;
+  h->swarm_bits_log2 = o->bits_log2;
+  if (r->trails) {
+    h->swarm_best = true;
+    h->swarm_best_seed = splitmix64_host(o->seed + r->best_member);
+    h->swarm_best_start = rec[r->best_member].best_walk_start;
+  }
+  return MC_OK;
+}
+
+int mc_swarm_members(const mc_model* h, mc_swarm_member* out, size_t cap) {
+  if (!h || !out) return MC_E_INVAL;
+  if (!h->swarm_members) return MC_E_STATE;
+  if (cap < h->swarm_members) return MC_E_BUFFER;
+  static_assert(sizeof(mc_swarm_member) == sizeof(SwarmMember), "swarm member record");
+  const SwarmPlan p = swarm_plan(h, h->swarm_members, 10);
+  HIPCHK(hipMemcpy(out, h->table + p.rec, sizeof(SwarmMember) * h->swarm_members,
+                   hipMemcpyDeviceToHost));
+  return MC_OK;
+}
+
+int mc_swarm_tune(mc_model* h, const mc_swarm_opts* o, uint32_t* t_found, uint32_t* rounds,
+                  mc_swarm_result* best) {
+  if (!h || !o || !t_found || !rounds) return MC_E_INVAL;
+  mc_swarm_opts q = *o;
+  q.prune = 0u;
+  mc_swarm_result r;
+  int rc = mc_swarm(h, &q, &r);
+  if (rc) return rc;
+  *rounds = 1;
+  if (!r.trails) return MC_E_STATE;
+  mc_swarm_result found = r;
+  unsigned long long bseed = h->swarm_best_seed, bstart = h->swarm_best_start;
+  while (found.best_clock > 0u) {
+    q.prune = 1u;
+    q.T = found.best_clock - 1u;
+    q.seed = o->seed + *rounds;
+    rc = mc_swarm(h, &q, &r);
+    if (rc) return rc;
+    ++*rounds;
+    if (!r.trails) break;  // nothing below T within the same budget: stop
+    found = r;
+    bseed = h->swarm_best_seed;
+    bstart = h->swarm_best_start;
+  }
+  // the best trail of the search stays available to mc_swarm_trace
+  h->swarm_best = true;
+  h->swarm_best_seed = bseed;
+  h->swarm_best_start = bstart;
+  *t_found = found.best_clock;
+  if (best) *best = found;
+  return MC_OK;
+}
+
+int mc_swarm_trace(mc_model* h, uint32_t* rows, size_t cap, size_t* len) {
+  if (!h || !len) return MC_E_INVAL;
+  if (!h->swarm_best) return MC_E_STATE;
+  hipStream_t s = h->stream;
+  // the rows go after the last swarm's member records, over its bit arrays
+  mc_swarm_opts o{};
+  o.members = h->swarm_members;
+  o.bits_log2 = h->swarm_bits_log2;
+  const SwarmPlan p = swarm_plan(h, o.members, o.bits_log2);
+  const SwarmArgs a = swarm_args(h, o, p);
+  uint32_t* drows = reinterpret_cast<uint32_t*>(h->table + p.rows);
+  h->dirty = true;  // the rows overwrite the visited-set region
+  h->trace_ready = false;
+  h->last = kQueryNone;
+  HIPCHK(hipMemsetAsync(&h->ctrl->error, 0, 4, s));
+  HIPCHK(launch_swarm_replay(s, a, h->ctrl, h->swarm_best_seed, h->swarm_best_start, drows,
+                             (uint32_t)h->plan.trace_cap));
+  HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h->hctrl->error == kDevErrTrace) return MC_E_DEVICE;
+  const uint32_t n = h->hctrl->trace_len;
+  *len = n;
+  if (!rows) return cap ? MC_E_INVAL : MC_OK;
+  if (cap < n) return MC_E_BUFFER;
+  HIPCHK(hipMemcpy(rows, drows, 4ull * (3 + h->mh.m) * n, hipMemcpyDeviceToHost));
   return MC_OK;
 }
 

@@ -148,4 +148,35 @@ hipError_t launch_clear(hipStream_t st, void* p, unsigned long long bytes);
 hipError_t launch_reset(hipStream_t st, Ctrl* ctrl, uint32_t* tc, uint32_t n_cfg);
 hipError_t launch_simulate(hipStream_t st, const QueryArgs& q, unsigned long long seed);
 
+// ---- swarm search (Sec. 5) ----------------------------------------------------------
+// One member of a swarm (device record, 80 bytes; mirrored by mc_swarm_member).
+struct SwarmMember {
+  unsigned long long walks, trails, steps;
+  unsigned long long best_walk_start;  // member step at which the best trail's walk began
+  unsigned long long first_step;       // member step at which its first trail ended (~0: none)
+  unsigned long long start_ticks, first_ticks;  // device clock (100 MHz) at start / first trail
+  uint32_t best_clock, best_cfg;       // kNoClock / kParentNone without trails
+  uint32_t first_clock, first_cfg;     // the member's first trail
+  uint32_t pad[2];
+};
+static_assert(sizeof(SwarmMember) == 80, "SwarmMember layout");
+
+struct SwarmArgs {
+  const CfgRec* cfgs;
+  uint32_t n_cfg, m;
+  unsigned long long seed;    // base seed; member i uses splitmix64(seed + i)
+  unsigned long long budget;  // member steps before no new walk starts
+  uint32_t members, bits_log2;
+  uint32_t prune, T;          // over-time property with threshold T, else non-termination
+  uint32_t* bits;             // members x 2^bits_log2 bits, zero
+  SwarmMember* out;           // members records
+};
+hipError_t launch_swarm(hipStream_t st, const SwarmArgs& a);
+// Replays the walk of member seed `mseed` that began at member step `start`, writing the
+// rows (cfg, clock, pending, rem[0..m-1]) of its states root first into `rows` (at most
+// `cap` rows; ctrl->trace_len gets the number written, ctrl->error kDevErrTrace if more).
+hipError_t launch_swarm_replay(hipStream_t st, const SwarmArgs& a, Ctrl* ctrl,
+                               unsigned long long mseed, unsigned long long start,
+                               uint32_t* rows, uint32_t cap);
+
 }  // namespace mc
