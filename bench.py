@@ -144,6 +144,33 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
             "speedup_vs_one_at_a_time": (total / el) / (s_alone / t_alone)}
 
 
+def swarm_leg(mc, workloads, names, members: int = 16384, bits_log2: int = 16,
+              budget: int = 20000):
+    """The swarm search of Sec. 5 on each named workload: one swarm against G(!FIN)
+    (time to its first trail, that trail's optimality T_min / T_first), then the search
+    loop with the over-time property; against the exact min_time on the same GPU."""
+    out = {}
+    for name in names:
+        model = workloads.WORKLOADS[name]()
+        g = mc.Model(model)
+        t_min, _ = g.mc_min_time()
+        exact_ms = g.last_stats["engine_ns"] / 1e6
+        r = g.mc_swarm(members, bits_log2, budget, 1)
+        t0 = time.perf_counter()
+        t_found, rounds, best = g.mc_swarm_tune(members, bits_log2, budget, 1)
+        tune_s = time.perf_counter() - t0
+        g.close()
+        out[name] = {"members": members, "bits_per_member": 1 << bits_log2,
+                     "budget_steps": budget, "t_min_exact": t_min, "exact_min_time_ms": exact_ms,
+                     "first_trail_us": r["first_trail_ns"] / 1e3,
+                     "first_trail_optimality": t_min / r["first_clock"],
+                     "swarm_ms": r["swarm_ns"] / 1e6, "trails": r["trails"],
+                     "walks": r["walks"], "best_of_one_swarm": r["best_clock"],
+                     "search_t_found": t_found, "search_swarms": rounds,
+                     "search_optimality": t_min / t_found, "search_wall_ms": 1e3 * tune_s}
+    return out
+
+
 def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int = 32):
     """Poisson arrivals of check(T)/min_time queries over a pool of models; continuous
     batching engine vs FIFO one-query-at-a-time service (fresh load per query)."""
@@ -241,7 +268,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--legs", default="plain,cpu,batch,serve",
+    ap.add_argument("--legs", default="plain,cpu,batch,serve,swarm",
                     help="extra legs beside the timed single-query step")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -320,6 +347,10 @@ def main():
     if "serve" in legs:
         _progress("batched leg done; served leg")
         served = served_leg(mc, torch, workloads, args.serve_queries, (0.5, 1.0, 2.0))
+    swarm = None
+    if "swarm" in legs:
+        _progress("swarm leg")
+        swarm = swarm_leg(mc, workloads, [args.workload, "matmul128_vw_cu8"])
 
     cfg = {"workload": args.workload, "kind": model["kind"], "cu": model["m"],
            "configurations": len(model["params"]),
@@ -359,6 +390,7 @@ def main():
         "plain_bfs": plain,
         "batched": batched,
         "served": served,
+        "swarm": swarm,
     }
     print(json.dumps(out), flush=True)
 
