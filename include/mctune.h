@@ -30,6 +30,22 @@
  *                                        log2(WG) x Ll, 1 x Lb, TS x Lc.
  *     MC_KIND_MATMUL (WGx, WGy, TS, VW): n = (M/WGx)(N/(WGy*VW)); 2K x Lg,
  *                                        K(1+VW) x Ll, 2K/TS x Lb, K*VW x Lc.
+ *   Two kinds follow the paper's own Promela models of a unit with NP processing
+ *   elements (size = {S, NP, 0}; GMT = Lg, the local step = Ll, the paper's 1; Lc and
+ *   Lb unused).  A workgroup of WG > NP work items runs in WG/NP waves of NP elements
+ *   (the unit relaunches finished elements, Listings 6 and 14); n = S/(WG*TS)
+ *   workgroups, at least one (Table 1 times one workgroup where WG*TS > S):
+ *     MC_KIND_ABSTRACT (WG, TS):  every wave is one run of the abstract pex of Sec. 4
+ *       (Listing 8) over s = S/TS tiles.  Its long_work(gt, tz) returns on the first
+ *       tick at which time exceeds start_time + gt*tz, and start_time is set at the
+ *       start, before each local step and before the final write, so the operations
+ *       last Lg*TS+1 (first tile's global load), then per tile Ll*TS+1 (local step)
+ *       and, from the second tile on, max(0, (Lg-Ll)*TS) (global load), and finally
+ *       Lg+1 (result write); a wave lasts S*Lg + S/TS + TS + Lg + 2 for Ll = 1 <= Lg.
+ *     MC_KIND_MINIMUM (WG, TS):   the Minimum kernel of Sec. 7 (Listings 10 and 15):
+ *       WG/NP waves x TS global accesses at Lg (MAP), then min(WG, NP) - 1 local
+ *       steps at Ll and one global write at Lg by element 0 (REDUCE local), per
+ *       workgroup as in the kernel.
  *   d_c is the workgroup duration; E_c the distinct cumulative operation end times.
  *
  * Conventions.  Every call returns an int: MC_OK (0) or a negative MC_E_* code; no
@@ -66,21 +82,25 @@ extern "C" {
 /* ---- model descriptor ---------------------------------------------------------- */
 #define MC_KIND_REDUCTION 0u
 #define MC_KIND_MATMUL 1u
+#define MC_KIND_ABSTRACT 2u  /* abstract kernel with NP elements per unit (Sec. 4) */
+#define MC_KIND_MINIMUM 3u   /* Minimum problem model (Sec. 7.2) */
 
 #define MC_MAX_CU 8u         /* compute units per model */
 
 typedef struct mc_desc {
-    uint32_t kind;           /* MC_KIND_REDUCTION or MC_KIND_MATMUL */
+    uint32_t kind;           /* MC_KIND_* */
     uint32_t n_cu;           /* m, 1..MC_MAX_CU */
-    uint32_t size[3];        /* reduction: {G, 0, 0}; matmul: {M, N, K} */
+    uint32_t size[3];        /* reduction: {G, 0, 0}; matmul: {M, N, K};
+                                abstract and minimum: {S, NP, 0} */
     uint32_t lat_global;     /* Lg >= 1 */
     uint32_t lat_local;      /* Ll >= 1 */
     uint32_t lat_compute;    /* Lc >= 1 */
     uint32_t lat_barrier;    /* Lb >= 0 */
     uint32_t n_cfg;          /* number of configurations, >= 1 */
-    const uint32_t *params;  /* host pointer, n_cfg rows of 4: reduction (WG, TS, 0, 0),
-                                matmul (WGx, WGy, TS, VW); VW = 0 means 1.  Powers of
-                                two; sizes must divide as the operation lists require. */
+    const uint32_t *params;  /* host pointer, n_cfg rows of 4: reduction, abstract and
+                                minimum (WG, TS, 0, 0), matmul (WGx, WGy, TS, VW); VW = 0
+                                means 1.  Powers of two; sizes must divide as the
+                                operation lists require. */
 } mc_desc;
 
 /* ---- options ------------------------------------------------------------------- */
@@ -150,6 +170,14 @@ int mc_workspace_bytes(const mc_desc *d, const mc_opts *o, size_t *bytes);
 /* Reachable-state count of the model (root included), its longest path, and the packed
  * key width, without touching the GPU. */
 int mc_describe(const mc_desc *d, uint64_t *states, uint64_t *max_depth, uint32_t *key_words);
+
+/* The operation end times E_c of configuration `cfg` (the per-workgroup operation lists
+ * of the model description above), without touching the GPU: *n = workgroups, *b =
+ * |E_c|, *dur = d_c, ends[0..b-1] = E_c ascending (host memory, may be NULL when cap is
+ * 0).  MC_E_BUFFER with *n, *b and *dur set if cap < b; MC_E_INVAL for a bad
+ * descriptor or cfg >= n_cfg. */
+int mc_config_ends(const mc_desc *d, uint32_t cfg, uint32_t *n, uint32_t *b, uint32_t *dur,
+                   uint32_t *ends, uint64_t cap);
 
 /* Load a model: validates, derives per-configuration tables, uploads them into
  * the caller's workspace and binds the stream.  dev_ws: device memory of ws_bytes

@@ -26,6 +26,7 @@ ROOT = 0xFFFFFFFF
 NONE = 0xFFFFFFFF
 
 CHK_MEASURE, CHK_DEADLOCK, CHK_GRADED, CHK_PERMUTE = 1, 2, 4, 8
+KINDS = {"reduction": 0, "matmul": 1, "abstract": 2, "minimum": 3}
 
 
 def build(force: bool = True) -> str:
@@ -43,7 +44,8 @@ def build(force: bool = True) -> str:
 class _Model(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_uint32),
                 ("G", ctypes.c_uint32), ("M", ctypes.c_uint32), ("N", ctypes.c_uint32),
-                ("K", ctypes.c_uint32), ("Lg", ctypes.c_uint32), ("Ll", ctypes.c_uint32),
+                ("K", ctypes.c_uint32), ("S", ctypes.c_uint32), ("NP", ctypes.c_uint32),
+                ("Lg", ctypes.c_uint32), ("Ll", ctypes.c_uint32),
                 ("Lc", ctypes.c_uint32), ("Lb", ctypes.c_uint32),
                 ("n_cfg", ctypes.c_uint32), ("params", ctypes.POINTER(ctypes.c_uint32)),
                 ("tick", ctypes.c_int32)]
@@ -96,9 +98,10 @@ def _u32p(a: np.ndarray):
 
 def _model(model: dict, tick: bool = False):
     params = np.ascontiguousarray(np.asarray(model["params"], dtype=np.uint32).reshape(-1, 4))
-    kind = 0 if model["kind"] == "reduction" else 1
+    kind = KINDS[model["kind"]]
     mo = _Model(kind, model["m"], model.get("G", 0), model.get("M", 0), model.get("N", 0),
-                model.get("K", 0), model["Lg"], model["Ll"], model["Lc"], model["Lb"],
+                model.get("K", 0), model.get("S", 0), model.get("NP", 0),
+                model["Lg"], model["Ll"], model.get("Lc", 1), model.get("Lb", 0),
                 params.shape[0], _u32p(params), 1 if tick else 0)
     return mo, params  # keep params alive
 

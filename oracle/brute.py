@@ -17,8 +17,41 @@ from __future__ import annotations
 ROOT = 0xFFFFFFFF
 
 
+def _ticked_pex(S: int, TS: int, gmt: int, loc: int) -> list[int]:
+    """Ticks spent in each long_work of one abstract work item (the pex of Listing 8),
+    found by running its clock one tick at a time: a long_work keeps reporting work,
+    and the clock keeps ticking, while time has not passed its start time + gt*tz."""
+    time = 0
+    spent = []
+
+    def long_work(start, budget):
+        nonlocal time
+        t0 = time
+        while time <= start + budget:
+            time += 1
+        spent.append(time - t0)
+
+    start = time
+    for _tile in range(S // TS):
+        long_work(start, gmt * TS)          # global load of the tile
+        start = time
+        long_work(start, loc * TS)          # local step on the tile
+    start = time
+    long_work(start, gmt)                   # the result to global memory
+    return spent
+
+
 def workgroup_program(model: dict, row) -> tuple[int, list[int]]:
     """(number of workgroups, latency of every operation of one workgroup, in order)."""
+    if model["kind"] in ("abstract", "minimum"):
+        S, NP, wg, ts = model["S"], model["NP"], row[0], row[1]
+        n = max(1, S // (wg * ts))
+        waves = max(1, wg // NP)
+        if model["kind"] == "abstract":
+            return n, _ticked_pex(S, ts, model["Lg"], model["Ll"]) * waves
+        # Minimum: every map access is a global access, then element 0 folds the other
+        # min(WG, NP) - 1 local minima and writes the workgroup's minimum
+        return n, [model["Lg"]] * (ts * waves) + [model["Ll"]] * (min(wg, NP) - 1) + [model["Lg"]]
     if model["kind"] == "reduction":
         G, wg, ts = model["G"], row[0], row[1]
         local_steps = 0

@@ -24,8 +24,29 @@ from __future__ import annotations
 from math import comb
 
 
+def _unit_shape(model: dict, row) -> tuple[int, int, int]:
+    """(workgroups, waves, working elements) of the abstract and minimum kinds: n =
+    S/(WG*TS), at least one; WG items on NP elements run in WG/NP waves."""
+    S, NP, wg, ts = model["S"], model["NP"], row[0], row[1]
+    return max(1, S // (wg * ts)), max(1, wg // NP), min(wg, NP)
+
+
 def ops(model: dict, row) -> tuple[int, list[tuple[int, int]]]:
     """(workgroups, [(count, latency), ...]) of one configuration."""
+    if model["kind"] == "abstract":
+        # one wave: the first tile's global load lasts GMT*TS + 1 ticks, every local step
+        # Ll*TS + 1, every later global load only the part of GMT*TS + 1 not already
+        # spent in the previous local step, the final write GMT + 1
+        n, waves, _ = _unit_shape(model, row)
+        ts, tiles, gmt, loc = row[1], model["S"] // row[1], model["Lg"], model["Ll"]
+        later = max(0, gmt * ts + 1 - (loc * ts + 1))
+        wave = [(1, gmt * ts + 1), (1, loc * ts + 1)]
+        wave += [(1, later), (1, loc * ts + 1)] * (tiles - 1)
+        wave += [(1, gmt + 1)]
+        return n, wave * waves
+    if model["kind"] == "minimum":
+        n, waves, nwe = _unit_shape(model, row)
+        return n, [(waves * row[1], model["Lg"]), (nwe - 1, model["Ll"]), (1, model["Lg"])]
     if model["kind"] == "reduction":
         G = model["G"]
         wg, ts = row[0], row[1]
@@ -38,6 +59,16 @@ def ops(model: dict, row) -> tuple[int, list[tuple[int, int]]]:
     n = (M // x) * (N // (y * vw))
     return n, [(2 * K, model["Lg"]), (K * (1 + vw), model["Ll"]),
                ((K // ts) * 2, model["Lb"]), (K * vw, model["Lc"])]
+
+
+def abstract_wave_time(S: int, TS: int, gmt: int, loc: int = 1) -> int:
+    """Duration of one wave of the abstract kernel for loc <= gmt.  Every global load
+    ends gmt*TS + 1 ticks after the previous load ended (the start time it waits from is
+    set when the previous local step starts, i.e. when the previous load ended), so load
+    k ends at k*(gmt*TS + 1); the last local step adds loc*TS + 1 and the final write
+    gmt + 1: (S/TS)*(gmt*TS + 1) + loc*TS + 1 + gmt + 1."""
+    assert loc <= gmt
+    return (S // TS) * (gmt * TS + 1) + loc * TS + 1 + gmt + 1
 
 
 def end_times(oplist) -> list[int]:
@@ -57,7 +88,7 @@ def per_config(model: dict, with_E: bool = True) -> list[dict]:
     for row in model["params"]:
         n, ol = ops(model, row)
         E = end_times(ol) if with_E else None
-        b = sum(cnt for cnt, lat in ol if lat > 0)
+        b = len(E) if E is not None else sum(cnt for cnt, lat in ol if lat > 0)
         d = sum(cnt * lat for cnt, lat in ol)
         q, p = divmod(n, m)
         rounds = -(-n // m)

@@ -38,6 +38,14 @@
  *                         1 x Lb, TS x Lc.
  *   matmul (WGx,WGy,TS,VW): n = (M/WGx)*(N/(WGy*VW)); 2K x Lg, K(1+VW) x Ll,
  *                         2K/TS x Lb, K*VW x Lc.
+ * Two kinds follow the paper's own Promela models of a unit with NP processing elements
+ * (data size S, GMT = Lg, the local step Ll; n = S/(WG*TS) workgroups, at least one;
+ * a workgroup of WG > NP items runs as WG/NP waves of NP elements, Listings 6 and 14):
+ *   abstract (WG, TS):    every wave is one run of the abstract pex (Listing 8) over
+ *                         S/TS tiles, timed by its long_work (see abstract_wave below).
+ *   minimum (WG, TS):     the Minimum kernel (Listings 10 and 15): TS global accesses
+ *                         at Lg per item and wave, then min(WG,NP)-1 local steps at Ll
+ *                         and one global write at Lg.
  * E_c lists the distinct cumulative operation end times of one workgroup, in order;
  * d_c = last(E_c) is the workgroup duration.
  *
@@ -63,12 +71,13 @@
 #define OR_CHK_GRADED 4u    /* a state reached at two different depths */
 #define OR_CHK_PERMUTE 8u   /* a state whose unit-permuted twin is unreachable */
 
-enum { OR_REDUCTION = 0, OR_MATMUL = 1 };
+enum { OR_REDUCTION = 0, OR_MATMUL = 1, OR_ABSTRACT = 2, OR_MINIMUM = 3 };
 
 typedef struct {
     int32_t kind;
     uint32_t m;
     uint32_t G, M, N, K;
+    uint32_t S, NP;         /* abstract and minimum kinds: data size, elements per unit */
     uint32_t Lg, Ll, Lc, Lb;
     uint32_t n_cfg;
     const uint32_t *params; /* n_cfg rows of 4 values */
@@ -102,11 +111,95 @@ static uint32_t ilog2(uint32_t x) {
     return r;
 }
 
+/* Growing list of operation latencies of one workgroup. */
+typedef struct {
+    uint64_t *lat;
+    uint64_t len, cap;
+} or_ops;
+
+static int ops_push(or_ops *o, uint64_t lat) {
+    if (o->len == o->cap) {
+        uint64_t nc = o->cap ? 2 * o->cap : 64;
+        if (nc > (1ull << 27)) return OR_E_INVAL;
+        uint64_t *p = (uint64_t *)realloc(o->lat, sizeof(uint64_t) * nc);
+        if (!p) return OR_E_NOMEM;
+        o->lat = p;
+        o->cap = nc;
+    }
+    o->lat[o->len++] = lat;
+    return OR_OK;
+}
+
+/* One wave of the abstract pex (Listing 8), from the time bookkeeping of the process.
+ * long_work(gt, tz) keeps reporting a unit of work, each report letting the clock tick
+ * once, until time exceeds start_time + gt*tz: it returns at start_time + gt*tz + 1, or
+ * at once if time is already past that.  The pex sets start_time when it starts, before
+ * the local step of every tile and before its final write; not before a tile's global
+ * load.  Each long_work call is one operation (its length may be zero).  Barriers cost
+ * no time (Listing 7). */
+static int abstract_wave(uint64_t S, uint64_t TS, uint64_t GMT, uint64_t LOC, or_ops *o) {
+    uint64_t time = 0, start_time = 0;
+    int rc;
+    for (uint64_t i = 0; i < S / TS; i++) {
+        uint64_t until = start_time + GMT * TS + 1;     /* global load of tile i */
+        uint64_t t1 = until > time ? until : time;
+        if ((rc = ops_push(o, t1 - time)) != OR_OK) return rc;
+        time = t1;
+        start_time = time;                              /* local step of tile i */
+        if ((rc = ops_push(o, LOC * TS + 1)) != OR_OK) return rc;
+        time = start_time + LOC * TS + 1;
+    }
+    start_time = time;                                  /* result to global memory */
+    return ops_push(o, GMT * 1 + 1);
+}
+
+/* Workgroup count and operation list of the abstract and minimum kinds. */
+static int derive_unit_model(const or_model *mo, const uint32_t *p, uint64_t *n, or_ops *o) {
+    uint64_t S = mo->S, NP = mo->NP, WG = p[0], TS = p[1];
+    if (!is_pow2(mo->S) || !is_pow2(mo->NP) || !is_pow2(p[0]) || !is_pow2(p[1])) return OR_E_INVAL;
+    if (WG > S || TS > S) return OR_E_INVAL;
+    *n = S / (WG * TS);
+    if (*n == 0) *n = 1;
+    uint64_t waves = WG > NP ? WG / NP : 1;
+    uint64_t nwe = WG < NP ? WG : NP;
+    int rc;
+    if (mo->kind == OR_ABSTRACT) {
+        for (uint64_t w = 0; w < waves; w++)
+            if ((rc = abstract_wave(S, TS, mo->Lg, mo->Ll, o)) != OR_OK) return rc;
+        return OR_OK;
+    }
+    for (uint64_t w = 0; w < waves; w++)            /* MAP, wave by wave */
+        for (uint64_t i = 0; i < TS; i++)
+            if ((rc = ops_push(o, mo->Lg)) != OR_OK) return rc;
+    for (uint64_t i = 1; i < nwe; i++)              /* REDUCE local by element 0 */
+        if ((rc = ops_push(o, mo->Ll)) != OR_OK) return rc;
+    return ops_push(o, mo->Lg);                     /* the minimum to global memory */
+}
+
 /* Per-configuration derivation: workgroup count and operation end times. */
 static int derive(const or_model *mo, uint32_t c, or_cfg *out) {
     const uint32_t *p = mo->params + 4u * c;
     uint64_t cnt[4], lat[4];
     uint64_t n;
+    if (mo->kind == OR_ABSTRACT || mo->kind == OR_MINIMUM) {
+        or_ops o = {NULL, 0, 0};
+        int rc = derive_unit_model(mo, p, &n, &o);
+        uint64_t b = 0, t = 0;
+        for (uint64_t i = 0; rc == OR_OK && i < o.len; i++) b += o.lat[i] ? 1 : 0;
+        if (rc == OR_OK && (n > 0xFFFFFFFFull || b == 0 || b > (1u << 26))) rc = OR_E_INVAL;
+        if (rc == OR_OK && !(out->E = (uint32_t *)malloc(sizeof(uint32_t) * b))) rc = OR_E_NOMEM;
+        for (uint64_t i = 0, k = 0; rc == OR_OK && i < o.len; i++) {
+            t += o.lat[i];
+            if (t > 0xFFFFFFFFull) { free(out->E); out->E = NULL; rc = OR_E_INVAL; break; }
+            if (o.lat[i]) out->E[k++] = (uint32_t)t;
+        }
+        free(o.lat);
+        if (rc != OR_OK) return rc;
+        out->n = (uint32_t)n;
+        out->b = (uint32_t)b;
+        out->d = (uint32_t)t;
+        return OR_OK;
+    }
     if (mo->kind == OR_REDUCTION) {
         uint32_t WG = p[0], TS = p[1];
         if (!is_pow2(WG) || !is_pow2(TS) || !is_pow2(mo->G) || WG > mo->G) return OR_E_INVAL;

@@ -22,7 +22,7 @@ MC_E_INVAL, MC_E_NOMEM, MC_E_DEVICE, MC_E_TABLE_FULL = -1, -2, -3, -4
 MC_E_BUFFER, MC_E_STATE, MC_E_OVERFLOW, MC_E_ADMIT, MC_E_NOTFOUND = -5, -6, -7, -8, -9
 MC_E_INTERNAL = -10
 NEVER_CUT = 0xFFFFFFFF
-MC_KIND_REDUCTION, MC_KIND_MATMUL = 0, 1
+MC_KIND_REDUCTION, MC_KIND_MATMUL, MC_KIND_ABSTRACT, MC_KIND_MINIMUM = 0, 1, 2, 3
 MC_ENGINE_SUPERSTEP, MC_ENGINE_LEVEL = 0, 1
 MC_MAX_CU = 8
 ROOT = 0xFFFFFFFF
@@ -138,6 +138,8 @@ _vp = ctypes.c_void_p
 _SIGS = {
     "mc_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "mc_describe": ([_P(McDesc), _u64p, _u64p, _u32p], ctypes.c_int),
+    "mc_config_ends": ([_P(McDesc), ctypes.c_uint32, _u32p, _u32p, _u32p, _u32p,
+                        ctypes.c_uint64], ctypes.c_int),
     "mc_workspace_bytes": ([_P(McDesc), _P(McOpts), _P(ctypes.c_size_t)], ctypes.c_int),
     "mc_model_load": ([_P(McDesc), _P(McOpts), _vp, ctypes.c_size_t, _vp, _P(_vp)], ctypes.c_int),
     "mc_model_free": ([_vp], ctypes.c_int),
@@ -198,15 +200,21 @@ def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
     """McDesc of a model dict (see workloads); returns the params array to keep alive."""
     params = np.ascontiguousarray(np.asarray(model["params"], dtype=np.uint32).reshape(-1, 4))
     d = McDesc()
-    if model["kind"] == "reduction":
+    kind = model["kind"]
+    if kind == "reduction":
         d.kind = MC_KIND_REDUCTION
         d.size[0], d.size[1], d.size[2] = model["G"], 0, 0
-    else:
+    elif kind == "matmul":
         d.kind = MC_KIND_MATMUL
         d.size[0], d.size[1], d.size[2] = model["M"], model["N"], model["K"]
+    elif kind in ("abstract", "minimum"):
+        d.kind = MC_KIND_ABSTRACT if kind == "abstract" else MC_KIND_MINIMUM
+        d.size[0], d.size[1], d.size[2] = model["S"], model["NP"], 0
+    else:
+        raise ValueError(f"unknown model kind {kind!r}")
     d.n_cu = model["m"]
     d.lat_global, d.lat_local = model["Lg"], model["Ll"]
-    d.lat_compute, d.lat_barrier = model["Lc"], model["Lb"]
+    d.lat_compute, d.lat_barrier = model.get("Lc", 1), model.get("Lb", 0)
     d.n_cfg = params.shape[0]
     d.params = params.ctypes.data_as(_u32p)
     return d, params
@@ -228,6 +236,22 @@ def mc_describe(model: dict) -> dict:
     _check("mc_describe", _lib.mc_describe(ctypes.byref(d), ctypes.byref(s), ctypes.byref(dep),
                                            ctypes.byref(w)))
     return {"states": s.value, "max_depth": dep.value, "key_words": w.value}
+
+
+def mc_config_ends(model: dict, cfg: int) -> dict:
+    """Workgroups n, duration d and operation end times E of one configuration, as the
+    library derives them (host only)."""
+    d, keep = make_desc(model)
+    n, b, dur = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    rc = _lib.mc_config_ends(ctypes.byref(d), cfg, ctypes.byref(n), ctypes.byref(b),
+                             ctypes.byref(dur), None, 0)
+    if rc not in (MC_OK, MC_E_BUFFER):
+        _check("mc_config_ends", rc)
+    ends = np.zeros(max(1, b.value), dtype=np.uint32)
+    _check("mc_config_ends", _lib.mc_config_ends(ctypes.byref(d), cfg, ctypes.byref(n),
+                                                 ctypes.byref(b), ctypes.byref(dur),
+                                                 ends.ctypes.data_as(_u32p), b.value))
+    return {"n": n.value, "b": b.value, "d": dur.value, "E": ends[:b.value].tolist()}
 
 
 def state_count(model: dict) -> int | None:

@@ -284,7 +284,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     pq.yielded = nullptr;
     pq.n_yielded = nullptr;
     const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
-    HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq));
+    HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general));
     HIPCHK(hipEventRecord(h->ev[5], s));
     launches = 2;
   } else {
@@ -403,6 +403,27 @@ int mc_describe(const mc_desc* d, uint64_t* states, uint64_t* max_depth, uint32_
     if (states) *states = mh.states;
     if (max_depth) *max_depth = mh.max_depth;
     if (key_words) *key_words = mh.W;
+    return MC_OK;
+  } catch (...) {
+    return MC_E_INVAL;
+  }
+}
+
+int mc_config_ends(const mc_desc* d, uint32_t cfg, uint32_t* n, uint32_t* b, uint32_t* dur,
+                   uint32_t* ends, uint64_t cap) {
+  if (!n || !b || !dur || (cap && !ends)) return MC_E_INVAL;
+  try {
+    ModelHost mh;
+    std::string err;
+    const int rc = build_model(d, &mh, &err);
+    if (rc) return rc;
+    if (cfg >= mh.n_cfg) return MC_E_INVAL;
+    const CfgRec& r = mh.cfgs[cfg];
+    *n = r.n;
+    *b = r.b;
+    *dur = r.d;
+    if (cap < r.b) return MC_E_BUFFER;
+    for (uint32_t k = 0; k < r.b; ++k) ends[k] = (uint32_t)end_at_host(r, k);
     return MC_OK;
   } catch (...) {
     return MC_E_INVAL;
@@ -639,6 +660,8 @@ int mc_simulate(mc_model* h, uint64_t seed, uint32_t* t_end, uint32_t* cfg) {
   return MC_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 uint64_t splitmix64_host(uint64_t z) {
@@ -682,6 +705,8 @@ SwarmArgs swarm_args(mc_model* h, const mc_swarm_opts& o, const SwarmPlan& p) {
 }
 
 }  // namespace
+
+extern "C" {
 
 int mc_swarm(mc_model* h, const mc_swarm_opts* o, mc_swarm_result* r) {
   if (!h || !o || !r || o->members == 0 || o->bits_log2 < 10 || o->bits_log2 > 30)

@@ -155,8 +155,10 @@ __device__ __forceinline__ bool is_terminal(const St& s, int m) {
 
 // ---- operation ends of one workgroup (phases of CfgRec) ----------------------------
 
-// number of operation ends at times <= e, for 0 <= e
-__device__ __forceinline__ uint32_t ends_upto(const CfgRec& r, uint32_t e) {
+// Uniform phases (one operation per period, back to back from 0, a single wave): the
+// operation lists of the reduction and matmul kinds.  Bit-for-bit the general helpers
+// below on such configurations, with fewer live registers.
+__device__ __forceinline__ uint32_t ends_upto_uniform(const CfgRec& r, uint32_t e) {
   if (e >= r.d) return r.b;
   uint32_t res = r.b;
   bool found = false;
@@ -170,8 +172,7 @@ __device__ __forceinline__ uint32_t ends_upto(const CfgRec& r, uint32_t e) {
   return res;
 }
 
-// time of the k-th operation end (0-based), k < b
-__device__ __forceinline__ uint32_t end_at(const CfgRec& r, uint32_t k) {
+__device__ __forceinline__ uint32_t end_at_uniform(const CfgRec& r, uint32_t k) {
   uint32_t res = r.d;
   bool found = false;
 #pragma unroll
@@ -184,14 +185,80 @@ __device__ __forceinline__ uint32_t end_at(const CfgRec& r, uint32_t k) {
   return res;
 }
 
+// number of operation ends of one wave at times <= e, 0 <= e <= dw
+__device__ __forceinline__ uint32_t wave_ends_upto(const CfgRec& r, uint32_t e) {
+  uint32_t res = 0;
+  bool found = false;
+#pragma unroll
+  for (int j = kMaxPhases - 1; j >= 0; --j) {
+    if (j < (int)r.nph && e >= r.t0[j] && !found) {
+      const uint32_t rel = e - r.t0[j], reps = rel / r.lat[j];
+      uint32_t k = reps;
+      if (r.la[j]) k = 2u * reps + (rel - reps * r.lat[j] >= r.la[j] ? 1u : 0u);
+      res = r.i0[j] + (k < r.cnt[j] ? k : r.cnt[j]);
+      found = true;
+    }
+  }
+  return res;
+}
+
+// number of operation ends at times <= e, for 0 <= e
+__device__ __forceinline__ uint32_t ends_upto(const CfgRec& r, uint32_t e) {
+  if (e >= r.d) return r.b;
+  if (r.waves > 1u) {
+    const uint32_t w = e / r.dw;
+    return w * r.bw + wave_ends_upto(r, e - w * r.dw);
+  }
+  return wave_ends_upto(r, e);
+}
+
+// time of the k-th operation end of one wave (0-based), k < bw
+__device__ __forceinline__ uint32_t wave_end_at(const CfgRec& r, uint32_t k) {
+  uint32_t res = r.dw;
+  bool found = false;
+#pragma unroll
+  for (int j = 0; j < kMaxPhases; ++j) {
+    if (j < (int)r.nph && !found && k < r.i0[j] + r.cnt[j]) {
+      const uint32_t q = k - r.i0[j];
+      res = r.t0[j] + (q + 1u) * r.lat[j];
+      if (r.la[j]) res = r.t0[j] + (q >> 1) * r.lat[j] + ((q & 1u) ? r.lat[j] : r.la[j]);
+      found = true;
+    }
+  }
+  return res;
+}
+
+// time of the k-th operation end (0-based), k < b
+__device__ __forceinline__ uint32_t end_at(const CfgRec& r, uint32_t k) {
+  if (r.waves > 1u) {
+    const uint32_t w = k / r.bw;
+    return w * r.dw + wave_end_at(r, k - w * r.bw);
+  }
+  return wave_end_at(r, k);
+}
+
+// The super-step engine is compiled twice: GEN = false for models whose
+// configurations all have uniform phases, GEN = true for the rest.
+template <bool GEN>
+__device__ __forceinline__ uint32_t ends_upto_t(const CfgRec& r, uint32_t e) {
+  if constexpr (GEN) return ends_upto(r, e);
+  else return ends_upto_uniform(r, e);
+}
+template <bool GEN>
+__device__ __forceinline__ uint32_t end_at_t(const CfgRec& r, uint32_t k) {
+  if constexpr (GEN) return end_at(r, k);
+  else return end_at_uniform(r, k);
+}
+
 // One ADVANCE step: the clock moves to the next operation end of any busy unit.
+template <bool GEN = true>
 __device__ __forceinline__ void advance_once(St& s, const CfgRec& r, int m) {
   uint32_t delta = 0xFFFFFFFFu;
 #pragma unroll
   for (int i = 0; i < kMaxCU; ++i) {
     if (i < m && s.rem[i]) {
       const uint32_t e = r.d - s.rem[i];
-      const uint32_t di = end_at(r, ends_upto(r, e)) - e;
+      const uint32_t di = end_at_t<GEN>(r, ends_upto_t<GEN>(r, e)) - e;
       delta = di < delta ? di : delta;
     }
   }

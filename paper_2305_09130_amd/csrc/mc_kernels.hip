@@ -360,7 +360,7 @@ struct Item {
 
 // State number i of the current batch: a closure state (a set of started units) or the
 // j-th state of a run from a leaf, built directly from the segment's templates.
-template <int W, int BLOCK, int NI, bool KEY>
+template <int W, int BLOCK, int NI, bool KEY, bool GEN>
 __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t nseg,
                                          const SuperShared<BLOCK, NI>& sh, const CfgRec& r,
                                          bool e_lds, const ModelDev& md, int m, Item<W>& it) {
@@ -406,7 +406,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
   it.rmask = sg.kstar ? (sg.nleaf == 1u ? (1u << sg.nfree) - 1u : (uint32_t)sh.leaf[leaf]) : 0u;
   it.dep = sg.fdep + sg.kstar + it.j + 1u;
   if (sg.lock) {
-    const uint32_t e = e_lds ? sh.E[sg.idx0 + it.j] : end_at(r, sg.idx0 + it.j);
+    const uint32_t e = e_lds ? sh.E[sg.idx0 + it.j] : end_at_t<GEN>(r, sg.idx0 + it.j);
     it.clk = sg.fclock + (e - sg.e0);
     if (KEY) {
       const unsigned long long rem = r.d - e;
@@ -443,7 +443,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
 
 __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
 
-template <int W, int BLOCK, int NI>
+template <int W, int BLOCK, int NI, bool GEN>
 __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t batch_items,
                                   uint32_t slice, const PartQueue& pq,
                                   SuperShared<BLOCK, NI>& sh) {
@@ -455,7 +455,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
   const CfgRec r = md.cfgs[c];
   const bool e_lds = r.b <= (uint32_t)kEMax;
   if (e_lds)
-    for (uint32_t k = tid; k < r.b; k += BLOCK) sh.E[k] = end_at(r, k);
+    for (uint32_t k = tid; k < r.b; k += BLOCK) sh.E[k] = end_at_t<GEN>(r, k);
   if (tid == 0) {
     sh.has_stop = 0u;
     sh.handed = 0u;
@@ -582,7 +582,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             const bool lock = kstar ? (busy == 0u) : bsame;
             sg.lock = lock ? 1u : 0u;
             sg.e0 = kstar ? 0u : r.d - brem;
-            sg.idx0 = lock ? ends_upto(r, sg.e0) : 0u;
+            sg.idx0 = lock ? ends_upto_t<GEN>(r, sg.e0) : 0u;
             sg.len = lock ? r.b - sg.idx0 : 1u;
             sg.pend = x.pending - kstar;
             sg.fclock = x.clock;
@@ -735,7 +735,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             }
           }
           y.pending -= sg.kstar;
-          advance_once(y, r, m);
+          advance_once<GEN>(y, r, m);
           const Key<W> yk = encode<W>(y, L);
 #pragma unroll
           for (int w = 0; w < W; ++w) sh.gkey[tid][w] = yk.w[w];
@@ -751,7 +751,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
           Item<W> x;
-          gen_item<W, BLOCK, NI, true>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+          gen_item<W, BLOCK, NI, true, GEN>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                        e_lds, md, m, x);
           if (x.active && x.clk > md.max_clock) {
             set_error(md.ctrl, kDevErrOverflow);
@@ -770,7 +770,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
-          gen_item<W, BLOCK, NI, false>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+          gen_item<W, BLOCK, NI, false, GEN>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                         e_lds, md, m, it[n]);
           it[n].active = act[n];
           fresh[n] = false;
@@ -878,7 +878,7 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
   }
 }
 
-template <int W, int BLOCK, int NI>
+template <int W, int BLOCK, int NI, bool GEN>
 __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
   __shared__ SuperShared<BLOCK, NI> sh;
   const uint32_t tid = threadIdx.x;
@@ -896,7 +896,7 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     const ModelDev& md = sh.md;
     const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
     const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
-    if (!skip) explore_partition<W, BLOCK, NI>(md, pc, a.batch_items, a.slice, a, sh);
+    if (!skip) explore_partition<W, BLOCK, NI, GEN>(md, pc, a.batch_items, a.slice, a, sh);
     if (tid == 0) {
       const unsigned long long dt = __builtin_amdgcn_s_memrealtime() - t_part;
       const unsigned long long prev = atomicMax(&md.ctrl->crit_ticks, dt);
@@ -1345,11 +1345,11 @@ hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, cons
   return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool GEN>
 static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32_t items,
                            const PartQueue& pq) {
 #define MC_LAUNCH_SUPER(B, N) \
-  hipLaunchKernelGGL((k_superstep<W, B, N>), dim3(grid), dim3(B), 0, st, pq)
+  hipLaunchKernelGGL((k_superstep<W, B, N, GEN>), dim3(grid), dim3(B), 0, st, pq)
   if (block == 256) {
     if (items >= 2) MC_LAUNCH_SUPER(256, 2);
     else MC_LAUNCH_SUPER(256, 1);
@@ -1364,16 +1364,23 @@ static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32
 }
 
 hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
-                        uint32_t items, const PartQueue& pq) {
+                        uint32_t items, const PartQueue& pq, bool general) {
   items = lane_items_for(items, W);
-  if (W == 1) launch_super_w<1>(st, grid, block, items, pq);
-  else if (W == 2) launch_super_w<2>(st, grid, block, items, pq);
-  else launch_super_w<4>(st, grid, block, items, pq);
+  if (general) {
+    if (W == 1) launch_super_w<1, true>(st, grid, block, items, pq);
+    else if (W == 2) launch_super_w<2, true>(st, grid, block, items, pq);
+    else launch_super_w<4, true>(st, grid, block, items, pq);
+  } else {
+    if (W == 1) launch_super_w<1, false>(st, grid, block, items, pq);
+    else if (W == 2) launch_super_w<2, false>(st, grid, block, items, pq);
+    else launch_super_w<4, false>(st, grid, block, items, pq);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)[3],
-                             const uint32_t (&grid)[3], uint32_t block, uint32_t items) {
+                             const uint32_t (&grid)[3], uint32_t block, uint32_t items,
+                             bool general) {
   static const uint32_t widths[3] = {1, 2, 4};
   int used = 0, last = -1;
   for (int w = 0; w < 3; ++w)
@@ -1383,12 +1390,13 @@ hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)
     }
   if (used == 0) return hipSuccess;
   if (used == 1)  // no fork needed
-    return launch_super(main, widths[last], grid[last], block, items, queue[last]);
+    return launch_super(main, widths[last], grid[last], block, items, queue[last], general);
   hipError_t e = hipEventRecord(f.fork, main);
   for (int w = 0; w < 3 && e == hipSuccess; ++w) {
     if (!queue[w].n_parts) continue;
     e = hipStreamWaitEvent(f.sub[w], f.fork, 0);
-    if (e == hipSuccess) e = launch_super(f.sub[w], widths[w], grid[w], block, items, queue[w]);
+    if (e == hipSuccess)
+      e = launch_super(f.sub[w], widths[w], grid[w], block, items, queue[w], general);
     if (e == hipSuccess) e = hipEventRecord(f.join[w], f.sub[w]);
     if (e == hipSuccess) e = hipStreamWaitEvent(main, f.join[w], 0);
   }

@@ -40,18 +40,35 @@ static int fail(std::string* err, const std::string& msg) {
   return MC_E_INVAL;
 }
 
-// Operation phases of configuration c: (count, latency) in execution order.
-static int phases(const mc_desc* d, const uint32_t* p, uint64_t* n, uint64_t cnt[4],
-                  uint64_t lat[4], std::string* err) {
+// One wave of a configuration's workgroup: its timed phases (zero-latency operations
+// dropped), how many waves make a workgroup and how many workgroups there are.
+struct WaveSpec {
+  uint64_t n = 0, waves = 1, t = 0;  // t: wave duration so far
+  uint32_t nph = 0;
+  uint64_t cnt[kMaxPhases] = {}, lat[kMaxPhases] = {}, la[kMaxPhases] = {}, t0[kMaxPhases] = {};
+  // cnt operations of latency lat, back to back from the current end
+  void seq(uint64_t c, uint64_t l) {
+    if (!c || !l) return;
+    grid(t, c, l, 0);
+  }
+  // cnt ends on the grid t0 + k*l (+ a for two-operation periods)
+  void grid(uint64_t start, uint64_t c, uint64_t l, uint64_t a) {
+    cnt[nph] = c; lat[nph] = l; la[nph] = a; t0[nph] = start;
+    ++nph;
+    t = start + (a ? c / 2 : c) * l;
+  }
+};
+
+static int phases(const mc_desc* d, const uint32_t* p, WaveSpec* w, std::string* err) {
   if (d->kind == MC_KIND_REDUCTION) {
     const uint64_t G = d->size[0], WG = p[0], TS = p[1];
     if (!pow2(G) || !pow2(WG) || !pow2(TS)) return fail(err, "reduction sizes must be powers of two");
     if (WG > G) return fail(err, "WG larger than G");
-    *n = G / WG;
-    cnt[0] = (G + WG * TS - 1) / (WG * TS); lat[0] = d->lat_global;
-    cnt[1] = bit_length(WG) - 1;            lat[1] = d->lat_local;
-    cnt[2] = 1;                             lat[2] = d->lat_barrier;
-    cnt[3] = TS;                            lat[3] = d->lat_compute;
+    w->n = G / WG;
+    w->seq((G + WG * TS - 1) / (WG * TS), d->lat_global);
+    w->seq(bit_length(WG) - 1, d->lat_local);
+    w->seq(1, d->lat_barrier);
+    w->seq(TS, d->lat_compute);
     return MC_OK;
   }
   if (d->kind == MC_KIND_MATMUL) {
@@ -60,11 +77,39 @@ static int phases(const mc_desc* d, const uint32_t* p, uint64_t* n, uint64_t cnt
     if (!pow2(M) || !pow2(N) || !pow2(K) || !pow2(X) || !pow2(Y) || !pow2(TS) || !pow2(VW))
       return fail(err, "matmul sizes must be powers of two");
     if (X > M || Y * VW > N || TS > K) return fail(err, "matmul tile larger than the matrix");
-    *n = (M / X) * (N / (Y * VW));
-    cnt[0] = 2 * K;          lat[0] = d->lat_global;
-    cnt[1] = K * (1 + VW);   lat[1] = d->lat_local;
-    cnt[2] = 2 * (K / TS);   lat[2] = d->lat_barrier;
-    cnt[3] = K * VW;         lat[3] = d->lat_compute;
+    w->n = (M / X) * (N / (Y * VW));
+    w->seq(2 * K, d->lat_global);
+    w->seq(K * (1 + VW), d->lat_local);
+    w->seq(2 * (K / TS), d->lat_barrier);
+    w->seq(K * VW, d->lat_compute);
+    return MC_OK;
+  }
+  if (d->kind == MC_KIND_ABSTRACT || d->kind == MC_KIND_MINIMUM) {
+    const uint64_t S = d->size[0], NP = d->size[1], WG = p[0], TS = p[1];
+    const uint64_t Lg = d->lat_global, Ll = d->lat_local;
+    if (!pow2(S) || !pow2(NP) || !pow2(WG) || !pow2(TS))
+      return fail(err, "size, NP, WG and TS must be powers of two");
+    if (WG > S || TS > S) return fail(err, "WG or TS larger than the data size");
+    w->n = std::max<uint64_t>(1, S / (WG * TS));  // one workgroup where WG*TS > S
+    const uint64_t waves = WG > NP ? WG / NP : 1;  // NP elements run WG items in waves
+    if (d->kind == MC_KIND_MINIMUM) {
+      w->seq(waves * TS, Lg);                       // MAP: TS global accesses per item
+      w->seq(std::min(WG, NP) - 1, Ll);             // REDUCE local by element 0
+      w->seq(1, Lg);                                // the workgroup's minimum to global
+      return MC_OK;
+    }
+    // abstract pex: long_work(gt, tz) ends one tick after start_time + gt*tz; start_time
+    // is reset before each local step but not before the next tile's global load
+    const uint64_t s = S / TS, bb = Ll * TS + 1, g = Lg > Ll ? (Lg - Ll) * TS : 0;
+    w->waves = waves;
+    if (g) {
+      // tile k: global load ends at k(g+bb), local step at k(g+bb)+bb: a grid from bb
+      w->grid(bb, 2 * s, g + bb, g);
+    } else {
+      w->seq(1, Lg * TS + 1);  // first tile's load; later loads end at once
+      w->seq(s, bb);
+    }
+    w->seq(1, Lg + 1);  // the work item's result to global memory
     return MC_OK;
   }
   return fail(err, "unknown model kind");
@@ -86,31 +131,41 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   h->params.assign(d->params, d->params + 4ull * d->n_cfg);
   h->desc.params = h->params.data();
   h->cfgs.assign(d->n_cfg, CfgRec{});
+  h->general = false;
   h->cfg_states.assign(d->n_cfg, 0);
   const uint32_t m = h->m;
   uint64_t total = 1, depth = 0, fb = d->n_cfg;
   uint64_t widest_sum = 0;
   uint32_t max_clock = 0, max_n = 0, max_d = 0;
   for (uint32_t c = 0; c < d->n_cfg; ++c) {
-    uint64_t n, cnt[4], lat[4];
-    int rc = phases(d, &h->params[4ull * c], &n, cnt, lat, err);
+    WaveSpec ws;
+    int rc = phases(d, &h->params[4ull * c], &ws, err);
     if (rc) return rc;
+    const uint64_t n = ws.n;
     if (n == 0 || n >= (1ull << 31)) return fail(err, "workgroup count out of range");
     CfgRec& r = h->cfgs[c];
     std::memset(&r, 0, sizeof(r));
-    uint64_t t = 0, b = 0;
-    for (int j = 0; j < 4; ++j) {
-      if (cnt[j] == 0 || lat[j] == 0) continue;
-      if (cnt[j] >= (1ull << 31)) return fail(err, "operation count out of range");
-      r.cnt[r.nph] = (uint32_t)cnt[j];
-      r.lat[r.nph] = (uint32_t)lat[j];
-      r.t0[r.nph] = (uint32_t)t;
-      r.i0[r.nph] = (uint32_t)b;
-      ++r.nph;
-      t += cnt[j] * lat[j];
-      b += cnt[j];
-      if (t >= (1ull << 31)) return fail(err, "workgroup duration exceeds 2^31");
+    uint64_t bw = 0;
+    for (uint32_t j = 0; j < ws.nph; ++j) {
+      if (ws.cnt[j] >= (1ull << 31)) return fail(err, "operation count out of range");
+      r.cnt[j] = (uint32_t)ws.cnt[j];
+      r.lat[j] = (uint32_t)ws.lat[j];
+      r.la[j] = (uint32_t)ws.la[j];
+      r.t0[j] = (uint32_t)ws.t0[j];
+      r.i0[j] = (uint32_t)bw;
+      bw += ws.cnt[j];
     }
+    r.nph = ws.nph;
+    if (ws.t >= (1ull << 31) || ws.waves >= (1ull << 31)) return fail(err, "workgroup duration exceeds 2^31");
+    const uint64_t t = ws.waves * ws.t, b = ws.waves * bw;
+    if (t >= (1ull << 31)) return fail(err, "workgroup duration exceeds 2^31");
+    if (b >= (1ull << 31)) return fail(err, "operation count out of range");
+    r.waves = (uint32_t)ws.waves;
+    r.dw = (uint32_t)ws.t;
+    r.bw = (uint32_t)bw;
+    for (uint32_t j = 0; j < ws.nph; ++j)
+      if (r.la[j] || r.t0[j] != (j ? r.t0[j - 1] + r.cnt[j - 1] * r.lat[j - 1] : 0u)) h->general = true;
+    if (r.waves > 1) h->general = true;
     if (b == 0) return fail(err, "workgroup without timed operations");
     const uint64_t rounds = (n + m - 1) / m;
     const uint64_t tc = rounds * t;
@@ -206,12 +261,31 @@ uint64_t auto_part_states(uint64_t states) {
 }
 
 // operation ends of one workgroup at or before time x
-static uint64_t ends_le(const CfgRec& r, uint64_t x) {
+uint64_t ends_le(const CfgRec& r, uint64_t x) {
+  if (x >= r.d) return r.b;
+  const uint64_t w = x / r.dw;
+  x -= w * r.dw;
   uint64_t c = 0;
-  for (uint32_t j = 0; j < r.nph; ++j)
-    if (x >= (uint64_t)r.t0[j] + r.lat[j])
-      c += std::min<uint64_t>(r.cnt[j], (x - r.t0[j]) / r.lat[j]);
-  return c;
+  for (uint32_t j = 0; j < r.nph; ++j) {
+    if (x < r.t0[j]) break;
+    const uint64_t rel = x - r.t0[j], reps = rel / r.lat[j];
+    const uint64_t k = r.la[j] ? 2 * reps + (rel - reps * r.lat[j] >= r.la[j] ? 1 : 0) : reps;
+    c = r.i0[j] + std::min<uint64_t>(k, r.cnt[j]);
+  }
+  return w * r.bw + c;
+}
+
+uint64_t end_at_host(const CfgRec& r, uint64_t k) {
+  const uint64_t w = k / r.bw;
+  k -= w * r.bw;
+  for (uint32_t j = 0; j < r.nph; ++j) {
+    if (k >= (uint64_t)r.i0[j] + r.cnt[j]) continue;
+    const uint64_t q = k - r.i0[j];
+    const uint64_t t = r.la[j] ? r.t0[j] + (q / 2) * r.lat[j] + (q % 2 ? r.lat[j] : r.la[j])
+                               : r.t0[j] + (q + 1) * r.lat[j];
+    return w * r.dw + t;
+  }
+  return (w + 1) * r.dw;
 }
 
 uint64_t count_le_bound(const ModelHost& h, uint64_t T) {

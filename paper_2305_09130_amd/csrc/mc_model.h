@@ -36,22 +36,32 @@ struct Layout {
   uint8_t pad[2];
 };
 
-// One configuration: workgroup count, duration and the timed operation phases
-// (phases of zero latency add no operation end and are dropped).  Phase j ends
-// cnt[j] operations at t0[j] + k*lat[j], k = 1..cnt[j]; i0[j] = ends before phase j.
+// One configuration: workgroup count, duration and the timed operation phases of one
+// wave (operations of zero latency add no end and are dropped).  A workgroup is
+// `waves` back-to-back repetitions of the wave, each lasting dw with bw ends.  Phase j
+// of a wave holds cnt[j] ends on a grid that starts at t0[j] (a phase may start after
+// the previous phase's last end when its first operation is longer than its period):
+//   la[j] = 0: one operation per period, ends at t0[j] + k*lat[j], k = 1..cnt[j];
+//   la[j] > 0: two operations per period lat[j], ends at t0[j] + k*lat[j] + la[j] and
+//              t0[j] + (k+1)*lat[j], k = 0..cnt[j]/2 - 1 (cnt[j] even).
+// i0[j] = ends of the wave before phase j.
 struct CfgRec {
   uint32_t n;      // workgroups
-  uint32_t d;      // workgroup duration = last operation end
-  uint32_t b;      // number of distinct operation ends
-  uint32_t nph;    // timed phases
+  uint32_t d;      // workgroup duration = last operation end = waves * dw
+  uint32_t b;      // number of distinct operation ends = waves * bw
+  uint32_t nph;    // timed phases of one wave
   uint32_t cnt[kMaxPhases];
   uint32_t lat[kMaxPhases];
   uint32_t t0[kMaxPhases];
   uint32_t i0[kMaxPhases];
+  uint32_t la[kMaxPhases];
+  uint32_t waves;  // repetitions of the wave, >= 1
+  uint32_t dw;     // duration of one wave
+  uint32_t bw;     // operation ends of one wave
   uint32_t tc;     // ceil(n/m) * d: clock of every terminal of this configuration
-  uint32_t pad[3];
+  uint32_t pad[4];
 };
-static_assert(sizeof(CfgRec) == 96, "CfgRec layout");
+static_assert(sizeof(CfgRec) == 128, "CfgRec layout");
 
 struct ModelHost {
   mc_desc desc{};
@@ -59,6 +69,7 @@ struct ModelHost {
   std::vector<CfgRec> cfgs;
   Layout layout{};
   uint32_t m = 0, n_cfg = 0, W = 1;
+  bool general = false;          // some configuration has waves or two-operation periods
   uint64_t states = 0;           // exact reachable count, root included
   uint64_t max_depth = 0;        // longest path (edges)
   uint32_t max_clock = 0;
@@ -93,6 +104,11 @@ uint64_t auto_part_states(uint64_t states);
 // An upper bound (exact for every configuration whose last round is not partial) on the
 // number of states with clock <= T, root included: what a check(T) inserts.  Sizes its
 // visited set only.
+// Operation ends of one workgroup of configuration r at or before time x.
+uint64_t ends_le(const CfgRec& r, uint64_t x);
+// Time of the k-th operation end (0-based, k < r.b) of one workgroup.
+uint64_t end_at_host(const CfgRec& r, uint64_t k);
+
 uint64_t count_le_bound(const ModelHost& h, uint64_t T);
 
 uint64_t binom(uint32_t n, uint32_t k);

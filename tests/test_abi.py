@@ -85,3 +85,67 @@ def test_batch_draws_agree(mc):
     a, ra = workloads.draw_batch(3, 64, lambda x: (mc.state_count(x) or budget + 1) <= budget)
     b, rb = workloads.draw_batch(3, 64, lambda x: cf.summary(x, with_E=False)["reachable"] <= budget)
     assert a == b and ra == rb
+
+
+# --- the unit-model kinds (abstract kernel, Minimum problem) --------------------------
+
+def _unit_sweep():
+    out = []
+    for seed in (31, 32):
+        out += workloads.tiny_unit_models(seed, 100, max_cu=8)
+    for kind in (workloads.KIND_ABSTRACT, workloads.KIND_MINIMUM):
+        for S, NP, gmt, loc in ((64, 4, 4, 1), (256, 2, 1, 3), (1024, 8, 9, 2)):
+            dom = workloads.pow2_range(0, 6)
+            out.append(workloads.unit_model(kind, S, NP, 3, dom, dom, gmt, loc))
+    return out
+
+
+def test_unit_kinds_config_ends_match_closed_form(mc):
+    """The library's per-configuration phase tables (waves, two-operation periods,
+    offset grids) give exactly the operation ends of the closed-form lists."""
+    n_cfg = 0
+    for model in _unit_sweep() + [f() for f in workloads.UNIT_WORKLOADS.values()]:
+        for c, row in enumerate(model["params"]):
+            n, ol = cf.ops(model, row)
+            E = cf.end_times(ol)
+            got = mc.mc_config_ends(model, c)
+            assert (got["n"], got["b"], got["d"]) == (n, len(E), E[-1]), workloads.describe(model)
+            assert got["E"] == E, (workloads.describe(model), row)
+            n_cfg += 1
+    assert n_cfg > 500
+
+
+def test_config_ends_uniform_kinds(mc):
+    for name, f in workloads.WORKLOADS.items():
+        model = f()
+        for c in range(0, len(model["params"]), 7):
+            n, ol = cf.ops(model, model["params"][c])
+            got = mc.mc_config_ends(model, c)
+            assert got["E"] == cf.end_times(ol) and got["n"] == n, name
+
+
+def test_unit_kinds_describe(mc):
+    for model in _unit_sweep():
+        d = mc.mc_describe(model)
+        s = cf.summary(model, with_E=False)
+        assert d["states"] == s["reachable"], workloads.describe(model)
+        assert d["max_depth"] + 1 == s["levels"]
+    want = {"abstract_s1024_np4_cu1": (1868340, 1), "abstract_s1024_np4_cu4": (2266564, 2),
+            "minimum_s1024_np4_cu4": (1052986, 2)}
+    for name, f in workloads.UNIT_WORKLOADS.items():
+        d = mc.mc_describe(f())
+        assert (d["states"], d["key_words"]) == want[name]
+        assert d["states"] == cf.summary(f(), with_E=False)["reachable"]
+
+
+@pytest.mark.parametrize("bad", [
+    {"S": 100}, {"NP": 3}, {"NP": 0}, {"params": [[3, 1, 0, 0]]}, {"params": [[1, 2048, 0, 0]]},
+    {"params": [[2048, 1, 0, 0]]},
+])
+def test_invalid_unit_descriptors(mc, bad):
+    model = dict(workloads.minimum_paper(1024, 2), **bad)
+    with pytest.raises(mc.McError) as e:
+        mc.mc_describe(model)
+    assert e.value.code == mc.MC_E_INVAL
+    with pytest.raises(mc.McError):
+        mc.mc_config_ends(model, 0)

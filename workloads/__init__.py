@@ -7,13 +7,15 @@ caller passes the filter in.
 
 A model is a plain dict:
 
-    {"kind": "reduction" | "matmul", "m": CU count,
-     "G": global size (reduction) | "M","N","K": matrix sizes (matmul),
+    {"kind": "reduction" | "matmul" | "abstract" | "minimum", "m": CU count,
+     "G": global size (reduction) | "M","N","K": matrix sizes (matmul) |
+     "S", "NP": data size and processing elements per unit (abstract, minimum),
      "Lg", "Ll", "Lc", "Lb": integer latencies,
      "params": [[p0, p1, p2, p3], ...]}     # one row per configuration
 
-Reduction rows are (WG, TS, 0, 0); matmul rows are (WGx, WGy, TS, VW).  Rows are in
-lexicographic order of the parameter domains unless a subset was drawn.
+Reduction, abstract and minimum rows are (WG, TS, 0, 0); matmul rows are
+(WGx, WGy, TS, VW).  Rows are in lexicographic order of the parameter domains unless a
+subset was drawn.
 """
 from __future__ import annotations
 
@@ -23,6 +25,8 @@ import numpy as np
 
 KIND_REDUCTION = "reduction"
 KIND_MATMUL = "matmul"
+KIND_ABSTRACT = "abstract"
+KIND_MINIMUM = "minimum"
 
 
 def latencies(seed: int) -> tuple[int, int]:
@@ -78,6 +82,46 @@ WORKLOADS = {
     "reduction_g256_cu2": reduction_g256,
     "matmul64_cu4": matmul_64,
     "matmul128_vw_cu8": matmul_128_vw,
+}
+
+
+# --- the paper's own unit models (abstract kernel, Minimum problem) ----------------------
+
+# Platform constants of the paper's abstract-model experiments: one device, units of
+# four processing elements, a global access GMT = 4 local steps of 1 (GMT is not
+# printed; 4 is the value under which the printed model times come out).
+PAPER_NP, PAPER_GMT, PAPER_LOCAL = 4, 4, 1
+
+
+def unit_model(kind: str, S: int, NP: int, m: int, wg_values, ts_values, Lg: int,
+               Ll: int = 1) -> dict:
+    params = [[wg, ts, 0, 0] for wg, ts in itertools.product(wg_values, ts_values)]
+    return {"kind": kind, "m": m, "S": S, "NP": NP, "Lg": Lg, "Ll": Ll, "Lc": 1, "Lb": 0,
+            "params": params}
+
+
+def paper_domain(S: int) -> list[int]:
+    """WG and TS values the parameter-selecting process picks from: 2 .. S/2."""
+    return pow2_range(1, S.bit_length() - 2)
+
+
+def abstract_paper(S: int = 1024, m: int = 1) -> dict:
+    """The abstract kernel on the paper's platform (units of 4 elements, GMT 4), every
+    (WG, TS) pair of the paper's domain; m = 1 is the single unit of its experiments."""
+    dom = paper_domain(S)
+    return unit_model(KIND_ABSTRACT, S, PAPER_NP, m, dom, dom, PAPER_GMT, PAPER_LOCAL)
+
+
+def minimum_paper(S: int = 1024, m: int = 4) -> dict:
+    """The Minimum problem model on the same platform and domain."""
+    dom = paper_domain(S)
+    return unit_model(KIND_MINIMUM, S, PAPER_NP, m, dom, dom, PAPER_GMT, PAPER_LOCAL)
+
+
+UNIT_WORKLOADS = {
+    "abstract_s1024_np4_cu1": lambda: abstract_paper(1024, 1),
+    "abstract_s1024_np4_cu4": lambda: abstract_paper(1024, 4),
+    "minimum_s1024_np4_cu4": lambda: minimum_paper(1024, 4),
 }
 
 
@@ -179,7 +223,30 @@ def tiny_models(seed: int, count: int, max_cu: int = 4) -> list[dict]:
     return out
 
 
+def tiny_unit_models(seed: int, count: int, max_cu: int = 3) -> list[dict]:
+    """Random tiny abstract / minimum models: S in 4..32, NP in {1,2,4}, GMT 1..5, local
+    step 1..3 (so GMT below, at and above it), CU counts 1..max_cu, a few (WG, TS)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        kind = KIND_ABSTRACT if rng.random() < 0.5 else KIND_MINIMUM
+        e = int(rng.integers(2, 6))
+        S = 1 << e
+        dom = [[wg, ts, 0, 0] for wg, ts in
+               itertools.product(pow2_range(0, min(e, 3)), pow2_range(0, min(e, 3)))]
+        k = int(rng.integers(1, min(len(dom), 5) + 1))
+        pick = np.sort(rng.choice(len(dom), size=k, replace=False))
+        out.append({"kind": kind, "m": int(rng.integers(1, max_cu + 1)), "S": S,
+                    "NP": int(rng.choice([1, 2, 4])), "Lg": int(rng.integers(1, 6)),
+                    "Ll": int(rng.integers(1, 4)), "Lc": 1, "Lb": 0,
+                    "params": [dom[int(i)] for i in pick]})
+    return out
+
+
 def describe(model: dict) -> str:
+    if model["kind"] in (KIND_ABSTRACT, KIND_MINIMUM):
+        return (f"{model['kind']}(S={model['S']}, NP={model['NP']}, m={model['m']}, "
+                f"GMT={model['Lg']}, local={model['Ll']}, #P={len(model['params'])})")
     if model["kind"] == KIND_REDUCTION:
         sz = f"G={model['G']}"
     else:
