@@ -171,6 +171,96 @@ def swarm_leg(mc, workloads, names, members: int = 16384, bits_log2: int = 16,
     return out
 
 
+def units_leg(mc, torch, workloads, reps: int = 5, cpu: bool = True):
+    """The paper's own unit models (abstract kernel, Minimum problem; NP elements per
+    unit, WG/NP waves) at S = 1024: the same step as the timed one (load + min_time +
+    trace + check(T_min - 1)) on the super-step engine built for general phases, with
+    its roofline figure and, on the CPU, the oracle on the same step."""
+    out = {}
+    for name, make in workloads.UNIT_WORKLOADS.items():
+        model = make()
+        nbytes = mc.mc_workspace_bytes(model)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+        run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = [run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0) for _ in range(reps)]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        del ws
+        states = sum(s["states"] for s in steps)
+        eng_s = sum(s["engine_ns_min"] for s in steps) * 1e-9 / reps
+        achieved = steps[0]["min_states"] * ALGO_BYTES_PER_STATE / eng_s / 1e9
+        rec = {"kind": model["kind"], "S": model["S"], "NP": model["NP"], "cu": model["m"],
+               "configurations": len(model["params"]), "GMT": model["Lg"], "local": model["Ll"],
+               "reachable": steps[0]["min_states"], "levels": steps[0]["levels"],
+               "t_min": steps[0]["t_min"], "argmin": steps[0]["argmin"],
+               "ms_per_step": 1e3 * elapsed / reps, "states_per_s": states / elapsed,
+               "min_time_engine_ms": eng_s * 1e3, "roofline_frac": achieved / HBM_PEAK_GBS,
+               "partitions": steps[0]["parts"]}
+        if cpu:
+            c = cpu_baseline(model, steps[0]["t_min"])
+            rec["cpu_oracle_states_per_s"] = c["value"]
+            rec["cpu_oracle_agrees"] = c["agrees"]
+            rec["gpu_over_cpu"] = rec["states_per_s"] / c["value"]
+        out[name] = rec
+        _progress(f"units leg: {name} {rec['ms_per_step']:.2f} ms/step")
+    return out
+
+
+def bb_leg(mc, torch, workloads, names, reps: int = 5):
+    """Step 3 of the method three ways on one handle: exhaustive min_time; a simulated
+    run's time T_ini followed by bisection over check(T) (the paper's loop); T_ini
+    followed by one branch-and-bound search.  Wall time per query (host clock, queries
+    synchronous) and the states each claimed."""
+    out = {}
+    for name in names:
+        model = (workloads.WORKLOADS.get(name) or workloads.UNIT_WORKLOADS[name])()
+        g = mc.Model(model)
+        g.mc_min_time()
+        g.mc_min_time_bb(0)
+        rec = {}
+
+        def timed(fn):
+            ts, res = [], None
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                res = fn()
+                ts.append(time.perf_counter() - t0)
+            return 1e3 * sorted(ts)[len(ts) // 2], res
+
+        ms, (t_min, _) = timed(g.mc_min_time)
+        rec["exhaustive"] = {"ms": ms, "states": g.last_stats["states"],
+                             "engine_ms": g.last_stats["engine_ns"] / 1e6}
+
+        def bisect():
+            return g.mc_tune_bisect(7)
+        ms, (t_b, n_checks) = timed(bisect)
+        rec["bisection"] = {"ms": ms, "checks": n_checks, "states": g.last_stats["states"],
+                            "engine_ms": g.last_stats["engine_ns"] / 1e6}
+
+        def bb():
+            t_ini, _ = g.mc_simulate(7)
+            return g.mc_min_time_bb(t_ini)
+        ms, (t_bb, _) = timed(bb)
+        rec["branch_and_bound"] = {"ms": ms, "states": g.last_stats["states"],
+                                   "engine_ms": g.last_stats["engine_ns"] / 1e6,
+                                   "clear_ms": g.last_stats["clear_ns"] / 1e6}
+        ms, (t_bb0, _) = timed(lambda: g.mc_min_time_bb(0))
+        rec["branch_and_bound_no_init"] = {"ms": ms, "states": g.last_stats["states"],
+                                           "engine_ms": g.last_stats["engine_ns"] / 1e6,
+                                           "clear_ms": g.last_stats["clear_ns"] / 1e6}
+        g.close()
+        assert t_min == t_b == t_bb == t_bb0
+        rec["t_min"] = t_min
+        rec["bb_speedup_vs_exhaustive"] = rec["exhaustive"]["ms"] / rec["branch_and_bound"]["ms"]
+        rec["bb_speedup_vs_bisection"] = rec["bisection"]["ms"] / rec["branch_and_bound"]["ms"]
+        out[name] = rec
+        _progress(f"bb leg: {name} exhaustive {rec['exhaustive']['ms']:.2f} ms, bisection "
+                  f"{rec['bisection']['ms']:.2f} ms, bb {rec['branch_and_bound']['ms']:.2f} ms")
+    return out
+
+
 def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int = 32):
     """Poisson arrivals of check(T)/min_time queries over a pool of models; continuous
     batching engine vs FIFO one-query-at-a-time service (fresh load per query)."""
@@ -268,7 +358,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--legs", default="plain,cpu,batch,serve,swarm",
+    ap.add_argument("--legs", default="plain,cpu,batch,serve,swarm,units,bb",
                     help="extra legs beside the timed single-query step")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -351,6 +441,15 @@ def main():
     if "swarm" in legs:
         _progress("swarm leg")
         swarm = swarm_leg(mc, workloads, [args.workload, "matmul128_vw_cu8"])
+    bbr = None
+    if "bb" in legs:
+        _progress("branch-and-bound leg")
+        bbr = bb_leg(mc, torch, workloads, [args.workload, "matmul128_vw_cu8",
+                                            "abstract_s1024_np4_cu4"])
+    units = None
+    if "units" in legs:
+        _progress("unit-model leg")
+        units = units_leg(mc, torch, workloads, cpu=not args.no_cpu and "cpu" in legs)
 
     cfg = {"workload": args.workload, "kind": model["kind"], "cu": model["m"],
            "configurations": len(model["params"]),
@@ -391,6 +490,8 @@ def main():
         "batched": batched,
         "served": served,
         "swarm": swarm,
+        "unit_models": units,
+        "branch_and_bound": bbr,
     }
     print(json.dumps(out), flush=True)
 

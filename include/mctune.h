@@ -198,6 +198,23 @@ int mc_model_info_get(const mc_model *h, mc_model_info *info);
 int mc_min_time(mc_model *h, uint32_t *t_min, uint32_t *argmin, size_t cap,
                 size_t *n_argmin, mc_stats *st);
 
+/* Branch-and-bound min_time: the single run that replaces the bisection of Sec. 4
+ * Step 3 (finding optimal values without repeated verifier runs is the paper's future
+ * work, Sec. 8).  The search prunes every state whose clock exceeds the incumbent, the
+ * least terminal clock found so far, which starts at T_init (0 = no initial bound, for
+ * instance the time of a simulated run, mc_simulate).  Clocks never decrease along a
+ * path and the incumbent never falls below T_min, so no state on a path to an optimal
+ * terminal is pruned: T_min and the configurations attaining it are exact, as from
+ * mc_min_time, and mc_trace gives a counterexample at T_min.  The statistics count the
+ * states this search claimed (between the count of clock <= T_min and that of clock
+ * <= T_init; the order of the concurrent search decides where), not the reachable
+ * set.  mc_terminal_clocks afterwards is exact for the argmin configurations only:
+ * others carry a clock found before the incumbent fell below it, or none.
+ * MC_E_STATE if no terminal has a clock <= T_init.  With the level engine the bound
+ * stays at T_init (a check(T_init) search that also reduces the terminal clocks). */
+int mc_min_time_bb(mc_model *h, uint32_t T_init, uint32_t *t_min, uint32_t *argmin, size_t cap,
+                   size_t *n_argmin, mc_stats *st);
+
 /* check(T): exhaustive exploration of the states with clock <= T (the clock never
  * decreases along a transition, so pruning at T is exact).  *violated = 1 iff some
  * terminal has clock <= T, i.e. G(FIN -> time > T) fails (Sec. 4, Step 2).

@@ -148,6 +148,8 @@ _SIGS = {
     "mc_min_time": ([_vp, _u32p, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t), _P(McStats)],
                     ctypes.c_int),
     "mc_check": ([_vp, ctypes.c_uint32, _P(ctypes.c_int), _P(McStats)], ctypes.c_int),
+    "mc_min_time_bb": ([_vp, ctypes.c_uint32, _u32p, _u32p, ctypes.c_size_t,
+                        _P(ctypes.c_size_t), _P(McStats)], ctypes.c_int),
     "mc_terminal_clocks": ([_vp, _u32p, ctypes.c_size_t], ctypes.c_int),
     "mc_trace": ([_vp, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t)], ctypes.c_int),
     "mc_simulate": ([_vp, ctypes.c_uint64, _u32p, _u32p], ctypes.c_int),
@@ -327,6 +329,19 @@ class Model:
         _check("mc_min_time", _lib.mc_min_time(self._h, ctypes.byref(t),
                                                arg.ctypes.data_as(_u32p), arg.shape[0],
                                                ctypes.byref(n), ctypes.byref(st)))
+        self.last_stats = st.as_dict()
+        return t.value, [int(v) for v in arg[:n.value]]
+
+    def mc_min_time_bb(self, T_init: int = 0) -> tuple[int, list[int]]:
+        """Branch-and-bound min_time (exact T_min and argmin; last_stats counts the states
+        the pruned search claimed).  T_init: initial incumbent, 0 = none."""
+        t = ctypes.c_uint32()
+        n = ctypes.c_size_t()
+        st = McStats()
+        arg = np.zeros(self.n_cfg, dtype=np.uint32)
+        _check("mc_min_time_bb", _lib.mc_min_time_bb(self._h, int(T_init), ctypes.byref(t),
+                                                     arg.ctypes.data_as(_u32p), arg.shape[0],
+                                                     ctypes.byref(n), ctypes.byref(st)))
         self.last_stats = st.as_dict()
         return t.value, [int(v) for v in arg[:n.value]]
 

@@ -225,7 +225,10 @@ int level_loop(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   return MC_OK;
 }
 
-int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
+// prune: drop states with clock > T.  bb (super-step engine): branch and bound, the
+// threshold falls to the least terminal clock found so far and partitions are taken
+// smallest first.
+int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = h->stream;
   h->trace_ready = false;
@@ -266,6 +269,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     md.T = T;
     md.max_clock = h->mh.max_clock;
     md.n_parts = h->n_parts;
+    md.bb = bb ? 1u : 0u;
     md.pstate = nullptr;
     HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
     HIPCHK(launch_reset_models(s, h->dmd, 1, h->head, 1));
@@ -280,7 +284,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st) {
     pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
     pq.head = h->head;
     pq.slice = 0u;
-    pq.pad = 0u;
+    pq.reverse = bb ? 1u : 0u;
     pq.yielded = nullptr;
     pq.n_yielded = nullptr;
     const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
@@ -574,6 +578,37 @@ int mc_min_time(mc_model* h, uint32_t* t_min, uint32_t* argmin, size_t cap, size
     uint32_t best = kNoClock;
     for (uint32_t c = 0; c < h->mh.n_cfg; ++c) best = std::min(best, h->tc_host[c]);
     if (best == kNoClock) return MC_E_STATE;
+    size_t n = 0;
+    for (uint32_t c = 0; c < h->mh.n_cfg; ++c) {
+      if (h->tc_host[c] != best) continue;
+      if (argmin && n < cap) argmin[n] = c;
+      ++n;
+    }
+    *t_min = best;
+    *n_argmin = n;
+    h->last = kQueryMin;
+    h->last_T = best;
+    return n > cap && argmin ? MC_E_BUFFER : MC_OK;
+  } catch (...) {
+    return MC_E_DEVICE;
+  }
+}
+
+int mc_min_time_bb(mc_model* h, uint32_t T_init, uint32_t* t_min, uint32_t* argmin, size_t cap,
+                   size_t* n_argmin, mc_stats* st) {
+  if (!h || !t_min || !n_argmin) return MC_E_INVAL;
+  try {
+    const uint32_t T = T_init ? T_init : kNoClock - 1u;
+    const int rc = run_query(h, true, T, st, h->opts.engine == MC_ENGINE_SUPERSTEP);
+    if (rc) return rc;
+    uint32_t best = kNoClock;
+    for (uint32_t c = 0; c < h->mh.n_cfg; ++c) best = std::min(best, h->tc_host[c]);
+    h->last = kQueryCheck;  // what the table holds: the states of a pruned search
+    h->last_T = T;
+    h->last_violated = 0;
+    if (best == kNoClock) return MC_E_STATE;  // no terminal within T_init
+    // configurations whose terminal was found before the incumbent fell below it may
+    // carry a larger clock: only those at the least clock are the optimum
     size_t n = 0;
     for (uint32_t c = 0; c < h->mh.n_cfg; ++c) {
       if (h->tc_host[c] != best) continue;

@@ -188,7 +188,7 @@ int enqueue_query(mc_batch* b) {
         b->opts.chunk ? b->opts.chunk : 2u * lane_items_for(li, 1u << w) * b->opts.block;
     pq[w].head = b->head + w;
     pq[w].slice = 0u;
-    pq[w].pad = 0u;
+    pq[w].reverse = 0u;
     pq[w].yielded = nullptr;
     pq[w].n_yielded = nullptr;
   }

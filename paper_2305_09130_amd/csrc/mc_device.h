@@ -32,7 +32,9 @@ struct Ctrl {
   unsigned long long chunks;     // insert batches (persistent engine)
   unsigned long long crit_ticks; // longest partition time, 100 MHz ticks
   unsigned int parts_done;       // partitions explored to the end (resumable queues)
-  unsigned int pad[7];
+  unsigned int bound;            // branch-and-bound min_time: least terminal clock found
+                                 // so far (starts at the query's T)
+  unsigned int pad[6];
 };
 static_assert(sizeof(Ctrl) == 160, "Ctrl layout");
 

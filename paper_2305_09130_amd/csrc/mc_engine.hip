@@ -445,7 +445,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
           e->opts.chunk ? e->opts.chunk : 2u * lane_items_for(li, 1u << g) * e->opts.block;
       pq[g].head = head + g;
       pq[g].slice = slice;
-      pq[g].pad = 0;
+      pq[g].reverse = 0u;
       pq[g].yielded = next;
       pq[g].n_yielded = ny;
       grid[g] = std::max<uint32_t>(1u, std::min<uint32_t>(gn[g], e->opts.grid ? e->opts.grid : 1024u));

@@ -326,6 +326,7 @@ struct SuperShared {
   // generates it, and whether it was reached
   unsigned long long stopkey[4];
   uint32_t has_stop, stop_clock, stop_dep, stop_item, stop_slot, handed;
+  uint32_t T;   // prune threshold of this super-step (check(T), or the incumbent)
   ModelDev md;  // descriptor of the model being explored
   // successors of the leaves of a segment whose run is not in lock step (one ADVANCE
   // each), computed once per super-step outside the batch loop
@@ -438,10 +439,20 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
       for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[leaf][w];
     }
   }
-  if (md.prune && it.clk > md.T) it.active = false;
+  if (md.prune && it.clk > sh.T) it.active = false;
 }
 
 __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
+
+// Prune threshold: the query's T, or under branch and bound the least terminal clock
+// found so far when that is lower.  The incumbent only falls, so a stale value prunes
+// less, never wrongly: every state on a path to an optimal terminal has a clock at most
+// T_min, which never exceeds the incumbent.
+__device__ __forceinline__ uint32_t prune_T(const ModelDev& md) {
+  if (!md.bb) return md.T;
+  const uint32_t b = __hip_atomic_load(&md.ctrl->bound, __ATOMIC_RELAXED, kScopeAgent);
+  return b < md.T ? b : md.T;
+}
 
 template <int W, int BLOCK, int NI, bool GEN>
 __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t batch_items,
@@ -460,6 +471,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     sh.has_stop = 0u;
     sh.handed = 0u;
     sh.stop_item = kNoItem;
+    sh.T = prune_T(md);
     const Seed sd = md.seeds[c];
     const uint32_t round_dep = (uint32_t)m + r.b;  // m dispatches, b advances
     if (pt.r1 != kRoundsToEnd) {
@@ -492,7 +504,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         field_add<W>(k0, L, kFClock, (unsigned long long)pt.r0 * r.d);
         field_add<W>(k0, L, kFPending, (unsigned long long)(-(long long)pt.r0 * m));
         dep0 = sd.depth + pt.r0 * round_dep;
-        if (md.prune && (unsigned long long)pt.r0 * r.d > md.T) {
+        if (md.prune && (unsigned long long)pt.r0 * r.d > sh.T) {
           sh.fcount[0] = 0u;
         } else {
           Key<W> k;
@@ -542,6 +554,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     for (uint32_t fi = 0; fi < nf; ++fi) {
       // ---- segments of this super-step (one thread builds them) ----
       if (tid == 0) {
+        sh.T = prune_T(md);
         Key<W> ck;
 #pragma unroll
         for (int w = 0; w < W; ++w) ck.w[w] = sh.fkey[cur][fi][w];
@@ -638,7 +651,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
               if (!ok) {
                 set_error(md.ctrl, kDevErrSplit);
                 sh.stop = 1u;
-              } else if (!(md.prune && end_clock > md.T)) {
+              } else if (!(md.prune && end_clock > sh.T)) {
                 // shared with the next block: agent-scope ordering
                 uint32_t slot = kParentNone;
                 const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, tl.probes);
@@ -662,7 +675,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           }
           const bool more = sg.lock && sg.nleaf == 1u && sg.pend > 0u &&
                             nseg < (uint32_t)kSegMax && total < batch_items &&
-                            !(md.prune && end_clock > md.T) && end_clock <= md.max_clock;
+                            !(md.prune && end_clock > sh.T) && end_clock <= md.max_clock;
           if (!more) break;
           // the run end: every unit idle, `pend` workgroups pending
           unsigned long long ek[W];
@@ -789,6 +802,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
                 ++tl.terms;
                 atomicMin(&md.tc[c], it[n].clk);
                 if (md.prune) md.ctrl->violated = 1u;
+                if (md.bb) atomicMin(&md.ctrl->bound, it[n].clk);
               }
             } else {
               ++tl.dups;
@@ -859,7 +873,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
   if (!yielded && tid == 0) {
     // a block that did not reach B_r1 (unless pruned away or stopped by an error) would
     // leave part of the subgraph unexplored
-    if (sh.has_stop && !sh.handed && !sh.stop && !(md.prune && sh.stop_clock > md.T) &&
+    if (sh.has_stop && !sh.handed && !sh.stop && !(md.prune && sh.stop_clock > prune_T(md)) &&
         __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) == 0u)
       set_error(md.ctrl, kDevErrSplit);
     if (md.pstate) md.pstate[pt.pidx].status = 2u;
@@ -890,7 +904,7 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     __syncthreads();
     const uint32_t part = sh.part;
     if (part >= a.n_parts) break;
-    const Part pc = a.parts[part];
+    const Part pc = a.parts[a.reverse ? a.n_parts - 1u - part : part];
     if (tid == 0) sh.md = a.models[pc.model];
     __syncthreads();
     const ModelDev& md = sh.md;
@@ -964,7 +978,9 @@ __global__ __launch_bounds__(256) void k_seed_models(const ModelDev* models) {
 __global__ void k_reset_models(const ModelDev* models, unsigned int* head, uint32_t n_heads) {
   const ModelDev md = models[blockIdx.x];
   unsigned int* cw = reinterpret_cast<unsigned int*>(md.ctrl);
-  for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) cw[i] = 0u;
+  constexpr uint32_t kBoundWord = offsetof(Ctrl, bound) / 4;
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x)
+    cw[i] = i == kBoundWord ? md.T : 0u;
   for (uint32_t i = threadIdx.x; i < md.n_cfg; i += blockDim.x) md.tc[i] = kNoClock;
   if (md.pstate)
     for (uint32_t i = threadIdx.x; i < md.n_parts; i += blockDim.x) md.pstate[i].status = 0u;

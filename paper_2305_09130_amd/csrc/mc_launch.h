@@ -69,7 +69,8 @@ struct ModelDev {
   uint32_t T;
   uint32_t max_clock;
   uint32_t n_parts;   // partitions of the model (entries of pstate)
-  uint32_t pad;
+  uint32_t bb;        // branch and bound: prune at min(T, ctrl->bound), every new
+                      // terminal lowers ctrl->bound
   PartState* pstate;  // one per partition when partitions may yield, else null
   unsigned long long pad2;
 };
@@ -93,7 +94,7 @@ struct PartQueue {
   uint32_t batch_items;  // states generated per super-step batch before waiting (target)
   unsigned int* head;
   uint32_t slice;        // super-step levels per partition before it yields (0 = no limit)
-  uint32_t pad;
+  uint32_t reverse;      // take the partitions smallest first
   Part* yielded;         // partitions that yielded, for the next launch
   unsigned int* n_yielded;
 };
