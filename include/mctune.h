@@ -48,6 +48,19 @@
  *       workgroup as in the kernel.
  *   d_c is the workgroup duration; E_c the distinct cumulative operation end times.
  *
+ * Units of unequal speed (the assumption of Sec. 4 that every unit works alike,
+ * dropped): unit i takes s_i cycles per cycle of work, so a workgroup on it ends its
+ * operations at s_i*E_c and lasts s_i*d_c; DISPATCH(i) sets rem_i := s_i*d_c and ADVANCE
+ * moves to the next end on any unit's own grid.  Which free units take the last
+ * workgroups now changes the makespan.  Dispatch stays eager, so while at least as many
+ * workgroups are pending as units are idle the run is determined; the first instant with
+ * fewer splits it into one tail per choice of units.  There is no closed-form count:
+ * sizes come from walking that determined part and every tail (a tail's states are
+ * counted even where tails meet, so the count is an upper bound, exact on the
+ * determined part).  Round blocks are not cut for such models, and the graph is no
+ * longer graded (tails meet at different depths): `levels` of the super-step engine is
+ * then the depth of each state's first claim, not its BFS depth.
+ *
  * Conventions.  Every call returns an int: MC_OK (0) or a negative MC_E_* code; no
  * call aborts and no C++ exception crosses the ABI.  Device pointers are plain
  * hipMalloc'd (or torch-allocated) device addresses; host pointers are ordinary host
@@ -101,7 +114,12 @@ typedef struct mc_desc {
                                 minimum (WG, TS, 0, 0), matmul (WGx, WGy, TS, VW); VW = 0
                                 means 1.  Powers of two; sizes must divide as the
                                 operation lists require. */
+    const uint32_t *unit_speed; /* host pointer, n_cu entries in 1..MC_MAX_SPEED, or NULL
+                                (all 1): unit i runs every operation unit_speed[i] times
+                                as long (see "Units of unequal speed" above) */
 } mc_desc;
+
+#define MC_MAX_SPEED 64u
 
 /* ---- options ------------------------------------------------------------------- */
 #define MC_ENGINE_SUPERSTEP 0u /* persistent kernel, one configuration's subgraph per

@@ -48,7 +48,7 @@ class _Model(ctypes.Structure):
                 ("Lg", ctypes.c_uint32), ("Ll", ctypes.c_uint32),
                 ("Lc", ctypes.c_uint32), ("Lb", ctypes.c_uint32),
                 ("n_cfg", ctypes.c_uint32), ("params", ctypes.POINTER(ctypes.c_uint32)),
-                ("tick", ctypes.c_int32)]
+                ("tick", ctypes.c_int32), ("speed", ctypes.c_uint32 * 16)]
 
 
 class _Result(ctypes.Structure):
@@ -103,6 +103,8 @@ def _model(model: dict, tick: bool = False):
                 model.get("K", 0), model.get("S", 0), model.get("NP", 0),
                 model["Lg"], model["Ll"], model.get("Lc", 1), model.get("Lb", 0),
                 params.shape[0], _u32p(params), 1 if tick else 0)
+    for i, v in enumerate(model.get("speed") or []):
+        mo.speed[i] = int(v)
     return mo, params  # keep params alive
 
 

@@ -84,18 +84,19 @@ def enumerate_model(model: dict, max_paths: int = 2_000_000) -> dict:
     lengths = {}
     npaths = 0
 
+    speed = list(model.get("speed") or [1] * m)  # unit i runs every operation speed[i] times as long
     for c, row in enumerate(model["params"]):
         n, prog = workgroup_program(model, row)
         total = sum(prog)
 
-        def rem_of(u):
+        def rem_of(i, u):
             if u is None:
                 return 0
             op, left = u
-            return left + sum(prog[op + 1:])
+            return left + speed[i] * sum(prog[op + 1:])
 
         def snap(clock, pending, units):
-            return (c, clock, pending) + tuple(rem_of(u) for u in units)
+            return (c, clock, pending) + tuple(rem_of(i, u) for i, u in enumerate(units))
 
         # iterative DFS; frame = (clock, pending, units tuple, depth)
         start = (0, n, (None,) * m, 1)
@@ -108,7 +109,7 @@ def enumerate_model(model: dict, max_paths: int = 2_000_000) -> dict:
                 for i in free:
                     op = _skip_free(prog, 0)
                     nu = list(units)
-                    nu[i] = (op, prog[op]) if op < len(prog) else None
+                    nu[i] = (op, speed[i] * prog[op]) if op < len(prog) else None
                     nu = tuple(nu)
                     states.add(snap(clock, pending - 1, nu))
                     stack.append((clock, pending - 1, nu, depth + 1))
@@ -133,13 +134,13 @@ def enumerate_model(model: dict, max_paths: int = 2_000_000) -> dict:
                     if left == 0:
                         event = True
                         op = _skip_free(prog, op + 1)
-                        us[i] = (op, prog[op]) if op < len(prog) else None
+                        us[i] = (op, speed[i] * prog[op]) if op < len(prog) else None
                     else:
                         us[i] = (op, left)
                 if event:
                     break
             nu = tuple(us)
-            assert clock <= n * total
+            assert clock <= n * total * max(speed)
             states.add(snap(clock, pending, nu))
             stack.append((clock, pending, nu, depth + 1))
     return {"states": states,
@@ -147,8 +148,8 @@ def enumerate_model(model: dict, max_paths: int = 2_000_000) -> dict:
             "lengths": lengths, "paths": npaths}
 
 
-def summary(model: dict) -> dict:
-    e = enumerate_model(model)
+def summary(model: dict, max_paths: int = 2_000_000) -> dict:
+    e = enumerate_model(model, max_paths)
     tc = [min(e["terminal_clocks"][c]) for c in range(len(model["params"]))]
     t_min = min(tc)
     return {"reachable": len(e["states"]), "tc": tc, "t_min": t_min,

@@ -82,6 +82,7 @@ typedef struct {
     uint32_t n_cfg;
     const uint32_t *params; /* n_cfg rows of 4 values */
     int32_t tick;           /* 1: the clock advances one cycle per step (test variant) */
+    uint32_t speed[OR_MAX_CU]; /* cycles a unit takes per cycle of work (0 or 1: full speed) */
 } or_model;
 
 typedef struct {
@@ -341,11 +342,17 @@ static int64_t set_insert(or_set *s, const uint32_t *w, uint32_t parent, uint32_
 
 /* ---- successor function -------------------------------------------------------- */
 
-/* smallest x in E with x > e; E is increasing and e < last(E) */
-static uint32_t next_end(const or_cfg *cf, uint32_t e) {
+static uint32_t unit_speed(const or_model *mo, uint32_t i) {
+    return mo->speed[i] ? mo->speed[i] : 1u;
+}
+
+/* A unit of speed s runs every operation s times as long: its operation ends within a
+ * workgroup are s*E and the workgroup lasts s*d.  Smallest s*x, x in E, with s*x > e,
+ * for 0 <= e < s*d. */
+static uint32_t next_end(const or_cfg *cf, uint32_t s, uint32_t e) {
     for (uint32_t k = 0; k < cf->b; k++)
-        if (cf->E[k] > e) return cf->E[k];
-    return cf->d; /* unreachable for a busy unit */
+        if ((uint64_t)s * cf->E[k] > e) return s * cf->E[k];
+    return s * cf->d; /* unreachable for a busy unit */
 }
 
 /*
@@ -374,7 +381,7 @@ static uint32_t successors(const or_model *mo, const or_cfg *cfs, const uint32_t
             uint32_t *y = out + (uint64_t)k++ * S;
             memcpy(y, x, sizeof(uint32_t) * S);
             y[2] = x[2] - 1;
-            y[3 + i] = cf->d;
+            y[3 + i] = unit_speed(mo, i) * cf->d;
         }
         if (k) return k;
     }
@@ -387,8 +394,9 @@ static uint32_t successors(const or_model *mo, const or_cfg *cfs, const uint32_t
     } else {
         for (uint32_t i = 0; i < m; i++) {
             if (!rem[i]) continue;
-            uint32_t e = cf->d - rem[i];
-            uint32_t di = next_end(cf, e) - e;
+            uint32_t s = unit_speed(mo, i);
+            uint32_t e = s * cf->d - rem[i];
+            uint32_t di = next_end(cf, s, e) - e;
             if (di < delta) delta = di;
         }
     }
@@ -539,16 +547,20 @@ int or_explore(const or_model *mo, int prune, uint32_t T, int self_check, or_res
     res->levels = maxdepth + 1;
 
     if (self_check && !prune) {
-        /* every unit permutation of a reachable state is reachable: test transpositions */
+        /* swapping two units of equal speed maps a reachable state to a reachable one:
+           test the transpositions of each unit with the first unit of its speed */
         uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * S);
         if (!y) { rc = OR_E_NOMEM; goto done; }
         for (uint64_t k = 0; k < set.count && !(flags & OR_CHK_PERMUTE); k++) {
             const uint32_t *z = set.st + k * S;
             if (z[0] == OR_ROOT) continue;
             for (uint32_t i = 1; i < m; i++) {
+                uint32_t f = 0;
+                while (unit_speed(mo, f) != unit_speed(mo, i)) f++;
+                if (f == i) continue;
                 memcpy(y, z, sizeof(uint32_t) * S);
-                y[3] = z[3 + i];
-                y[3 + i] = z[3];
+                y[3 + f] = z[3 + i];
+                y[3 + i] = z[3 + f];
                 if (set_find(&set, y) < 0) { flags |= OR_CHK_PERMUTE; break; }
             }
         }

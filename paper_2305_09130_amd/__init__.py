@@ -42,7 +42,7 @@ class McDesc(ctypes.Structure):
                 ("size", ctypes.c_uint32 * 3), ("lat_global", ctypes.c_uint32),
                 ("lat_local", ctypes.c_uint32), ("lat_compute", ctypes.c_uint32),
                 ("lat_barrier", ctypes.c_uint32), ("n_cfg", ctypes.c_uint32),
-                ("params", _u32p)]
+                ("params", _u32p), ("unit_speed", _u32p)]
 
 
 class McOpts(ctypes.Structure):
@@ -198,8 +198,8 @@ def _check(where: str, rc: int) -> None:
         raise McError(where, rc)
 
 
-def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
-    """McDesc of a model dict (see workloads); returns the params array to keep alive."""
+def make_desc(model: dict) -> tuple[McDesc, tuple]:
+    """McDesc of a model dict (see workloads); returns the arrays to keep alive."""
     params = np.ascontiguousarray(np.asarray(model["params"], dtype=np.uint32).reshape(-1, 4))
     d = McDesc()
     kind = model["kind"]
@@ -219,7 +219,11 @@ def make_desc(model: dict) -> tuple[McDesc, np.ndarray]:
     d.lat_compute, d.lat_barrier = model.get("Lc", 1), model.get("Lb", 0)
     d.n_cfg = params.shape[0]
     d.params = params.ctypes.data_as(_u32p)
-    return d, params
+    speed = None
+    if model.get("speed") is not None:
+        speed = np.ascontiguousarray(np.asarray(model["speed"], dtype=np.uint32))
+        d.unit_speed = speed.ctypes.data_as(_u32p)
+    return d, (params, speed)
 
 
 def make_opts(engine: int = MC_ENGINE_SUPERSTEP, block: int = 0, log2_slots: int = 0,

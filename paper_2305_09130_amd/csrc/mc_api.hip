@@ -736,6 +736,7 @@ SwarmArgs swarm_args(mc_model* h, const mc_swarm_opts& o, const SwarmPlan& p) {
   a.T = o.T;
   a.bits = reinterpret_cast<uint32_t*>(h->table + p.bits);
   a.out = reinterpret_cast<SwarmMember*>(h->table + p.rec);
+  for (int u = 0; u < kMaxCU; ++u) a.speed[u] = h->mh.layout.speed[u];
   return a;
 }
 

@@ -252,15 +252,34 @@ __device__ __forceinline__ uint32_t end_at_t(const CfgRec& r, uint32_t k) {
   else return end_at_uniform(r, k);
 }
 
-// One ADVANCE step: the clock moves to the next operation end of any busy unit.
+// Workgroup duration on unit u: a unit of speed s runs every operation s times as long
+// (its operation ends are s*E, its workgroup lasts s*d).  The uniform-phase build only
+// runs models whose units all have speed 1.
+template <bool GEN>
+__device__ __forceinline__ uint32_t unit_dur(const CfgRec& r, const uint8_t* speed, int u) {
+  if constexpr (GEN) return (uint32_t)speed[u] * r.d;
+  else return r.d;
+}
+
+// One ADVANCE step: the clock moves to the next operation end of any busy unit, on that
+// unit's own grid s*E (speed null: every unit at speed 1).
 template <bool GEN = true>
-__device__ __forceinline__ void advance_once(St& s, const CfgRec& r, int m) {
+__device__ __forceinline__ void advance_once(St& s, const CfgRec& r, int m,
+                                             const uint8_t* speed = nullptr) {
   uint32_t delta = 0xFFFFFFFFu;
 #pragma unroll
   for (int i = 0; i < kMaxCU; ++i) {
     if (i < m && s.rem[i]) {
-      const uint32_t e = r.d - s.rem[i];
-      const uint32_t di = end_at_t<GEN>(r, ends_upto_t<GEN>(r, e)) - e;
+      uint32_t di;
+      if (GEN && speed && speed[i] != 1u) {
+        // elapsed e < sp*d; the next end sp*E[k] > e has E[k] > floor(e / sp)
+        const uint32_t sp = speed[i];
+        const uint32_t e = sp * r.d - s.rem[i];
+        di = sp * end_at_t<GEN>(r, ends_upto_t<GEN>(r, e / sp)) - e;
+      } else {
+        const uint32_t e = r.d - s.rem[i];
+        di = end_at_t<GEN>(r, ends_upto_t<GEN>(r, e)) - e;
+      }
       delta = di < delta ? di : delta;
     }
   }

@@ -171,13 +171,13 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
     const bool dispatch = valid && x.pending > 0 && freem != 0;
     const bool advance = valid && !dispatch && busy != 0;
     St adv = x;
-    if (advance) advance_once(adv, r, m);
+    if (advance) advance_once(adv, r, m, q.L.speed);
 #pragma unroll
     for (int j = 0; j < kMaxCU; ++j) {
       bool has = false;
       St y = x;
       if (dispatch && ((freem >> j) & 1u)) {
-        y.rem[j] = r.d;
+        y.rem[j] = unit_dur<true>(r, q.L.speed, j);
         y.pending -= 1u;
         has = true;
       } else if (advance && j == 0) {
@@ -306,7 +306,7 @@ struct SegDesc {
   uint32_t start, nclos, nleaf, len;
   uint32_t kstar, freem, lock, idx0;
   uint32_t e0, fclock, pend, fdep;
-  uint32_t fslot, nfree, aux, pad;
+  uint32_t fslot, nfree, aux, pad;  // pad: 1 for a chain (states listed in gkey)
 };
 
 template <int BLOCK, int NI>
@@ -392,7 +392,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
 #pragma unroll
       for (int u = 0; u < kMaxCU; ++u) {
         if ((sg.freem >> u) & 1u) {
-          if ((it.rmask >> t) & 1u) field_add<W>(it.key, L, kFRem + u, r.d);
+          if ((it.rmask >> t) & 1u) field_add<W>(it.key, L, kFRem + u, unit_dur<GEN>(r, L.speed, u));
           ++t;
         }
       }
@@ -432,11 +432,12 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
     }
     it.term = sg.pend == 0u && e == r.d;
   } else {
-    it.clk = sh.gclk[leaf];
-    it.term = sh.gterm[leaf] != 0u;
+    const uint32_t gi = sg.pad ? it.j : leaf;  // a chain lists its states in order
+    it.clk = sh.gclk[gi];
+    it.term = sh.gterm[gi] != 0u;
     if (KEY) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[leaf][w];
+      for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[gi][w];
     }
   }
   if (md.prune && it.clk > sh.T) it.active = false;
@@ -592,7 +593,8 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             uint32_t nleaf = 1;  // C(nfree, kstar)
             for (uint32_t i = 1; i <= kstar; ++i) nleaf = nleaf * (nfree - kstar + i) / i;
             sg.nleaf = nleaf;
-            const bool lock = kstar ? (busy == 0u) : bsame;
+            // units of unequal speed leave lock step at once: one ADVANCE per leaf
+            const bool lock = !(GEN && L.hetero) && (kstar ? (busy == 0u) : bsame);
             sg.lock = lock ? 1u : 0u;
             sg.e0 = kstar ? 0u : r.d - brem;
             sg.idx0 = lock ? ends_upto_t<GEN>(r, sg.e0) : 0u;
@@ -617,6 +619,32 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
               sg.M[w] = Mv[w];
             }
             sg.aux = (kstar && busy == 0u && nleaf == 1u) ? 1u : 0u;  // a full round start
+            sg.pad = 0u;
+            if (GEN && L.hetero && !lock && kstar == 0u) {
+              // units of unequal speed with nothing to dispatch: the ADVANCE steps up to the
+              // next state with a dispatch (or the terminal) are determined, so this thread
+              // lists up to kMaxLeaves of them as one segment (a chain)
+              St y = x;
+              uint32_t len = 0;
+              for (;;) {
+                advance_once<GEN>(y, r, m, L.speed);
+                const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+                for (int w = 0; w < W; ++w) sh.gkey[len][w] = yk.w[w];
+                sh.gclk[len] = y.clock;
+                const bool term = is_terminal(y, m);
+                sh.gterm[len] = term ? 1u : 0u;
+                ++len;
+                bool idle = false;
+#pragma unroll
+                for (int u = 0; u < kMaxCU; ++u) idle |= u < m && y.rem[u] == 0u;
+                if (term || (y.pending && idle) || len == (uint32_t)kMaxLeaves ||
+                    (md.prune && y.clock > sh.T))
+                  break;
+              }
+              sg.len = len;
+              sg.pad = 1u;
+            }
           }
           sg.fdep = fdep;
           sg.fslot = fslot;
@@ -729,7 +757,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         }
         __syncthreads();
       }
-      if (nseg && !sh.seg[nseg - 1].lock) {
+      if (nseg && !sh.seg[nseg - 1].lock && !sh.seg[nseg - 1].pad) {
         // one ADVANCE from every leaf of a run that is not in lock step
         const SegDesc& sg = sh.seg[nseg - 1];
         if (tid < sg.nleaf && tid < (uint32_t)kMaxLeaves) {
@@ -743,12 +771,12 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
 #pragma unroll
           for (int u = 0; u < kMaxCU; ++u) {
             if ((sg.freem >> u) & 1u) {
-              if ((rmask >> t) & 1u) y.rem[u] = r.d;
+              if ((rmask >> t) & 1u) y.rem[u] = unit_dur<GEN>(r, L.speed, u);
               ++t;
             }
           }
           y.pending -= sg.kstar;
-          advance_once<GEN>(y, r, m);
+          advance_once<GEN>(y, r, m, L.speed);
           const Key<W> yk = encode<W>(y, L);
 #pragma unroll
           for (int w = 0; w < W; ++w) sh.gkey[tid][w] = yk.w[w];
@@ -1105,6 +1133,7 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
 __global__ void k_simulate(QueryArgs a, unsigned long long seed) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int m = a.L.m;
+  const uint8_t* speed = a.L.speed;
   unsigned long long step = 0;
   const uint32_t c = (uint32_t)(splitmix64(seed ^ splitmix64(step)) % a.n_cfg);
   ++step;
@@ -1113,14 +1142,15 @@ __global__ void k_simulate(QueryArgs a, unsigned long long seed) {
   x.cfg = c;
   x.pending = r.n;
   for (;;) {
-    uint32_t freem = 0, busy = 0, brem = 0;
+    uint32_t freem = 0, busy = 0, brem = 0, bsp = 0;
     bool same = true;
     for (int u = 0; u < m; ++u) {
       if (x.rem[u] == 0u) {
         freem |= 1u << u;
       } else {
-        if (busy && x.rem[u] != brem) same = false;
+        if (busy && (x.rem[u] != brem || speed[u] != bsp)) same = false;
         brem = x.rem[u];
+        bsp = speed[u];
         busy |= 1u << u;
       }
     }
@@ -1131,7 +1161,7 @@ __global__ void k_simulate(QueryArgs a, unsigned long long seed) {
       for (int u = 0; u < m; ++u) {
         if ((freem >> u) & 1u) {
           if (pick == 0u) {
-            x.rem[u] = r.d;
+            x.rem[u] = unit_dur<true>(r, speed, u);
             x.pending -= 1u;
             break;
           }
@@ -1142,12 +1172,13 @@ __global__ void k_simulate(QueryArgs a, unsigned long long seed) {
     }
     if (!busy) break;
     if (same) {
-      const uint32_t e0 = r.d - brem;
-      step += r.b - ends_upto(r, e0);
+      // busy units in lock step (equal speed and time left): one step per end to go
+      const uint32_t e0 = bsp * r.d - brem;
+      step += r.b - ends_upto(r, e0 / bsp);
       x.clock += brem;
       for (int u = 0; u < m; ++u) x.rem[u] = 0u;
     } else {
-      advance_once(x, r, m);
+      advance_once(x, r, m, speed);
       ++step;
     }
   }
@@ -1184,19 +1215,20 @@ __device__ __forceinline__ unsigned long long swarm_hash(const St& x, int m) {
 }
 
 // successor count of a non-root state, its free and busy units, and whether the busy
-// units are in lock step (equal remaining time)
+// units are in lock step (equal speed and remaining time)
 struct SwarmView {
-  uint32_t k, freem, busy, brem;
+  uint32_t k, freem, busy, brem, bsp;
   bool same;
 };
-__device__ __forceinline__ SwarmView swarm_view(const St& x, int m) {
-  SwarmView v{0u, 0u, 0u, 0u, true};
+__device__ __forceinline__ SwarmView swarm_view(const St& x, int m, const uint8_t* speed) {
+  SwarmView v{0u, 0u, 0u, 0u, 1u, true};
   for (int u = 0; u < m; ++u) {
     if (x.rem[u] == 0u) {
       v.freem |= 1u << u;
     } else {
-      if (v.busy && x.rem[u] != v.brem) v.same = false;
+      if (v.busy && (x.rem[u] != v.brem || speed[u] != v.bsp)) v.same = false;
       v.brem = x.rem[u];
+      v.bsp = speed[u];
       v.busy |= 1u << u;
     }
   }
@@ -1205,11 +1237,11 @@ __device__ __forceinline__ SwarmView swarm_view(const St& x, int m) {
 }
 
 __device__ __forceinline__ void swarm_dispatch(St& x, const CfgRec& r, uint32_t freem,
-                                               uint32_t pick, int m) {
+                                               uint32_t pick, int m, const uint8_t* speed) {
   for (int u = 0; u < m; ++u) {
     if ((freem >> u) & 1u) {
       if (pick == 0u) {
-        x.rem[u] = r.d;
+        x.rem[u] = unit_dur<true>(r, speed, u);
         x.pending -= 1u;
         return;
       }
@@ -1245,7 +1277,7 @@ __global__ __launch_bounds__(256) void k_swarm(SwarmArgs a) {
     x.pending = r.n;
     for (;;) {  // x was just reached by a transition
       if (a.prune && x.clock > a.T) break;
-      const SwarmView v = swarm_view(x, m);
+      const SwarmView v = swarm_view(x, m, a.speed);
       if (v.k != 1u) {
         const unsigned long long h = swarm_hash(x, m);
         const unsigned long long p0 = h & (B - 1ull), p1 = (h >> 32) & (B - 1ull);
@@ -1273,15 +1305,16 @@ __global__ __launch_bounds__(256) void k_swarm(SwarmArgs a) {
       if (x.pending && v.freem) {  // DISPATCH
         const uint32_t pick = (uint32_t)(splitmix64(seed ^ splitmix64(t)) % v.k);
         ++t;
-        swarm_dispatch(x, r, v.freem, pick, m);
+        swarm_dispatch(x, r, v.freem, pick, m, a.speed);
         continue;
       }
       if (v.same) {  // a lock-step run to its end, one transition per operation end
-        const uint32_t e0 = r.d - v.brem;
-        const uint32_t idx0 = ends_upto(r, e0);
+        // ends of the busy units' grid bsp*E after the elapsed time e0
+        const uint32_t e0 = v.bsp * r.d - v.brem;
+        const uint32_t idx0 = ends_upto(r, e0 / v.bsp);
         if (a.prune && x.clock + v.brem > a.T) {
           // stop at the first state of the run past T
-          const uint32_t idx = ends_upto(r, a.T - x.clock + e0);
+          const uint32_t idx = ends_upto(r, (a.T - x.clock + e0) / v.bsp);
           t += (unsigned long long)(idx - idx0 + 1u);
           break;
         }
@@ -1290,7 +1323,7 @@ __global__ __launch_bounds__(256) void k_swarm(SwarmArgs a) {
         for (int u = 0; u < m; ++u) x.rem[u] = 0u;
         continue;
       }
-      advance_once(x, r, m);
+      advance_once(x, r, m, a.speed);
       ++t;
     }
   }
@@ -1328,14 +1361,14 @@ __global__ void k_swarm_replay(SwarmArgs a, Ctrl* ctrl, unsigned long long seed,
   x.pending = r.n;
   put(x, false);
   for (;;) {
-    const SwarmView v = swarm_view(x, m);
+    const SwarmView v = swarm_view(x, m, a.speed);
     if (v.k == 0u || bad) break;
     if (x.pending && v.freem) {
       const uint32_t pick = (uint32_t)(splitmix64(seed ^ splitmix64(t)) % v.k);
       ++t;
-      swarm_dispatch(x, r, v.freem, pick, m);
+      swarm_dispatch(x, r, v.freem, pick, m, a.speed);
     } else {
-      advance_once(x, r, m);
+      advance_once(x, r, m, a.speed);
       ++t;
     }
     put(x, false);

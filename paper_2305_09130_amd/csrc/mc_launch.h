@@ -174,6 +174,7 @@ struct SwarmArgs {
   uint32_t prune, T;          // over-time property with threshold T, else non-termination
   uint32_t* bits;             // members x 2^bits_log2 bits, zero
   SwarmMember* out;           // members records
+  uint8_t speed[kMaxCU];      // speed of each unit (1 = full speed)
 };
 hipError_t launch_swarm(hipStream_t st, const SwarmArgs& a);
 // Replays the walk of member seed `mseed` that began at member step `start`, writing the

@@ -115,6 +115,91 @@ static int phases(const mc_desc* d, const uint32_t* p, WaveSpec* w, std::string*
   return fail(err, "unknown model kind");
 }
 
+// Units of unequal speed.  Dispatch is eager: while a workgroup is pending no unit
+// stays idle, so as long as at least as many workgroups are pending as units fall idle
+// together every run of a configuration is the same one (only the order of the
+// zero-time dispatches differs, giving the subsets of the idle units as states).  At
+// the first instant with p pending < f idle, every choice of p units starts a tail in
+// which nothing is dispatched any more.  This walks that determined part and every
+// tail.  Tails are counted separately even where they meet (once only some units are
+// still busy two tails can agree), so `states` bounds the reachable count from above;
+// `depth` (edges from the SELECT state) and `max_clock` are exact maxima.  Only states
+// with clock <= T are counted.
+static void tail_walk(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T,
+                      uint64_t t, uint64_t* start, uint32_t busy, uint64_t dep,
+                      ChainCount* out) {
+  while (busy) {
+    uint64_t nt = ~0ull;
+    for (uint32_t u = 0; u < m; ++u) {
+      if (!((busy >> u) & 1u)) continue;
+      const uint64_t e = t - start[u];
+      nt = std::min<uint64_t>(nt, start[u] + sp[u] * end_at_host(r, ends_le(r, e / sp[u])));
+    }
+    t = nt;
+    ++dep;
+    if (t <= T) ++out->states;
+    for (uint32_t u = 0; u < m; ++u)
+      if (((busy >> u) & 1u) && start[u] + (uint64_t)sp[u] * r.d == t) busy &= ~(1u << u);
+  }
+  out->depth = std::max(out->depth, dep);
+  out->max_clock = std::max(out->max_clock, t);
+}
+
+ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T) {
+  ChainCount out;
+  uint64_t t = 0, p = r.n, dep = 0;
+  uint64_t start[kMaxCU] = {0};
+  uint32_t busy = 0;
+  out.states = 1;  // the SELECT state, clock 0
+  for (;;) {
+    const uint32_t freem = ((1u << m) - 1u) & ~busy;
+    const uint32_t f = (uint32_t)__builtin_popcount(freem);
+    if (p > 0 && f > 0) {
+      if (p >= f) {
+        if (t <= T) out.states += (1ull << f) - 1;
+        dep += f;
+        p -= f;
+        for (uint32_t u = 0; u < m; ++u)
+          if ((freem >> u) & 1u) start[u] = t;
+        busy |= freem;
+      } else {
+        if (t <= T)
+          for (uint32_t j = 1; j <= p; ++j) out.states += binom(f, j);
+        // one tail per choice of p idle units
+        for (uint32_t sub = freem;; sub = (sub - 1) & freem) {
+          if ((uint32_t)__builtin_popcount(sub) == p) {
+            uint64_t st[kMaxCU];
+            for (uint32_t u = 0; u < m; ++u) st[u] = ((sub >> u) & 1u) ? t : start[u];
+            tail_walk(r, sp, m, T, t, st, busy | sub, dep + p, &out);
+          }
+          if (sub == 0) break;
+        }
+        return out;
+      }
+    }
+    if (!busy) {  // every workgroup done: the terminal (counted as the last advance)
+      out.depth = std::max(out.depth, dep);
+      out.max_clock = std::max(out.max_clock, t);
+      return out;
+    }
+    if (p == 0) {  // nothing left to dispatch: one tail
+      tail_walk(r, sp, m, T, t, start, busy, dep, &out);
+      return out;
+    }
+    uint64_t nt = ~0ull;
+    for (uint32_t u = 0; u < m; ++u) {
+      if (!((busy >> u) & 1u)) continue;
+      const uint64_t e = t - start[u];
+      nt = std::min<uint64_t>(nt, start[u] + sp[u] * end_at_host(r, ends_le(r, e / sp[u])));
+    }
+    t = nt;
+    ++dep;
+    if (t <= T) ++out.states;
+    for (uint32_t u = 0; u < m; ++u)
+      if (((busy >> u) & 1u) && start[u] + (uint64_t)sp[u] * r.d == t) busy &= ~(1u << u);
+  }
+}
+
 int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   if (!d || !h) return fail(err, "null descriptor");
   if (d->n_cu < 1 || d->n_cu > (uint32_t)kMaxCU) return fail(err, "n_cu out of range 1..8");
@@ -125,7 +210,19 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   if (d->lat_global > (1u << 20) || d->lat_local > (1u << 20) || d->lat_compute > (1u << 20) ||
       d->lat_barrier > (1u << 20))
     return fail(err, "latency too large");
+  h->hetero = false;
+  for (int i = 0; i < kMaxCU; ++i) h->speed[i] = 1;
+  if (d->unit_speed) {
+    for (uint32_t i = 0; i < d->n_cu; ++i) {
+      if (d->unit_speed[i] < 1 || d->unit_speed[i] > MC_MAX_SPEED)
+        return fail(err, "unit speed out of range 1..64");
+      h->speed[i] = d->unit_speed[i];
+      if (h->speed[i] != h->speed[0]) h->hetero = true;
+    }
+    if (!h->hetero && h->speed[0] != 1) h->hetero = true;  // one common factor: still scaled
+  }
   h->desc = *d;
+  h->desc.unit_speed = nullptr;  // the speeds live in h->speed
   h->m = d->n_cu;
   h->n_cfg = d->n_cfg;
   h->params.assign(d->params, d->params + 4ull * d->n_cfg);
@@ -168,22 +265,36 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
     if (r.waves > 1) h->general = true;
     if (b == 0) return fail(err, "workgroup without timed operations");
     const uint64_t rounds = (n + m - 1) / m;
-    const uint64_t tc = rounds * t;
-    if (tc >= 0xFFFFFFFFull) return fail(err, "terminal clock exceeds 32 bits");
+    uint64_t tc = rounds * t;
     r.n = (uint32_t)n;
     r.d = (uint32_t)t;
     r.b = (uint32_t)b;
-    r.tc = (uint32_t)tc;
-    const uint64_t q = n / m, p = n % m;
-    uint64_t cs = 1 + q * (((1ull << m) - 1) + b);
-    if (p) {
-      uint64_t s = 0;
-      for (uint32_t j = 1; j <= p; ++j) s += binom(m, j);
-      cs += s + binom(m, (uint32_t)p) * (b - 1) + 1;
+    uint64_t cs, cdepth;
+    if (h->hetero) {
+      h->general = true;
+      uint32_t smax = 1;
+      for (uint32_t i = 0; i < m; ++i) smax = std::max(smax, h->speed[i]);
+      if ((uint64_t)smax * t >= (1ull << 31)) return fail(err, "workgroup duration exceeds 2^31");
+      if (rounds * b * m > (1ull << 26)) return fail(err, "model too long for units of unequal speed");
+      const ChainCount cc = walk_unequal(r, h->speed, m, ~0ull);
+      tc = cc.max_clock;  // the latest terminal clock of this configuration
+      cs = cc.states;
+      cdepth = 1 + cc.depth;
+    } else {
+      const uint64_t q = n / m, p = n % m;
+      cs = 1 + q * (((1ull << m) - 1) + b);
+      if (p) {
+        uint64_t s = 0;
+        for (uint32_t j = 1; j <= p; ++j) s += binom(m, j);
+        cs += s + binom(m, (uint32_t)p) * (b - 1) + 1;
+      }
+      cdepth = 1 + n + rounds * b;
     }
+    if (tc >= 0xFFFFFFFFull) return fail(err, "terminal clock exceeds 32 bits");
+    r.tc = (uint32_t)tc;
     h->cfg_states[c] = cs;
     total += cs;
-    depth = std::max<uint64_t>(depth, 1 + n + rounds * b);
+    depth = std::max<uint64_t>(depth, cdepth);
     max_clock = std::max<uint32_t>(max_clock, (uint32_t)tc);
     max_n = std::max<uint32_t>(max_n, (uint32_t)n);
     max_d = std::max<uint32_t>(max_d, (uint32_t)t);
@@ -206,7 +317,8 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   widths[kFCfg] = std::max<uint32_t>(1, bit_length((uint64_t)d->n_cfg + 1));
   widths[kFPending] = std::max<uint32_t>(1, bit_length(max_n));
   widths[kFClock] = std::max<uint32_t>(1, bit_length(max_clock));
-  for (uint32_t i = 0; i < m; ++i) widths[kFRem + i] = std::max<uint32_t>(1, bit_length(max_d));
+  for (uint32_t i = 0; i < m; ++i)
+    widths[kFRem + i] = std::max<uint32_t>(1, bit_length((uint64_t)h->speed[i] * max_d));
   Layout L;
   std::memset(&L, 0, sizeof(L));
   // every word after the first keeps its top bit clear, so that no valid key has a word
@@ -228,6 +340,8 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   if (words > 4) return fail(err, "packed state wider than 256 bits");
   L.W = (uint8_t)(words == 1 ? 1 : words == 2 ? 2 : 4);
   L.m = (uint8_t)m;
+  L.hetero = h->hetero ? 1 : 0;
+  for (int i = 0; i < kMaxCU; ++i) L.speed[i] = (uint8_t)h->speed[i];
   L.used_bits = (uint8_t)used;
   h->layout = L;
   h->W = L.W;
@@ -236,7 +350,9 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
 
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out) {
   const Layout& L = h.layout;
-  const bool cuttable = target > 0 && L.word[kFPending] == 0 && L.word[kFClock] == 0;
+  // units of unequal speed pass through no common idle state after whole rounds
+  const bool cuttable =
+      target > 0 && !h.hetero && L.word[kFPending] == 0 && L.word[kFClock] == 0;
   for (uint32_t c = 0; c < h.n_cfg; ++c) {
     const CfgRec& r = h.cfgs[c];
     const uint64_t q = r.n / h.m;
@@ -296,6 +412,10 @@ uint64_t count_le_bound(const ModelHost& h, uint64_t T) {
     const CfgRec& r = h.cfgs[c];
     if (T >= r.tc) {
       total += h.cfg_states[c];
+      continue;
+    }
+    if (h.hetero) {
+      total += walk_unequal(r, h.speed, m, T).states;
       continue;
     }
     const uint64_t q = r.n / m, p = r.n % m;

@@ -33,7 +33,9 @@ struct Layout {
   uint8_t m;
   uint8_t W;  // key words: 1, 2 or 4
   uint8_t used_bits;
-  uint8_t pad[2];
+  uint8_t hetero;            // units of unequal speed
+  uint8_t pad;
+  uint8_t speed[kMaxCU];     // cycles per cycle of work of each unit (1 = full speed)
 };
 
 // One configuration: workgroup count, duration and the timed operation phases of one
@@ -69,7 +71,10 @@ struct ModelHost {
   std::vector<CfgRec> cfgs;
   Layout layout{};
   uint32_t m = 0, n_cfg = 0, W = 1;
-  bool general = false;          // some configuration has waves or two-operation periods
+  bool general = false;          // some configuration has waves or two-operation periods,
+                                 // or the units have unequal speeds
+  bool hetero = false;           // units of unequal speed (no closed-form counts)
+  uint32_t speed[kMaxCU] = {1, 1, 1, 1, 1, 1, 1, 1};
   uint64_t states = 0;           // exact reachable count, root included
   uint64_t max_depth = 0;        // longest path (edges)
   uint32_t max_clock = 0;
@@ -106,6 +111,14 @@ uint64_t auto_part_states(uint64_t states);
 // visited set only.
 // Operation ends of one workgroup of configuration r at or before time x.
 uint64_t ends_le(const CfgRec& r, uint64_t x);
+
+// Sizes of one configuration's subgraph on units of unequal speed (sp[0..m-1]): states
+// with clock <= T (an upper bound: tails that meet are counted twice), the longest path
+// from the SELECT state, the latest terminal clock.
+struct ChainCount {
+  uint64_t states = 0, depth = 0, max_clock = 0;
+};
+ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T);
 // Time of the k-th operation end (0-based, k < r.b) of one workgroup.
 uint64_t end_at_host(const CfgRec& r, uint64_t k);
 

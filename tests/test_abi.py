@@ -149,3 +149,28 @@ def test_invalid_unit_descriptors(mc, bad):
     assert e.value.code == mc.MC_E_INVAL
     with pytest.raises(mc.McError):
         mc.mc_config_ends(model, 0)
+
+
+def test_unequal_units_describe_bounds_the_oracle(mc):
+    """On units of unequal speed the library sizes each configuration by walking its
+    determined run and every tail: an upper bound on the reachable count (tails that
+    meet are counted twice) and the exact longest path."""
+    import oracle
+    exact = 0
+    for model in workloads.tiny_hetero_models(51, 60, max_cu=6):
+        d = mc.mc_describe(model)
+        r = oracle.explore(model)
+        assert d["states"] >= r["reachable"], workloads.describe(model)
+        assert d["max_depth"] + 1 >= len(r["trace"])
+        exact += d["states"] == r["reachable"]
+    assert exact >= 10
+    for name, model in workloads.hetero_workloads().items():
+        assert mc.mc_describe(model)["states"] >= 86474
+
+
+def test_invalid_speeds(mc):
+    base = workloads.reduction_g256()
+    for speeds in ([0, 1], [1, 65]):
+        with pytest.raises(mc.McError) as e:
+            mc.mc_describe(workloads.with_speeds(base, speeds))
+        assert e.value.code == mc.MC_E_INVAL

@@ -280,7 +280,7 @@ MUTANTS = {
     # pruning keeps clock == T out (off by one in the threshold)
     "prune_off_by_one": ("if (prune && y[1] > T) continue;", "if (prune && y[1] >= T) continue;"),
     # the advance jumps straight to the end of the workgroup
-    "advance_to_end": ("uint32_t di = next_end(cf, e) - e;", "uint32_t di = cf->d - e;"),
+    "advance_to_end": ("uint32_t di = next_end(cf, s, e) - e;", "uint32_t di = s * cf->d - e;"),
     # workgroup count uses the tile size too
     "wrong_workgroups": ("n = mo->G / WG;", "n = mo->G / (WG * TS) ? mo->G / (WG * TS) : 1;"),
     # zero-latency operations are counted as end times

@@ -243,7 +243,50 @@ def tiny_unit_models(seed: int, count: int, max_cu: int = 3) -> list[dict]:
     return out
 
 
+def with_speeds(model: dict, speeds) -> dict:
+    """The model on units of unequal speed: unit i runs every operation speeds[i] times as
+    long (speeds[i] >= 1)."""
+    out = dict(model)
+    out["speed"] = [int(v) for v in speeds]
+    assert len(out["speed"]) == model["m"]
+    return out
+
+
+def hetero_workloads() -> dict:
+    """Models on units of unequal speed (speeds 1, 1, 2, 3): the reduction-shaped model of
+    G = 256 on four units and the matmul-shaped model of M = N = K = 32 on four units,
+    with the latencies of the single-query workloads (seeds 0 and 1)."""
+    return {
+        "reduction_g256_cu4_s1123": with_speeds(
+            reduction_model(256, 4, pow2_range(0, 5), pow2_range(0, 2), *latencies(0)),
+            [1, 1, 2, 3]),
+        "matmul32_cu4_s1123": with_speeds(
+            matmul_model(32, 32, 32, 4, pow2_range(0, 4), pow2_range(0, 4), pow2_range(0, 3),
+                         [1], *latencies(1)),
+            [1, 1, 2, 3]),
+    }
+
+
+def tiny_hetero_models(seed: int, count: int, max_cu: int = 4, max_speed: int = 3) -> list[dict]:
+    """Tiny models of every kind on 2..max_cu units whose speeds are drawn from
+    1..max_speed (at least two distinct speeds)."""
+    rng = np.random.default_rng(seed)
+    pool = tiny_models(seed + 1, count, max_cu) + tiny_unit_models(seed + 2, count, max_cu)
+    out = []
+    for k in range(count):
+        base = pool[int(rng.integers(0, len(pool)))]
+        m = max(2, base["m"])
+        speeds = [int(v) for v in rng.integers(1, max_speed + 1, size=m)]
+        if len(set(speeds)) == 1:
+            speeds[int(rng.integers(0, m))] = 1 + speeds[0] % max_speed
+        out.append(with_speeds(dict(base, m=m), speeds))
+    return out
+
+
 def describe(model: dict) -> str:
+    if model.get("speed") and len(set(model["speed"])) > 1:
+        base = describe({k: v for k, v in model.items() if k != "speed"})
+        return base[:-1] + f", speeds={model['speed']})"
     if model["kind"] in (KIND_ABSTRACT, KIND_MINIMUM):
         return (f"{model['kind']}(S={model['S']}, NP={model['NP']}, m={model['m']}, "
                 f"GMT={model['Lg']}, local={model['Ll']}, #P={len(model['params'])})")
