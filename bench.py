@@ -176,9 +176,19 @@ def units_leg(mc, torch, workloads, reps: int = 5, cpu: bool = True):
     unit, WG/NP waves) at S = 1024: the same step as the timed one (load + min_time +
     trace + check(T_min - 1)) on the super-step engine built for general phases, with
     its roofline figure and, on the CPU, the oracle on the same step."""
+    return model_leg(mc, torch, {k: f() for k, f in workloads.UNIT_WORKLOADS.items()},
+                     reps, cpu)
+
+
+def hetero_leg(mc, torch, workloads, reps: int = 5, cpu: bool = True):
+    """Models on units of unequal speed (1, 1, 2, 3): the same step, the general-phase
+    engine with determined ADVANCE chains, and the oracle on the same step."""
+    return model_leg(mc, torch, workloads.hetero_workloads(), reps, cpu)
+
+
+def model_leg(mc, torch, models: dict, reps: int, cpu: bool):
     out = {}
-    for name, make in workloads.UNIT_WORKLOADS.items():
-        model = make()
+    for name, model in models.items():
         nbytes = mc.mc_workspace_bytes(model)
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
         run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0)
@@ -191,20 +201,23 @@ def units_leg(mc, torch, workloads, reps: int = 5, cpu: bool = True):
         states = sum(s["states"] for s in steps)
         eng_s = sum(s["engine_ns_min"] for s in steps) * 1e-9 / reps
         achieved = steps[0]["min_states"] * ALGO_BYTES_PER_STATE / eng_s / 1e9
-        rec = {"kind": model["kind"], "S": model["S"], "NP": model["NP"], "cu": model["m"],
-               "configurations": len(model["params"]), "GMT": model["Lg"], "local": model["Ll"],
+        rec = {"kind": model["kind"], "cu": model["m"], "configurations": len(model["params"]),
+               "Lg": model["Lg"], "Ll": model["Ll"],
                "reachable": steps[0]["min_states"], "levels": steps[0]["levels"],
                "t_min": steps[0]["t_min"], "argmin": steps[0]["argmin"],
                "ms_per_step": 1e3 * elapsed / reps, "states_per_s": states / elapsed,
                "min_time_engine_ms": eng_s * 1e3, "roofline_frac": achieved / HBM_PEAK_GBS,
                "partitions": steps[0]["parts"]}
+        for k in ("S", "NP", "G", "M", "N", "K", "speed"):
+            if k in model:
+                rec[k] = model[k]
         if cpu:
             c = cpu_baseline(model, steps[0]["t_min"])
             rec["cpu_oracle_states_per_s"] = c["value"]
             rec["cpu_oracle_agrees"] = c["agrees"]
             rec["gpu_over_cpu"] = rec["states_per_s"] / c["value"]
         out[name] = rec
-        _progress(f"units leg: {name} {rec['ms_per_step']:.2f} ms/step")
+        _progress(f"model leg: {name} {rec['ms_per_step']:.2f} ms/step")
     return out
 
 
@@ -215,7 +228,8 @@ def bb_leg(mc, torch, workloads, names, reps: int = 5):
     synchronous) and the states each claimed."""
     out = {}
     for name in names:
-        model = (workloads.WORKLOADS.get(name) or workloads.UNIT_WORKLOADS[name])()
+        make = workloads.WORKLOADS.get(name) or workloads.UNIT_WORKLOADS.get(name)
+        model = make() if make else workloads.hetero_workloads()[name]
         g = mc.Model(model)
         g.mc_min_time()
         g.mc_min_time_bb(0)
@@ -358,7 +372,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--legs", default="plain,cpu,batch,serve,swarm,units,bb",
+    ap.add_argument("--legs", default="plain,cpu,batch,serve,swarm,units,bb,hetero",
                     help="extra legs beside the timed single-query step")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -445,7 +459,11 @@ def main():
     if "bb" in legs:
         _progress("branch-and-bound leg")
         bbr = bb_leg(mc, torch, workloads, [args.workload, "matmul128_vw_cu8",
-                                            "abstract_s1024_np4_cu4"])
+                                            "abstract_s1024_np4_cu4", "matmul32_cu4_s1123"])
+    hetero = None
+    if "hetero" in legs:
+        _progress("unequal-units leg")
+        hetero = hetero_leg(mc, torch, workloads, cpu=not args.no_cpu and "cpu" in legs)
     units = None
     if "units" in legs:
         _progress("unit-model leg")
@@ -492,6 +510,7 @@ def main():
         "swarm": swarm,
         "unit_models": units,
         "branch_and_bound": bbr,
+        "unequal_units": hetero,
     }
     print(json.dumps(out), flush=True)
 

@@ -288,7 +288,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     pq.yielded = nullptr;
     pq.n_yielded = nullptr;
     const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
-    HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general));
+    HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general, h->mh.hetero));
     HIPCHK(hipEventRecord(h->ev[5], s));
     launches = 2;
   } else {

@@ -192,9 +192,12 @@ int enqueue_query(mc_batch* b) {
     pq[w].yielded = nullptr;
     pq[w].n_yielded = nullptr;
   }
-  bool general = false;
-  for (const ModelHost& mh : b->ms) general |= mh.general;
-  HIPCHK(launch_super_fork(s, b->fork, pq, b->grid, b->opts.block, li, general));
+  bool general = false, hetero = false;
+  for (const ModelHost& mh : b->ms) {
+    general |= mh.general;
+    hetero |= mh.hetero;
+  }
+  HIPCHK(launch_super_fork(s, b->fork, pq, b->grid, b->opts.block, li, general, hetero));
   HIPCHK(hipMemcpyAsync(b->hctrl, b->ws + b->plan.ctrl, kCtrlStride * n, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(b->htc, b->ws + b->plan.tc, 4ull * b->tc_words, hipMemcpyDeviceToHost, s));
   return MC_OK;

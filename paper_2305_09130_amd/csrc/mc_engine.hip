@@ -417,8 +417,11 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
     std::vector<Part> grouped;
     grouped.reserve(e->pending_parts.size());
     uint32_t gn[3] = {0, 0, 0};
-    bool general = false;
-    for (const Part& p : e->pending_parts) general |= e->slots[p.model]->mh.general;
+    bool general = false, hetero = false;
+    for (const Part& p : e->pending_parts) {
+      general |= e->slots[p.model]->mh.general;
+      hetero |= e->slots[p.model]->mh.hetero;
+    }
     for (int g = 0; g < 3; ++g)
       for (const Part& p : e->pending_parts) {
         const uint32_t W = e->slots[p.model]->mh.W;
@@ -451,7 +454,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       grid[g] = std::max<uint32_t>(1u, std::min<uint32_t>(gn[g], e->opts.grid ? e->opts.grid : 1024u));
       off += gn[g];
     }
-    HIPCHK(launch_super_fork(s, e->fork, pq, grid, e->opts.block, li, general));
+    HIPCHK(launch_super_fork(s, e->fork, pq, grid, e->opts.block, li, general, hetero));
     ++e->launches;
     HIPCHK(hipMemcpyAsync(e->hny, ny, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(e->hctrl, e->base + e->ctrl_off, kCtrlStride * hi, hipMemcpyDeviceToHost,

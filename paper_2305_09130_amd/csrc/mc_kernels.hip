@@ -298,6 +298,9 @@ constexpr uint32_t kNoItem = 0xFFFFFFFFu;
 constexpr int kEMax = 4096;  // operation ends kept in LDS
 constexpr int kFCap = 256;   // frontier states per super-step level (LDS)
 constexpr int kMaxLeaves = 72;  // C(8, 4) = 70 leaves at most
+constexpr int kChainCand = 8 * 64;       // chain candidates: 64 ends to go per unit
+constexpr int kChainTimes = 1024;        // the chain's times, listed in E from here
+static_assert(kChainTimes >= kChainCand + 1 && kChainTimes + kChainCand <= kEMax, "E use");
 
 struct SegDesc {
   unsigned long long fkey[4];  // frontier state of the segment
@@ -361,7 +364,7 @@ struct Item {
 
 // State number i of the current batch: a closure state (a set of started units) or the
 // j-th state of a run from a leaf, built directly from the segment's templates.
-template <int W, int BLOCK, int NI, bool KEY, bool GEN>
+template <int W, int BLOCK, int NI, bool KEY, bool GEN, bool HET>
 __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t nseg,
                                          const SuperShared<BLOCK, NI>& sh, const CfgRec& r,
                                          bool e_lds, const ModelDev& md, int m, Item<W>& it) {
@@ -431,19 +434,120 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
       field_add<W>(it.key, L, kFClock, it.clk);
     }
     it.term = sg.pend == 0u && e == r.d;
+  } else if (HET && sg.pad) {
+    // state j of a chain: the frontier state advanced to the j-th listed time
+    Key<W> fk;
+#pragma unroll
+    for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
+    St y = decode<W>(fk, L);
+    const uint32_t tau = sh.E[kChainTimes + it.j], dt = tau - y.clock;
+#pragma unroll
+    for (int u = 0; u < kMaxCU; ++u) y.rem[u] = y.rem[u] > dt ? y.rem[u] - dt : 0u;
+    y.clock = tau;
+    it.clk = tau;
+    it.term = is_terminal(y, m);
+    if (KEY) {
+      const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+      for (int w = 0; w < W; ++w) it.key[w] = yk.w[w];
+    }
   } else {
-    const uint32_t gi = sg.pad ? it.j : leaf;  // a chain lists its states in order
-    it.clk = sh.gclk[gi];
-    it.term = sh.gterm[gi] != 0u;
+    it.clk = sh.gclk[leaf];
+    it.term = sh.gterm[leaf] != 0u;
     if (KEY) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[gi][w];
+      for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[leaf][w];
     }
   }
   if (md.prune && it.clk > sh.T) it.active = false;
 }
 
 __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
+
+// A chain on units of unequal speed: from the frontier state x of the last segment (no
+// DISPATCH enabled) the clock visits the union of the busy units' operation ends, up to
+// the first workgroup end while work is pending (then a DISPATCH follows), or to the
+// terminal.  Every lane writes one candidate end (unit u, its k-th end to go, k < 64)
+// into the LDS table E (unused on such models: no run is in lock step), the workgroup
+// sorts the candidates (bitonic), and one wavefront keeps the distinct times up to the
+// smallest 64th candidate of any unit (below it no end of any unit is missing), in
+// order, as the chain's states.  Their number is the segment's length.
+template <int W, int BLOCK, int NI>
+__device__ __noinline__ void build_chain(SuperShared<BLOCK, NI>& sh, const CfgRec& r, const Layout& L,
+                            int m) {
+  const uint32_t tid = threadIdx.x;
+  SegDesc& sg = sh.seg[sh.nseg - 1];
+  Key<W> fk;
+#pragma unroll
+  for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
+  const St x = decode<W>(fk, L);
+  uint32_t H = 0xFFFFFFFFu;  // with work pending the chain stops at the first workgroup end
+  if (x.pending)
+    for (int u = 0; u < m; ++u)
+      if (x.rem[u]) H = min(H, x.clock + x.rem[u]);
+  uint32_t* ct = sh.E;
+  if (tid == 0) ct[kChainCand] = 0xFFFFFFFFu;  // the smallest 64th candidate
+  __syncthreads();
+  for (uint32_t i = tid; i < (uint32_t)kChainCand; i += BLOCK) {
+    const int u = (int)(i >> 6);
+    const uint32_t k = i & 63u;
+    uint32_t v = 0xFFFFFFFFu;
+    if (u < m && x.rem[u]) {
+      const uint32_t sp = L.speed[u];
+      const uint32_t e = sp * r.d - x.rem[u];
+      const uint32_t kk = ends_upto(r, e / sp) + k;
+      if (kk < r.b) {
+        const uint32_t tau = x.clock + sp * end_at(r, kk) - e;
+        if (tau <= H) {
+          v = tau;
+          if (k == 63u) atomicMin(&ct[kChainCand], tau);
+        }
+      }
+    }
+    ct[i] = v;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= (uint32_t)kChainCand; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < (uint32_t)kChainCand; i += BLOCK) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = ct[i], b = ct[ixj];
+          if ((a > b) == ((i & k) == 0u)) {
+            ct[i] = b;
+            ct[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < 64) {
+    const uint32_t lim = ct[kChainCand];
+    constexpr int kPer = kChainCand / 64;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t i = tid * kPer + q, v = ct[i];
+      cnt += (v <= lim && v != 0xFFFFFFFFu && (i == 0u || v != ct[i - 1])) ? 1u : 0u;
+    }
+    uint32_t incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if ((int)tid >= off) incl += y;
+    }
+    uint32_t j = incl - cnt;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t i = tid * kPer + q, v = ct[i];
+      if (v <= lim && v != 0xFFFFFFFFu && (i == 0u || v != ct[i - 1])) ct[kChainTimes + j++] = v;
+    }
+    if (tid == 63) {
+      sg.len = incl;
+      sh.total = sg.start + incl;
+    }
+  }
+}
 
 // Prune threshold: the query's T, or under branch and bound the least terminal clock
 // found so far when that is lower.  The incumbent only falls, so a stale value prunes
@@ -455,7 +559,7 @@ __device__ __forceinline__ uint32_t prune_T(const ModelDev& md) {
   return b < md.T ? b : md.T;
 }
 
-template <int W, int BLOCK, int NI, bool GEN>
+template <int W, int BLOCK, int NI, bool GEN, bool HET>
 __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t batch_items,
                                   uint32_t slice, const PartQueue& pq,
                                   SuperShared<BLOCK, NI>& sh) {
@@ -594,7 +698,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             for (uint32_t i = 1; i <= kstar; ++i) nleaf = nleaf * (nfree - kstar + i) / i;
             sg.nleaf = nleaf;
             // units of unequal speed leave lock step at once: one ADVANCE per leaf
-            const bool lock = !(GEN && L.hetero) && (kstar ? (busy == 0u) : bsame);
+            const bool lock = !(HET && L.hetero) && (kstar ? (busy == 0u) : bsame);
             sg.lock = lock ? 1u : 0u;
             sg.e0 = kstar ? 0u : r.d - brem;
             sg.idx0 = lock ? ends_upto_t<GEN>(r, sg.e0) : 0u;
@@ -620,29 +724,11 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             }
             sg.aux = (kstar && busy == 0u && nleaf == 1u) ? 1u : 0u;  // a full round start
             sg.pad = 0u;
-            if (GEN && L.hetero && !lock && kstar == 0u) {
-              // units of unequal speed with nothing to dispatch: the ADVANCE steps up to the
-              // next state with a dispatch (or the terminal) are determined, so this thread
-              // lists up to kMaxLeaves of them as one segment (a chain)
-              St y = x;
-              uint32_t len = 0;
-              for (;;) {
-                advance_once<GEN>(y, r, m, L.speed);
-                const Key<W> yk = encode<W>(y, L);
-#pragma unroll
-                for (int w = 0; w < W; ++w) sh.gkey[len][w] = yk.w[w];
-                sh.gclk[len] = y.clock;
-                const bool term = is_terminal(y, m);
-                sh.gterm[len] = term ? 1u : 0u;
-                ++len;
-                bool idle = false;
-#pragma unroll
-                for (int u = 0; u < kMaxCU; ++u) idle |= u < m && y.rem[u] == 0u;
-                if (term || (y.pending && idle) || len == (uint32_t)kMaxLeaves ||
-                    (md.prune && y.clock > sh.T))
-                  break;
-              }
-              sg.len = len;
+            if (HET && L.hetero && !lock && kstar == 0u) {
+              // units of unequal speed with nothing to dispatch: the ADVANCE steps up to
+              // the next state with a dispatch (or the terminal) are determined; the
+              // workgroup lists them below (a chain) and sets its length
+              sg.len = 0u;
               sg.pad = 1u;
             }
           }
@@ -735,6 +821,12 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         sh.carry = sh.fslot[cur][fi];
       }
       __syncthreads();
+      if constexpr (HET) {
+        if (sh.nseg && sh.seg[sh.nseg - 1].pad) {
+          build_chain<W, BLOCK, NI>(sh, r, L, m);
+          __syncthreads();
+        }
+      }
       const uint32_t nseg = sh.nseg;
       const uint32_t total = sh.total;
       const uint32_t stop_item = sh.stop_item;
@@ -792,7 +884,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
           Item<W> x;
-          gen_item<W, BLOCK, NI, true, GEN>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+          gen_item<W, BLOCK, NI, true, GEN, HET>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                        e_lds, md, m, x);
           if (x.active && x.clk > md.max_clock) {
             set_error(md.ctrl, kDevErrOverflow);
@@ -811,7 +903,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
-          gen_item<W, BLOCK, NI, false, GEN>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+          gen_item<W, BLOCK, NI, false, GEN, HET>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                         e_lds, md, m, it[n]);
           it[n].active = act[n];
           fresh[n] = false;
@@ -920,7 +1012,7 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
   }
 }
 
-template <int W, int BLOCK, int NI, bool GEN>
+template <int W, int BLOCK, int NI, bool GEN, bool HET>
 __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
   __shared__ SuperShared<BLOCK, NI> sh;
   const uint32_t tid = threadIdx.x;
@@ -938,7 +1030,7 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     const ModelDev& md = sh.md;
     const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
     const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
-    if (!skip) explore_partition<W, BLOCK, NI, GEN>(md, pc, a.batch_items, a.slice, a, sh);
+    if (!skip) explore_partition<W, BLOCK, NI, GEN, HET>(md, pc, a.batch_items, a.slice, a, sh);
     if (tid == 0) {
       const unsigned long long dt = __builtin_amdgcn_s_memrealtime() - t_part;
       const unsigned long long prev = atomicMax(&md.ctrl->crit_ticks, dt);
@@ -1394,11 +1486,11 @@ hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, cons
   return hipGetLastError();
 }
 
-template <int W, bool GEN>
+template <int W, bool GEN, bool HET>
 static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32_t items,
                            const PartQueue& pq) {
 #define MC_LAUNCH_SUPER(B, N) \
-  hipLaunchKernelGGL((k_superstep<W, B, N, GEN>), dim3(grid), dim3(B), 0, st, pq)
+  hipLaunchKernelGGL((k_superstep<W, B, N, GEN, HET>), dim3(grid), dim3(B), 0, st, pq)
   if (block == 256) {
     if (items >= 2) MC_LAUNCH_SUPER(256, 2);
     else MC_LAUNCH_SUPER(256, 1);
@@ -1413,23 +1505,27 @@ static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32
 }
 
 hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
-                        uint32_t items, const PartQueue& pq, bool general) {
+                        uint32_t items, const PartQueue& pq, bool general, bool hetero) {
   items = lane_items_for(items, W);
-  if (general) {
-    if (W == 1) launch_super_w<1, true>(st, grid, block, items, pq);
-    else if (W == 2) launch_super_w<2, true>(st, grid, block, items, pq);
-    else launch_super_w<4, true>(st, grid, block, items, pq);
+  if (hetero) {
+    if (W == 1) launch_super_w<1, true, true>(st, grid, block, items, pq);
+    else if (W == 2) launch_super_w<2, true, true>(st, grid, block, items, pq);
+    else launch_super_w<4, true, true>(st, grid, block, items, pq);
+  } else if (general) {
+    if (W == 1) launch_super_w<1, true, false>(st, grid, block, items, pq);
+    else if (W == 2) launch_super_w<2, true, false>(st, grid, block, items, pq);
+    else launch_super_w<4, true, false>(st, grid, block, items, pq);
   } else {
-    if (W == 1) launch_super_w<1, false>(st, grid, block, items, pq);
-    else if (W == 2) launch_super_w<2, false>(st, grid, block, items, pq);
-    else launch_super_w<4, false>(st, grid, block, items, pq);
+    if (W == 1) launch_super_w<1, false, false>(st, grid, block, items, pq);
+    else if (W == 2) launch_super_w<2, false, false>(st, grid, block, items, pq);
+    else launch_super_w<4, false, false>(st, grid, block, items, pq);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)[3],
                              const uint32_t (&grid)[3], uint32_t block, uint32_t items,
-                             bool general) {
+                             bool general, bool hetero) {
   static const uint32_t widths[3] = {1, 2, 4};
   int used = 0, last = -1;
   for (int w = 0; w < 3; ++w)
@@ -1439,13 +1535,14 @@ hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)
     }
   if (used == 0) return hipSuccess;
   if (used == 1)  // no fork needed
-    return launch_super(main, widths[last], grid[last], block, items, queue[last], general);
+    return launch_super(main, widths[last], grid[last], block, items, queue[last], general,
+                        hetero);
   hipError_t e = hipEventRecord(f.fork, main);
   for (int w = 0; w < 3 && e == hipSuccess; ++w) {
     if (!queue[w].n_parts) continue;
     e = hipStreamWaitEvent(f.sub[w], f.fork, 0);
     if (e == hipSuccess)
-      e = launch_super(f.sub[w], widths[w], grid[w], block, items, queue[w], general);
+      e = launch_super(f.sub[w], widths[w], grid[w], block, items, queue[w], general, hetero);
     if (e == hipSuccess) e = hipEventRecord(f.join[w], f.sub[w]);
     if (e == hipSuccess) e = hipStreamWaitEvent(main, f.join[w], 0);
   }

@@ -107,9 +107,10 @@ hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, cons
 // All models of the queue have key width W (1, 2, 4).  items: keys per lane per insert
 // round trip, as for lane_items_for.  general: some configuration of some model of the
 // queue has waves or two-operation periods (ModelHost::general); false selects the
-// engine built for uniform phases only.
+// engine built for uniform phases only.  hetero: some model runs on units of unequal
+// speed (ModelHost::hetero), which selects the build with determined ADVANCE chains.
 hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
-                        uint32_t items, const PartQueue& pq, bool general);
+                        uint32_t items, const PartQueue& pq, bool general, bool hetero);
 
 // Runs up to three launches (one per key width) concurrently on sub-streams forked from
 // and joined back into a main stream with events; usable inside stream capture.
@@ -140,7 +141,7 @@ struct Fork {
 // queue[w] (w = 0, 1, 2 for key widths 1, 2, 4) with n_parts == 0 are skipped
 hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)[3],
                              const uint32_t (&grid)[3], uint32_t block, uint32_t items,
-                             bool general);
+                             bool general, bool hetero);
 hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n);
 hipError_t launch_reset_models(hipStream_t st, const ModelDev* models, uint32_t n,
                                unsigned int* head, uint32_t n_heads);

@@ -125,30 +125,52 @@ static int phases(const mc_desc* d, const uint32_t* p, WaveSpec* w, std::string*
 // still busy two tails can agree), so `states` bounds the reachable count from above;
 // `depth` (edges from the SELECT state) and `max_clock` are exact maxima.  Only states
 // with clock <= T are counted.
-static void tail_walk(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T,
-                      uint64_t t, uint64_t* start, uint32_t busy, uint64_t dep,
-                      ChainCount* out) {
+namespace {
+
+// One unit's workgroup in progress: when it started and its next operation end.
+struct UnitRun {
+  uint64_t start = 0, next = 0;
+  uint32_t k = 0;  // index of that end in E
+};
+
+// Moves the clock to the next operation end of any busy unit; units whose workgroup
+// ends there fall idle.
+uint64_t advance_units(const CfgRec& r, const uint32_t* sp, uint32_t m, UnitRun* ur,
+                       uint32_t* busy) {
+  uint64_t t = ~0ull;
+  for (uint32_t u = 0; u < m; ++u)
+    if ((*busy >> u) & 1u) t = std::min(t, ur[u].next);
+  for (uint32_t u = 0; u < m; ++u) {
+    if (!((*busy >> u) & 1u) || ur[u].next != t) continue;
+    if (++ur[u].k == r.b) *busy &= ~(1u << u);
+    else ur[u].next = ur[u].start + (uint64_t)sp[u] * end_at_host(r, ur[u].k);
+  }
+  return t;
+}
+
+void start_unit(const CfgRec& r, const uint32_t* sp, UnitRun* ur, uint32_t u, uint64_t t) {
+  ur[u].start = t;
+  ur[u].k = 0;
+  ur[u].next = t + (uint64_t)sp[u] * end_at_host(r, 0);
+}
+
+void tail_walk(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T, uint64_t t,
+               UnitRun* ur, uint32_t busy, uint64_t dep, ChainCount* out) {
   while (busy) {
-    uint64_t nt = ~0ull;
-    for (uint32_t u = 0; u < m; ++u) {
-      if (!((busy >> u) & 1u)) continue;
-      const uint64_t e = t - start[u];
-      nt = std::min<uint64_t>(nt, start[u] + sp[u] * end_at_host(r, ends_le(r, e / sp[u])));
-    }
-    t = nt;
+    t = advance_units(r, sp, m, ur, &busy);
     ++dep;
     if (t <= T) ++out->states;
-    for (uint32_t u = 0; u < m; ++u)
-      if (((busy >> u) & 1u) && start[u] + (uint64_t)sp[u] * r.d == t) busy &= ~(1u << u);
   }
   out->depth = std::max(out->depth, dep);
   out->max_clock = std::max(out->max_clock, t);
 }
 
+}  // namespace
+
 ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T) {
   ChainCount out;
   uint64_t t = 0, p = r.n, dep = 0;
-  uint64_t start[kMaxCU] = {0};
+  UnitRun ur[kMaxCU];
   uint32_t busy = 0;
   out.states = 1;  // the SELECT state, clock 0
   for (;;) {
@@ -160,7 +182,7 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
         dep += f;
         p -= f;
         for (uint32_t u = 0; u < m; ++u)
-          if ((freem >> u) & 1u) start[u] = t;
+          if ((freem >> u) & 1u) start_unit(r, sp, ur, u, t);
         busy |= freem;
       } else {
         if (t <= T)
@@ -168,9 +190,11 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
         // one tail per choice of p idle units
         for (uint32_t sub = freem;; sub = (sub - 1) & freem) {
           if ((uint32_t)__builtin_popcount(sub) == p) {
-            uint64_t st[kMaxCU];
-            for (uint32_t u = 0; u < m; ++u) st[u] = ((sub >> u) & 1u) ? t : start[u];
-            tail_walk(r, sp, m, T, t, st, busy | sub, dep + p, &out);
+            UnitRun tu[kMaxCU];
+            for (uint32_t u = 0; u < m; ++u) tu[u] = ur[u];
+            for (uint32_t u = 0; u < m; ++u)
+              if ((sub >> u) & 1u) start_unit(r, sp, tu, u, t);
+            tail_walk(r, sp, m, T, t, tu, busy | sub, dep + p, &out);
           }
           if (sub == 0) break;
         }
@@ -183,20 +207,12 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
       return out;
     }
     if (p == 0) {  // nothing left to dispatch: one tail
-      tail_walk(r, sp, m, T, t, start, busy, dep, &out);
+      tail_walk(r, sp, m, T, t, ur, busy, dep, &out);
       return out;
     }
-    uint64_t nt = ~0ull;
-    for (uint32_t u = 0; u < m; ++u) {
-      if (!((busy >> u) & 1u)) continue;
-      const uint64_t e = t - start[u];
-      nt = std::min<uint64_t>(nt, start[u] + sp[u] * end_at_host(r, ends_le(r, e / sp[u])));
-    }
-    t = nt;
+    t = advance_units(r, sp, m, ur, &busy);
     ++dep;
     if (t <= T) ++out.states;
-    for (uint32_t u = 0; u < m; ++u)
-      if (((busy >> u) & 1u) && start[u] + (uint64_t)sp[u] * r.d == t) busy &= ~(1u << u);
   }
 }
 
@@ -414,8 +430,8 @@ uint64_t count_le_bound(const ModelHost& h, uint64_t T) {
       total += h.cfg_states[c];
       continue;
     }
-    if (h.hetero) {
-      total += walk_unequal(r, h.speed, m, T).states;
+    if (h.hetero) {  // no closed form: the configuration's whole bound
+      total += h.cfg_states[c];
       continue;
     }
     const uint64_t q = r.n / m, p = r.n % m;
