@@ -77,11 +77,13 @@ int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) 
   return MC_OK;
 }
 
+constexpr uint32_t kWideParts = 256;
+
 mc_opts default_opts(const mc_opts* o) {
   mc_opts r;
   std::memset(&r, 0, sizeof(r));
   if (o) r = *o;
-  if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 256;
+  if (r.block != 256 && r.block != 512 && r.block != 1024) r.block = 0;  // chosen at load
   if (r.engine > MC_ENGINE_LEVEL) r.engine = MC_ENGINE_SUPERSTEP;
   if (r.lane_items > 2) r.lane_items = 0;
   return r;
@@ -499,6 +501,11 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     h->q_slots = h->plan.slots;
     const std::vector<Part> parts = model_parts(h->mh, h->opts);
     h->n_parts = (uint32_t)parts.size();
+    // automatic workgroup size: with fewer partitions than a wide launch has workgroups,
+    // each runs nearly alone on its compute unit and its chain of insert round trips is
+    // the launch time, which 512 threads shorten; with many, 256 keeps more of them
+    // resident
+    if (!h->opts.block) h->opts.block = h->n_parts < kWideParts ? 512u : 256u;
     // one pooled pinned block: counters, poll words, descriptor, clocks and, when small,
     // the staging of the uploads below
     static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "pinned block layout");
