@@ -100,7 +100,7 @@ std::vector<Part> model_parts(const ModelHost& mh, const mc_opts& o) {
                    [](const PartPlan& a, const PartPlan& b) { return a.states > b.states; });
   std::vector<Part> parts(plan.size());
   for (size_t i = 0; i < plan.size(); ++i)
-    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1, (uint32_t)i, {0u, 0u, 0u}};
+    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1, (uint32_t)i, plan[i].j0, plan[i].j1, 0u};
   return parts;
 }
 

@@ -52,7 +52,7 @@ mc_batch_opts default_bopts(const mc_batch_opts* o) {
 // grouped by key width (one launch each) and largest first within a group.
 struct BPart {
   uint64_t size;
-  uint32_t model, cfg, r0, r1;
+  uint32_t model, cfg, r0, r1, j0, j1;
 };
 
 int width_group(uint32_t W) { return W == 1 ? 0 : W == 2 ? 1 : 2; }
@@ -68,7 +68,7 @@ std::vector<BPart> batch_parts(const std::vector<ModelHost>& ms, const mc_batch_
   for (uint32_t i = 0; i < (uint32_t)ms.size(); ++i) {
     plan.clear();
     plan_parts(ms[i], target, &plan);
-    for (const auto& q : plan) ps.push_back({q.states, i, q.cfg, q.r0, q.r1});
+    for (const auto& q : plan) ps.push_back({q.states, i, q.cfg, q.r0, q.r1, q.j0, q.j1});
   }
   std::stable_sort(ps.begin(), ps.end(), [&](const BPart& a, const BPart& c) {
     const int ga = width_group(ms[a.model].W), gc = width_group(ms[c.model].W);
@@ -323,7 +323,8 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
     std::vector<Part> parts(ps.size());
     std::vector<uint32_t> pidx(n, 0u);  // partitions of each model so far
     for (size_t k = 0; k < ps.size(); ++k) {
-      parts[k] = Part{ps[k].model, ps[k].cfg, ps[k].r0, ps[k].r1, pidx[ps[k].model]++, {0u, 0u, 0u}};
+      parts[k] = Part{ps[k].model, ps[k].cfg, ps[k].r0, ps[k].r1, pidx[ps[k].model]++, ps[k].j0,
+                      ps[k].j1, 0u};
       ++b->group_n[width_group(b->ms[ps[k].model].W)];
     }
     b->group_off[0] = 0;

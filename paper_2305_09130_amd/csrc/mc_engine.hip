@@ -393,7 +393,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       for (size_t k = 0; k < q->parts.size(); ++k) {
         const PartPlan& pp = q->parts[k];
         e->pending_parts.push_back(
-            Part{(uint32_t)q->slot_idx, pp.cfg, pp.r0, pp.r1, (uint32_t)k, {0u, 0u, 0u}});
+            Part{(uint32_t)q->slot_idx, pp.cfg, pp.r0, pp.r1, (uint32_t)k, pp.j0, pp.j1, 0u});
       }
     // the host must not overwrite the pinned staging before the copy ran
     HIPCHK(hipStreamSynchronize(s));

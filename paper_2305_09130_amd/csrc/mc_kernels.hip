@@ -703,6 +703,8 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             sg.e0 = kstar ? 0u : r.d - brem;
             sg.idx0 = lock ? ends_upto_t<GEN>(r, sg.e0) : 0u;
             sg.len = lock ? r.b - sg.idx0 : 1u;
+            // runs continued by run slices stop at the partition's cap
+            if (lock && pt.j1 && sg.len > pt.j1) sg.len = pt.j1;
             sg.pend = x.pending - kstar;
             sg.fclock = x.clock;
             // run keys: every unit not busy in a lock-step run is idle
@@ -958,7 +960,8 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             *slot_parent<W>(md.table, slot[n]) = par;
             if (jmp != kParentNone) *slot_jump<W>(md.table, slot[n]) = jmp;
           }
-          if (!x.is_clos && x.j + 1u == sg.len && !x.term && x.sgi + 1u == nseg) {
+          if (!x.is_clos && x.j + 1u == sg.len && !x.term && x.sgi + 1u == nseg &&
+              !(sg.lock && sg.idx0 + sg.len < r.b)) {  // a capped run ends in the slices
             const uint32_t pos = atomicAdd(&sh.fcount[cur ^ 1], 1u);
             if (pos < (uint32_t)kFCap) {
 #pragma unroll
@@ -1012,6 +1015,120 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
   }
 }
 
+// A run slice (Part::r0 = kRunSlice): states j0 <= j < j1 of every lock-step run of a
+// configuration with a single round.  All n <= m workgroups start at clock 0 on one of
+// the C(m, n) choices of units, so state j of the run of choice U is
+// (c, E_j, 0, d - E_j on U, 0 elsewhere): built from j alone, no frontier.  Items are
+// ordered by choice, then j.  Interior states store no links (the trace derives their
+// dispatch leaf from the key); a run's end stores its predecessor, inserted by the same
+// slice.  Inserts are agent-scope like a block's boundary states; no state of a slice
+// has a clock that another partition's states have.
+template <int W, int BLOCK, int NI, bool GEN>
+__device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLOCK, NI>& sh) {
+  Tally tl;
+  const Layout& L = md.L;
+  const int m = L.m;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t c = pt.cfg;
+  const CfgRec r = md.cfgs[c];
+  const uint32_t n = r.n;  // <= m
+  if (tid == 0) sh.T = prune_T(md);
+  if (tid < 64) {  // the choices of n units out of m, in increasing mask order
+    uint32_t off = 0;
+    for (uint32_t g0 = 1; g0 < (1u << m); g0 += 64) {
+      const uint32_t mk = g0 + tid;
+      const bool isleaf = mk < (1u << m) && (uint32_t)__popc(mk) == n;
+      const unsigned long long bm = __ballot(isleaf);
+      if (isleaf) sh.leaf[off + lanes_below(bm)] = (uint8_t)mk;
+      off += (uint32_t)__popcll(bm);
+    }
+    if (tid == 0) sh.nseg = off;  // number of choices
+  }
+  __syncthreads();
+  const uint32_t nleaf = sh.nseg, len = pt.j1 - pt.j0, total = nleaf * len;
+  const uint32_t fdep = 1u + n;  // the dispatch leaf: SELECT at depth 1, then n dispatches
+  const uint32_t T = sh.T;
+  for (uint32_t base = 0; base < total; base += NI * BLOCK) {
+    ++tl.chunks;
+    unsigned long long keys[NI][W];
+    bool act[NI], term[NI];
+    uint32_t clk[NI], dep[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const uint32_t i = base + (uint32_t)q * BLOCK + tid;
+      act[q] = i < total;
+      term[q] = false;
+      clk[q] = 0u;
+      dep[q] = 0u;
+#pragma unroll
+      for (int w = 0; w < W; ++w) keys[q][w] = 0ull;
+      if (!act[q]) continue;
+      const uint32_t leaf = i / len, j = pt.j0 + (i - leaf * len);
+      const uint32_t e = end_at_t<GEN>(r, j);
+      const uint32_t mask = sh.leaf[leaf];
+      St y{};
+      y.cfg = c;
+      y.clock = e;
+      y.pending = 0u;
+#pragma unroll
+      for (int u = 0; u < kMaxCU; ++u) y.rem[u] = ((mask >> u) & 1u) ? r.d - e : 0u;
+      const Key<W> k = encode<W>(y, L);
+#pragma unroll
+      for (int w = 0; w < W; ++w) keys[q][w] = k.w[w];
+      clk[q] = e;
+      dep[q] = fdep + j + 1u;
+      term[q] = j + 1u == r.b;
+      if (md.prune && e > T) act[q] = false;
+    }
+    uint32_t slot[NI];
+    int res[NI];
+    const uint32_t p0 = tl.probes;
+    table_insert_n<W, kScopeAgent, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+    tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
+    bool fresh[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      fresh[q] = false;
+      if (act[q]) {
+        ++tl.edges;
+        if (res[q] == kInsFail) {
+          set_error(md.ctrl, kDevErrTableFull);
+          act[q] = false;
+          slot[q] = kParentNone;
+        } else if (res[q] == kInsNew) {
+          fresh[q] = true;
+          ++tl.states;
+          tl.depth = dep[q] > tl.depth ? dep[q] : tl.depth;
+          if (term[q]) {
+            ++tl.terms;
+            atomicMin(&md.tc[c], clk[q]);
+            if (md.prune) md.ctrl->violated = 1u;
+            if (md.bb) atomicMin(&md.ctrl->bound, clk[q]);
+          }
+        } else {
+          ++tl.dups;
+        }
+      }
+      sh.chunk_slot[q * BLOCK + tid] = act[q] ? slot[q] : kParentNone;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      if (!fresh[q] || !term[q]) continue;
+      const uint32_t li = (uint32_t)q * BLOCK + tid;  // the run's previous state: item i-1
+      *slot_parent<W>(md.table, slot[q]) = li ? sh.chunk_slot[li - 1] : sh.carry;
+    }
+    __syncthreads();
+    if (tid == BLOCK - 1) sh.carry = sh.chunk_slot[NI * BLOCK - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (md.pstate) md.pstate[pt.pidx].status = 2u;
+    atomicAdd(&md.ctrl->parts_done, 1u);
+  }
+  flush_tally(md, tl);
+}
+
 template <int W, int BLOCK, int NI, bool GEN, bool HET>
 __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
   __shared__ SuperShared<BLOCK, NI> sh;
@@ -1030,7 +1147,8 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     const ModelDev& md = sh.md;
     const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
     const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
-    if (!skip) explore_partition<W, BLOCK, NI, GEN, HET>(md, pc, a.batch_items, a.slice, a, sh);
+    if (!skip && pc.r0 == kRunSlice) explore_slice<W, BLOCK, NI, GEN>(md, pc, sh);
+    else if (!skip) explore_partition<W, BLOCK, NI, GEN, HET>(md, pc, a.batch_items, a.slice, a, sh);
     if (tid == 0) {
       const unsigned long long dt = __builtin_amdgcn_s_memrealtime() - t_part;
       const unsigned long long prev = atomicMax(&md.ctrl->crit_ticks, dt);

@@ -80,9 +80,10 @@ struct ModelDev {
 // configuration passes through the single state (c, r*d, n - r*m, every unit idle), so a
 // block of whole rounds can be explored from that state on its own.
 struct Part {
-  uint32_t model, cfg, r0, r1;
+  uint32_t model, cfg, r0, r1;  // r0 = r1 = kRunSlice: a run slice [j0, j1)
   uint32_t pidx;  // index of the partition within its model (its PartState)
-  uint32_t pad[3];
+  uint32_t j0, j1;  // a run slice's states; else j1 > 0 caps the runs from SELECT
+  uint32_t pad;
 };
 static_assert(sizeof(Part) == 32, "Part layout");
 

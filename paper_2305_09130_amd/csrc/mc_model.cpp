@@ -375,6 +375,27 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
     const uint64_t per_round = ((1ull << h.m) - 1) + r.b;
     uint64_t R = cuttable ? std::max<uint64_t>(kMinBlockRounds, target / per_round) : q;
     const uint64_t K = R ? (q + R - 1) / R : 1;
+    const uint64_t slice =
+        std::min<uint64_t>(kMaxSlice, std::max<uint64_t>(kMinSlice, target));
+    if (cuttable && r.n <= h.m && r.b > slice + 1) {
+      // one round: the SELECT closure and the first `slice` states of every run, then
+      // slices of the runs (the last one keeps at least two states, so a run's end and
+      // the state before it are inserted together)
+      const uint64_t nleaf = binom(h.m, r.n);
+      PartPlan a{c, 0u, kRoundsToEnd, h.cfg_states[c] - nleaf * (r.b - slice)};
+      a.j1 = (uint32_t)slice;
+      out->push_back(a);
+      for (uint64_t j0 = slice; j0 < r.b;) {
+        uint64_t j1 = std::min<uint64_t>(j0 + slice, r.b);
+        if (r.b - j1 < 2) j1 = r.b;
+        PartPlan sp{c, kRunSlice, kRunSlice, nleaf * (j1 - j0)};
+        sp.j0 = (uint32_t)j0;
+        sp.j1 = (uint32_t)j1;
+        out->push_back(sp);
+        j0 = j1;
+      }
+      continue;
+    }
     if (!cuttable || K < 2) {
       out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
       continue;

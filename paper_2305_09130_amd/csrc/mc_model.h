@@ -90,9 +90,17 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err);
 // (r1 = kRoundsToEnd: through the terminal), with its expected state count.
 constexpr uint32_t kRoundsToEnd = 0xFFFFFFFFu;
 constexpr uint32_t kMinBlockRounds = 8;  // shortest block worth a partition of its own
+// A run slice: states j0 <= j < j1 of every lock-step run of a configuration with a
+// single round (n <= m workgroups all start at clock 0, so run j of every choice of
+// units is (c, E_j, 0, d - E_j on the chosen units)); the partition that holds the
+// configuration's SELECT closure then explores its runs only up to j1 of its plan
+// (its `j1`, 0 = whole runs).
+constexpr uint32_t kRunSlice = 0xFFFFFFFEu;
+constexpr uint32_t kMinSlice = 64, kMaxSlice = 8192;
 struct PartPlan {
   uint32_t cfg, r0, r1;
   uint64_t states;
+  uint32_t j0 = 0, j1 = 0;
 };
 
 // Partitions of a model.  Each configuration's subgraph is cut into blocks of whole
@@ -100,7 +108,10 @@ struct PartPlan {
 // state reached after r0 full rounds, (c, r0 d, n - r0 m, all units idle), which every
 // path of the configuration passes through.  A cut needs the configuration index, the
 // pending count and the clock in key word 0: two blocks then share no word-0 value
-// except their common boundary state.
+// except their common boundary state.  Under the same condition a configuration with a
+// single round whose runs are longer than a slice of about `target` states (64..8192)
+// is cut into run slices (every state of a slice has a clock no other partition's
+// states have).
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
 
 // Default target states per partition for a launch exploring `states` states in total.
