@@ -373,15 +373,19 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
     const CfgRec& r = h.cfgs[c];
     const uint64_t q = r.n / h.m;
     const uint64_t per_round = ((1ull << h.m) - 1) + r.b;
-    uint64_t R = cuttable ? std::max<uint64_t>(kMinBlockRounds, target / per_round) : q;
+    // blocks of at least kMinBlockRounds rounds, or of fewer when the rounds are long
+    const uint64_t min_rounds = std::min<uint64_t>(
+        kMinBlockRounds, std::max<uint64_t>(1, (kMinBlockStates + per_round - 1) / per_round));
+    uint64_t R = cuttable ? std::max<uint64_t>(min_rounds, target / per_round) : q;
     const uint64_t K = R ? (q + R - 1) / R : 1;
-    const uint64_t slice =
-        std::min<uint64_t>(kMaxSlice, std::max<uint64_t>(kMinSlice, target));
+    const uint64_t nleaf = r.n <= h.m ? binom(h.m, r.n) : 1;
+    // a slice spans every run (one per choice of units), about `target` states in all
+    const uint64_t slice = std::max<uint64_t>(
+        kMinSlice, std::min<uint64_t>(kMaxSlice, std::max<uint64_t>(kMinSlice, target)) / nleaf);
     if (cuttable && r.n <= h.m && r.b > slice + 1) {
       // one round: the SELECT closure and the first `slice` states of every run, then
       // slices of the runs (the last one keeps at least two states, so a run's end and
       // the state before it are inserted together)
-      const uint64_t nleaf = binom(h.m, r.n);
       PartPlan a{c, 0u, kRoundsToEnd, h.cfg_states[c] - nleaf * (r.b - slice)};
       a.j1 = (uint32_t)slice;
       out->push_back(a);

@@ -89,7 +89,8 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err);
 // One partition of a model's exploration: rounds [r0, r1) of configuration cfg
 // (r1 = kRoundsToEnd: through the terminal), with its expected state count.
 constexpr uint32_t kRoundsToEnd = 0xFFFFFFFFu;
-constexpr uint32_t kMinBlockRounds = 8;  // shortest block worth a partition of its own
+constexpr uint32_t kMinBlockRounds = 8;     // shortest block worth a partition of its own,
+constexpr uint32_t kMinBlockStates = 2048;  // unless fewer rounds already hold this many
 // A run slice: states j0 <= j < j1 of every lock-step run of a configuration with a
 // single round (n <= m workgroups all start at clock 0, so run j of every choice of
 // units is (c, E_j, 0, d - E_j on the chosen units)); the partition that holds the
@@ -109,9 +110,9 @@ struct PartPlan {
 // path of the configuration passes through.  A cut needs the configuration index, the
 // pending count and the clock in key word 0: two blocks then share no word-0 value
 // except their common boundary state.  Under the same condition a configuration with a
-// single round whose runs are longer than a slice of about `target` states (64..8192)
-// is cut into run slices (every state of a slice has a clock no other partition's
-// states have).
+// single round whose runs are longer than a slice is cut into run slices: each spans
+// every run of the configuration over about max(64, min(8192, target) / runs) states
+// of each (every state of a slice has a clock no other partition's states have).
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
 
 // Default target states per partition for a launch exploring `states` states in total.
