@@ -329,6 +329,7 @@ struct SuperShared {
   // generates it, and whether it was reached
   unsigned long long stopkey[4];
   uint32_t has_stop, stop_clock, stop_dep, stop_item, stop_slot, handed;
+  uint32_t stop_capped;  // B_r1 ends a run cut short by run slices: no item generates it
   uint32_t T;   // prune threshold of this super-step (check(T), or the incumbent)
   ModelDev md;  // descriptor of the model being explored
   // successors of the leaves of a segment whose run is not in lock step (one ADVANCE
@@ -575,6 +576,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
   if (tid == 0) {
     sh.has_stop = 0u;
     sh.handed = 0u;
+    sh.stop_capped = 0u;
     sh.stop_item = kNoItem;
     sh.T = prune_T(md);
     const Seed sd = md.seeds[c];
@@ -666,6 +668,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         uint32_t fslot = sh.fslot[cur][fi], fdep = sh.fdep[cur][fi];
         uint32_t total = 0, nseg = 0;
         sh.stop_item = kNoItem;
+        sh.stop_capped = 0u;
         bool decoded = false;  // sh.seg[nseg] already derived from the previous segment
         for (;;) {
           SegDesc& sg = sh.seg[nseg];
@@ -751,13 +754,16 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             if (end_clock == sh.stop_clock) {
               // the run end is B_r1: generated by the same arithmetic as every run end,
               // it must be the state r1 full rounds give, at the depth they give
-              sh.stop_item = total - 1u;  // the last run state of this segment
+              // the last run state of this segment, unless run slices hold the run's end
+              const bool capped = sg.len < r.b - sg.idx0;
+              sh.stop_item = capped ? kNoItem : total - 1u;
+              sh.stop_capped = capped ? 1u : 0u;
               sh.stop_slot = kParentNone;
               unsigned long long ek[W];
 #pragma unroll
               for (int w = 0; w < W; ++w) ek[w] = sg.base[w];
               field_add<W>(ek, L, kFClock, end_clock);
-              bool ok = fdep + sg.kstar + sg.len == sh.stop_dep;
+              bool ok = fdep + sg.kstar + (r.b - sg.idx0) == sh.stop_dep;
               Key<W> k;
 #pragma unroll
               for (int w = 0; w < W; ++w) {
@@ -987,6 +993,13 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             sg.len > 1u ? sh.chunk_slot[(stop_item - 1u) % (NI * BLOCK)] : leaf_slot;
         *slot_parent<W>(md.table, sh.stop_slot) = par;
         *slot_jump<W>(md.table, sh.stop_slot) = leaf_slot;
+      } else if (sh.stop_capped && tid == 0 && sh.stop_slot != kParentNone) {
+        // B_r1 after a run whose later states are in run slices: the run is regenerated
+        // from its dispatch leaf, which is both links
+        const SegDesc& sg = sh.seg[nseg - 1u];
+        const uint32_t leaf_slot = sh.mslot[nseg - 1u][(1u << sg.nfree) - 1u];
+        *slot_parent<W>(md.table, sh.stop_slot) = leaf_slot;
+        *slot_jump<W>(md.table, sh.stop_slot) = leaf_slot;
       }
     }
     if (tid == 0) sh.fcount[cur] = 0u;
@@ -1015,14 +1028,17 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
   }
 }
 
-// A run slice (Part::r0 = kRunSlice): states j0 <= j < j1 of every lock-step run of a
-// configuration with a single round.  All n <= m workgroups start at clock 0 on one of
-// the C(m, n) choices of units, so state j of the run of choice U is
-// (c, E_j, 0, d - E_j on U, 0 elsewhere): built from j alone, no frontier.  Items are
-// ordered by choice, then j.  Interior states store no links (the trace derives their
-// dispatch leaf from the key); a run's end stores its predecessor, inserted by the same
-// slice.  Inserts are agent-scope like a block's boundary states; no state of a slice
-// has a clock that another partition's states have.
+// A run slice (Part::r0 = kRunSlice, Part::r1 = the round r): states j0 <= j < j1 of
+// every lock-step run of round r of a configuration.  At the start of the round every
+// unit is idle (clock r*d, n - r*m pending) and k = min(m, n - r*m) workgroups start on
+// one of the C(m, k) choices of units, so state j of the run of choice U is
+// (c, r*d + E_j, n - r*m - k, d - E_j on U, 0 elsewhere): built from j alone, no
+// frontier.  Items are ordered by choice, then j.  Interior states store no links (the
+// trace derives their dispatch leaf from the key); a run ending at a terminal stores its
+// predecessor, inserted by the same slice; a run ending at the next round's start is
+// not in a slice (the round's block claims that state).  Inserts are agent-scope like a
+// block's boundary states; no state of a slice has a (pending, clock) pair that another
+// partition's states have.
 template <int W, int BLOCK, int NI, bool GEN>
 __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLOCK, NI>& sh) {
   Tally tl;
@@ -1031,13 +1047,16 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
   const uint32_t tid = threadIdx.x;
   const uint32_t c = pt.cfg;
   const CfgRec r = md.cfgs[c];
-  const uint32_t n = r.n;  // <= m
+  const uint32_t rd = pt.r1;  // the round
+  const uint32_t left = r.n - rd * (uint32_t)m;
+  const uint32_t k = left < (uint32_t)m ? left : (uint32_t)m;
+  const uint32_t pend = left - k;
   if (tid == 0) sh.T = prune_T(md);
-  if (tid < 64) {  // the choices of n units out of m, in increasing mask order
+  if (tid < 64) {  // the choices of k units out of m, in increasing mask order
     uint32_t off = 0;
     for (uint32_t g0 = 1; g0 < (1u << m); g0 += 64) {
       const uint32_t mk = g0 + tid;
-      const bool isleaf = mk < (1u << m) && (uint32_t)__popc(mk) == n;
+      const bool isleaf = mk < (1u << m) && (uint32_t)__popc(mk) == k;
       const unsigned long long bm = __ballot(isleaf);
       if (isleaf) sh.leaf[off + lanes_below(bm)] = (uint8_t)mk;
       off += (uint32_t)__popcll(bm);
@@ -1046,7 +1065,9 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
   }
   __syncthreads();
   const uint32_t nleaf = sh.nseg, len = pt.j1 - pt.j0, total = nleaf * len;
-  const uint32_t fdep = 1u + n;  // the dispatch leaf: SELECT at depth 1, then n dispatches
+  // the dispatch leaf's depth: SELECT at 1, m dispatches and b advances per round, k more
+  const uint32_t fdep = 1u + rd * ((uint32_t)m + r.b) + k;
+  const uint32_t clock0 = rd * r.d;
   const uint32_t T = sh.T;
   for (uint32_t base = 0; base < total; base += NI * BLOCK) {
     ++tl.chunks;
@@ -1068,17 +1089,17 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
       const uint32_t mask = sh.leaf[leaf];
       St y{};
       y.cfg = c;
-      y.clock = e;
-      y.pending = 0u;
+      y.clock = clock0 + e;
+      y.pending = pend;
 #pragma unroll
       for (int u = 0; u < kMaxCU; ++u) y.rem[u] = ((mask >> u) & 1u) ? r.d - e : 0u;
-      const Key<W> k = encode<W>(y, L);
+      const Key<W> yk = encode<W>(y, L);
 #pragma unroll
-      for (int w = 0; w < W; ++w) keys[q][w] = k.w[w];
-      clk[q] = e;
+      for (int w = 0; w < W; ++w) keys[q][w] = yk.w[w];
+      clk[q] = y.clock;
       dep[q] = fdep + j + 1u;
-      term[q] = j + 1u == r.b;
-      if (md.prune && e > T) act[q] = false;
+      term[q] = pend == 0u && j + 1u == r.b;
+      if (md.prune && y.clock > T) act[q] = false;
     }
     uint32_t slot[NI];
     int res[NI];

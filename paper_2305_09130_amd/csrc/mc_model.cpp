@@ -378,25 +378,66 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
         kMinBlockRounds, std::max<uint64_t>(1, (kMinBlockStates + per_round - 1) / per_round));
     uint64_t R = cuttable ? std::max<uint64_t>(min_rounds, target / per_round) : q;
     const uint64_t K = R ? (q + R - 1) / R : 1;
-    const uint64_t nleaf = r.n <= h.m ? binom(h.m, r.n) : 1;
-    // a slice spans every run (one per choice of units), about `target` states in all
-    const uint64_t slice = std::max<uint64_t>(
-        kMinSlice, std::min<uint64_t>(kMaxSlice, std::max<uint64_t>(kMinSlice, target)) / nleaf);
-    if (cuttable && r.n <= h.m && r.b > slice + 1) {
-      // one round: the SELECT closure and the first `slice` states of every run, then
-      // slices of the runs (the last one keeps at least two states, so a run's end and
-      // the state before it are inserted together)
-      PartPlan a{c, 0u, kRoundsToEnd, h.cfg_states[c] - nleaf * (r.b - slice)};
-      a.j1 = (uint32_t)slice;
-      out->push_back(a);
-      for (uint64_t j0 = slice; j0 < r.b;) {
-        uint64_t j1 = std::min<uint64_t>(j0 + slice, r.b);
-        if (r.b - j1 < 2) j1 = r.b;
-        PartPlan sp{c, kRunSlice, kRunSlice, nleaf * (j1 - j0)};
+    const uint64_t p = r.n % h.m;
+    // a slice spans every run of its round (one per choice of units), about `target`
+    // states in all
+    const auto slice_of = [&](uint64_t choices) {
+      return std::max<uint64_t>(
+          kMinSlice,
+          std::min<uint64_t>(kMaxSlice, std::max<uint64_t>(kMinSlice, target)) / choices);
+    };
+    // run slices of round rd: states [sl, b) of its runs when they end at a terminal (the
+    // last slice keeps at least two states, so a run's end and the state before it are
+    // inserted together), else [sl, b - 1) (the next round's start is the block's)
+    const auto add_slices = [&](uint64_t rd, uint64_t choices, uint64_t sl, bool terminal) {
+      const uint64_t end = terminal ? r.b : r.b - 1;
+      for (uint64_t j0 = sl; j0 < end;) {
+        uint64_t j1 = std::min<uint64_t>(j0 + sl, end);
+        if (terminal && end - j1 < 2) j1 = end;
+        PartPlan sp{c, kRunSlice, (uint32_t)rd, choices * (j1 - j0)};
         sp.j0 = (uint32_t)j0;
         sp.j1 = (uint32_t)j1;
         out->push_back(sp);
         j0 = j1;
+      }
+    };
+    if (cuttable && r.n <= h.m) {
+      // one round: the SELECT closure and the first `slice` states of every run, then
+      // slices of the runs
+      const uint64_t choices = binom(h.m, r.n), sl = slice_of(choices);
+      if (r.b > sl + 1) {
+        PartPlan a{c, 0u, kRoundsToEnd, h.cfg_states[c] - choices * (r.b - sl)};
+        a.j1 = (uint32_t)sl;
+        out->push_back(a);
+        add_slices(0, choices, sl, true);
+        continue;
+      }
+    }
+    const uint64_t sl1 = slice_of(1);
+    if (cuttable && R == 1 && q >= 1 && r.n > h.m && r.b > sl1 + 1) {
+      // long rounds: one block per round that explores the round's closure and the first
+      // `sl1` states of its run and claims the next round's start; slices hold the rest
+      const uint64_t full_blocks = p ? q : q - 1;  // rounds whose block ends at a cut
+      for (uint64_t k = 0; k < full_blocks; ++k) {
+        PartPlan b{c, (uint32_t)k, (uint32_t)(k + 1), per_round - (r.b - 1 - sl1)};
+        b.j1 = (uint32_t)sl1;
+        out->push_back(b);
+        add_slices(k, 1, sl1, false);
+      }
+      if (p) {  // the partial round, to the terminals
+        const uint64_t choices = binom(h.m, (uint32_t)p), slp = slice_of(choices);
+        const bool cut = r.b > slp + 1;
+        PartPlan b{c, (uint32_t)q, kRoundsToEnd,
+                   h.cfg_states[c] - q * per_round - (cut ? choices * (r.b - slp) : 0)};
+        b.j1 = cut ? (uint32_t)slp : 0u;
+        out->push_back(b);
+        if (cut) add_slices(q, choices, slp, true);
+      } else {  // the last full round, to the terminal
+        PartPlan b{c, (uint32_t)(q - 1), kRoundsToEnd, (uint64_t)h.cfg_states[c] -
+                                                      (q - 1) * per_round - (r.b - sl1)};
+        b.j1 = (uint32_t)sl1;
+        out->push_back(b);
+        add_slices(q - 1, 1, sl1, true);
       }
       continue;
     }

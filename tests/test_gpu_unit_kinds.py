@@ -185,3 +185,37 @@ def test_unit_swarm_members_equal_oracle(mc):
             oracle.check_trace(model, g.mc_swarm_trace(), target_clock=r["best_clock"],
                                cfgs=[r["best_cfg"]])
     g.close()
+
+
+def test_table1_rows_on_the_gpu(mc):
+    """Table 1 rows 1-5 (tests/golden/table1_abstract.txt): the printed model time is
+    T_min of the printed configuration on one unit of four elements with GMT = 4, now
+    computed by the HIP path."""
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table1_abstract.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append([int(v) for v in line.split()])
+    for n, size, t_printed, ts, wg in rows[:5]:
+        model = workloads.unit_model(workloads.KIND_ABSTRACT, size, workloads.PAPER_NP, 1,
+                                     [wg], [ts], workloads.PAPER_GMT, workloads.PAPER_LOCAL)
+        g = mc.Model(model)
+        assert g.mc_min_time()[0] == t_printed, (n, size)
+        g.close()
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_long_rounds_cut_into_round_blocks_and_run_slices(mc, m):
+    """Workgroups of 2056 operation ends (8 waves of 257): with small partitions every
+    round is a block of its own and its run beyond 64 states goes to run slices (m = 3:
+    16 workgroups leave a partial round with 3 choices of units)."""
+    model = workloads.unit_model(workloads.KIND_ABSTRACT, 256, 1, m, [8, 4], [2], 3, 1)
+    _say(f"long rounds m={m}")
+    r = oracle.explore(model)
+    for ps in (1, 0):
+        g = mc.Model(model, part_states=ps)
+        check_min_time(g, model, r)
+        for T in (r["t_min"] - 1, r["t_min"], max(r["tc"]) // 2):
+            check_threshold(mc, g, model, T, oracle.explore(model, T=T))
+        assert g.mc_min_time_bb(0) == (r["t_min"], r["argmin"])
+        g.close()
