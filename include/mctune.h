@@ -143,7 +143,9 @@ typedef struct mc_opts {
                                 1 for wider keys) */
     uint32_t part_states;    /* super-step engine: target states per partition when a
                                 configuration's subgraph is cut into blocks of whole
-                                rounds (0 = automatic, UINT32_MAX = never cut) */
+                                rounds and its long lock-step runs into run slices (a
+                                round's states j0..j1-1 of every run; 64..8192 states per
+                                slice) (0 = automatic, UINT32_MAX = never cut) */
 } mc_opts;
 
 /* ---- statistics of the last query ---------------------------------------------- */

@@ -729,6 +729,10 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             }
             sg.aux = (kstar && busy == 0u && nleaf == 1u) ? 1u : 0u;  // a full round start
             sg.pad = 0u;
+            // units of unequal speed, every idle unit takes work (one leaf): the segment
+            // holds the dispatch closure only and the leaf's determined steps follow as
+            // a chain segment in the same super-step
+            if (HET && L.hetero && !lock && kstar && nleaf == 1u) sg.len = 0u;
             if (HET && L.hetero && !lock && kstar == 0u) {
               // units of unequal speed with nothing to dispatch: the ADVANCE steps up to
               // the next state with a dispatch (or the terminal) are determined; the
@@ -742,6 +746,38 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           sg.start = total;
           total += sg.nclos + sg.nleaf * sg.len;
           ++nseg;
+          if (HET && L.hetero && !sg.lock && sg.kstar && sg.nleaf == 1u) {
+            SegDesc& nx = sh.seg[nseg];
+            Key<W> lk;
+#pragma unroll
+            for (int w = 0; w < W; ++w) lk.w[w] = sg.fkey[w];
+            St y = decode<W>(lk, L);
+#pragma unroll
+            for (int u = 0; u < kMaxCU; ++u)
+              if ((sg.freem >> u) & 1u) y.rem[u] = unit_dur<GEN>(r, L.speed, u);
+            y.pending -= sg.kstar;
+            const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+            for (int w = 0; w < W; ++w) nx.fkey[w] = yk.w[w];
+            nx.kstar = 0u;
+            nx.freem = 0u;
+            nx.nfree = 0u;
+            nx.nclos = 0u;
+            nx.nleaf = 1u;
+            nx.lock = 0u;
+            nx.aux = 0u;
+            nx.pad = 1u;  // a chain: build_chain lists it and sets its length
+            nx.len = 0u;
+            nx.e0 = 0u;
+            nx.idx0 = 0u;
+            nx.pend = y.pending;
+            nx.fclock = y.clock;
+            nx.fdep = fdep + sg.kstar;
+            nx.fslot = kParentNone;  // the leaf: its slot comes from the closure's items
+            nx.start = total;
+            ++nseg;
+            break;
+          }
           // continue with the run end: a single lock-step run ending with work pending
           const uint32_t end_clock = sg.fclock + (r.d - sg.e0);
           if (sh.has_stop) {
@@ -936,7 +972,13 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
               ++tl.dups;
             }
             const SegDesc& sg = sh.seg[it[n].sgi];
-            if (it[n].is_clos) sh.mslot[it[n].sgi][it[n].rmask] = slot[n];
+            if (it[n].is_clos) {
+              sh.mslot[it[n].sgi][it[n].rmask] = slot[n];
+              // the full dispatch leaf starts the chain segment that follows
+              if (HET && it[n].rmask == (1u << sg.nfree) - 1u && it[n].sgi + 1u < nseg &&
+                  sh.seg[it[n].sgi + 1u].pad)
+                sh.segfslot[it[n].sgi + 1u] = slot[n];
+            }
             else if (it[n].j + 1u == sg.len && it[n].sgi + 1u < nseg)
               sh.segfslot[it[n].sgi + 1u] = slot[n];
           }
