@@ -144,7 +144,7 @@ typedef struct mc_opts {
     uint32_t part_states;    /* super-step engine: target states per partition when a
                                 configuration's subgraph is cut into blocks of whole
                                 rounds and its long lock-step runs into run slices (a
-                                round's states j0..j1-1 of every run; 64..8192 states per
+                                round's states j0..j1-1 of every run; 1024..8192 states per
                                 slice) (0 = automatic, UINT32_MAX = never cut) */
 } mc_opts;
 

@@ -309,15 +309,16 @@ int mc_engine_submit(mc_engine* e, const mc_desc* model, uint32_t kind, uint32_t
     }
     q->kind = kind;
     q->T = T;
-    // blocks of about states/256 (at most kExtraParts more partitions than
-    // configurations), whole configurations if that bound is still exceeded
+    // blocks of about states/256, with larger blocks while the plan has more than
+    // kExtraParts partitions beyond one per configuration (whole configurations last)
     const uint32_t ps = e->opts.part_states;
-    plan_parts(q->mh,
-               ps == 0xFFFFFFFFu ? 0u : ps ? ps : std::max<uint64_t>(1, q->mh.states / kExtraParts),
-               &q->parts);
-    if (q->parts.size() > (size_t)q->mh.n_cfg + kExtraParts) {
+    uint64_t target =
+        ps == 0xFFFFFFFFu ? 0u : ps ? ps : std::max<uint64_t>(1, q->mh.states / kExtraParts);
+    plan_parts(q->mh, target, &q->parts);
+    while (target && q->parts.size() > (size_t)q->mh.n_cfg + kExtraParts) {
+      target = target >= (1ull << 40) ? 0u : target * 4;
       q->parts.clear();
-      plan_parts(q->mh, 0, &q->parts);
+      plan_parts(q->mh, target, &q->parts);
     }
     std::stable_sort(q->parts.begin(), q->parts.end(),
                      [](const PartPlan& a, const PartPlan& b) { return a.states > b.states; });

@@ -97,7 +97,7 @@ constexpr uint32_t kMinBlockStates = 2048;  // unless fewer rounds already hold 
 // configuration's SELECT closure then explores its runs only up to j1 of its plan
 // (its `j1`, 0 = whole runs).
 constexpr uint32_t kRunSlice = 0xFFFFFFFEu;
-constexpr uint32_t kMinSlice = 64, kMaxSlice = 8192;
+constexpr uint32_t kMinSlice = 1024, kMaxSlice = 8192;
 struct PartPlan {
   uint32_t cfg, r0, r1;
   uint64_t states;
@@ -111,7 +111,7 @@ struct PartPlan {
 // pending count and the clock in key word 0: two blocks then share no word-0 value
 // except their common boundary state.  Under the same condition a configuration with a
 // single round whose runs are longer than a slice is cut into run slices: each spans
-// every run of the configuration over about max(64, min(8192, target) / runs) states
+// every run of the configuration over about max(1024, min(8192, target) / runs) states
 // of each (every state of a slice has a clock no other partition's states have).
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
 
