@@ -294,11 +294,12 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
 // ends exactly on B_r1 with the depth r1 rounds give, so that the union of the blocks
 // is the configuration's whole subgraph.
 constexpr int kSegMax = 8;
+constexpr int kSegMaxChain = 32;  // segments of a batch on units of unequal speed
 constexpr uint32_t kNoItem = 0xFFFFFFFFu;
 constexpr int kEMax = 4096;  // operation ends kept in LDS
 constexpr int kFCap = 256;   // frontier states per super-step level (LDS)
 constexpr int kMaxLeaves = 72;  // C(8, 4) = 70 leaves at most
-constexpr int kChainCand = 8 * 64;       // chain candidates: 64 ends to go per unit
+constexpr int kChainCand = 8 * 64;       // chain candidates: 512 / m ends to go per unit
 constexpr int kChainTimes = 1024;        // the chain's times, listed in E from here
 static_assert(kChainTimes >= kChainCand + 1 && kChainTimes + kChainCand <= kEMax, "E use");
 
@@ -312,19 +313,20 @@ struct SegDesc {
   uint32_t fslot, nfree, aux, pad;  // pad: 1 for a chain (states listed in gkey)
 };
 
-template <int BLOCK, int NI>
+template <int BLOCK, int NI, int SEGS = kSegMax>
 struct SuperShared {
   uint32_t E[kEMax];
-  uint32_t mslot[kSegMax][256];
+  uint32_t mslot[SEGS][256];
   uint8_t leaf[256];
   uint32_t chunk_slot[NI * BLOCK];
-  SegDesc seg[kSegMax];
-  uint32_t segfslot[kSegMax];
+  SegDesc seg[SEGS];
+  uint32_t segfslot[SEGS];
   unsigned long long fkey[2][kFCap][4];
   uint32_t fslot[2][kFCap];
   uint32_t fdep[2][kFCap];
   uint32_t fcount[2];
   uint32_t part, carry, stop, nseg, total;
+  uint32_t chain_more;  // another chain joined the batch: list it
   // end of a block of rounds: the state B_r1, its clock and depth, the batch item that
   // generates it, and whether it was reached
   unsigned long long stopkey[4];
@@ -365,9 +367,9 @@ struct Item {
 
 // State number i of the current batch: a closure state (a set of started units) or the
 // j-th state of a run from a leaf, built directly from the segment's templates.
-template <int W, int BLOCK, int NI, bool KEY, bool GEN, bool HET>
+template <int W, int BLOCK, int NI, bool KEY, bool GEN, bool HET, int SEGS>
 __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t nseg,
-                                         const SuperShared<BLOCK, NI>& sh, const CfgRec& r,
+                                         const SuperShared<BLOCK, NI, SEGS>& sh, const CfgRec& r,
                                          bool e_lds, const ModelDev& md, int m, Item<W>& it) {
   const Layout& L = md.L;
   it.active = i < total;
@@ -441,7 +443,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
 #pragma unroll
     for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
     St y = decode<W>(fk, L);
-    const uint32_t tau = sh.E[kChainTimes + it.j], dt = tau - y.clock;
+    const uint32_t tau = sh.E[kChainTimes + sg.idx0 + it.j], dt = tau - y.clock;
 #pragma unroll
     for (int u = 0; u < kMaxCU; ++u) y.rem[u] = y.rem[u] > dt ? y.rem[u] - dt : 0u;
     y.clock = tau;
@@ -468,14 +470,15 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
 // A chain on units of unequal speed: from the frontier state x of the last segment (no
 // DISPATCH enabled) the clock visits the union of the busy units' operation ends, up to
 // the first workgroup end while work is pending (then a DISPATCH follows), or to the
-// terminal.  Every lane writes one candidate end (unit u, its k-th end to go, k < 64)
-// into the LDS table E (unused on such models: no run is in lock step), the workgroup
-// sorts the candidates (bitonic), and one wavefront keeps the distinct times up to the
-// smallest 64th candidate of any unit (below it no end of any unit is missing), in
-// order, as the chain's states.  Their number is the segment's length.
-template <int W, int BLOCK, int NI>
-__device__ __noinline__ void build_chain(SuperShared<BLOCK, NI>& sh, const CfgRec& r, const Layout& L,
-                            int m) {
+// terminal.  Every lane writes one candidate end (unit u, its k-th end to go, k < p =
+// 512 / m) into the LDS table E (unused on such models: no run is in lock step), the
+// workgroup sorts the candidates (bitonic), and one wavefront keeps the distinct times
+// up to the smallest p-th candidate of any unit (below it no end of any unit is missing), in
+// order, as the chain's states, from E[kChainTimes + idx0] (the batch's chains are
+// listed one after another).  Their number is the segment's length.
+template <int W, int BLOCK, int NI, int SEGS>
+__device__ __noinline__ void build_chain(SuperShared<BLOCK, NI, SEGS>& sh, const CfgRec& r,
+                                         const Layout& L, int m) {
   const uint32_t tid = threadIdx.x;
   SegDesc& sg = sh.seg[sh.nseg - 1];
   Key<W> fk;
@@ -487,11 +490,12 @@ __device__ __noinline__ void build_chain(SuperShared<BLOCK, NI>& sh, const CfgRe
     for (int u = 0; u < m; ++u)
       if (x.rem[u]) H = min(H, x.clock + x.rem[u]);
   uint32_t* ct = sh.E;
-  if (tid == 0) ct[kChainCand] = 0xFFFFFFFFu;  // the smallest 64th candidate
+  if (tid == 0) ct[kChainCand] = 0xFFFFFFFFu;  // the smallest last-slot candidate
   __syncthreads();
+  const uint32_t per = (uint32_t)kChainCand / (uint32_t)m;  // candidates per unit
   for (uint32_t i = tid; i < (uint32_t)kChainCand; i += BLOCK) {
-    const int u = (int)(i >> 6);
-    const uint32_t k = i & 63u;
+    const int u = (int)(i / per);
+    const uint32_t k = i - (uint32_t)u * per;
     uint32_t v = 0xFFFFFFFFu;
     if (u < m && x.rem[u]) {
       const uint32_t sp = L.speed[u];
@@ -501,7 +505,7 @@ __device__ __noinline__ void build_chain(SuperShared<BLOCK, NI>& sh, const CfgRe
         const uint32_t tau = x.clock + sp * end_at(r, kk) - e;
         if (tau <= H) {
           v = tau;
-          if (k == 63u) atomicMin(&ct[kChainCand], tau);
+          if (k + 1u == per) atomicMin(&ct[kChainCand], tau);
         }
       }
     }
@@ -537,17 +541,116 @@ __device__ __noinline__ void build_chain(SuperShared<BLOCK, NI>& sh, const CfgRe
       const uint32_t y = __shfl_up(incl, off);
       if ((int)tid >= off) incl += y;
     }
-    uint32_t j = incl - cnt;
+    uint32_t j = kChainTimes + sg.idx0 + incl - cnt;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const uint32_t i = tid * kPer + q, v = ct[i];
-      if (v <= lim && v != 0xFFFFFFFFu && (i == 0u || v != ct[i - 1])) ct[kChainTimes + j++] = v;
+      if (v <= lim && v != 0xFFFFFFFFu && (i == 0u || v != ct[i - 1])) ct[j++] = v;
     }
     if (tid == 63) {
       sg.len = incl;
       sh.total = sg.start + incl;
     }
   }
+}
+
+// After a chain is listed (thread 0): when its last state is neither terminal nor a
+// choice among units (its dispatch has one leaf), what follows it is determined too, and
+// joins the same batch: the dispatch closure (every idle unit takes a workgroup) and the
+// chain from its leaf, or, after a chain cut by its candidate window, the chain that
+// continues it.  sh.chain_more tells the workgroup to list the new chain.  Only a
+// choice among units, a terminal, the prune threshold or the batch's room ends a batch.
+template <int W, int BLOCK, int NI, int SEGS, bool GEN>
+__device__ __noinline__ void extend_chain(SuperShared<BLOCK, NI, SEGS>& sh, const CfgRec& r,
+                                          const ModelDev& md, int m, uint32_t batch_items) {
+  const Layout& L = md.L;
+  sh.chain_more = 0u;
+  uint32_t nseg = sh.nseg;
+  const SegDesc& sg = sh.seg[nseg - 1u];
+  const uint32_t off = sg.idx0 + sg.len;  // the next chain's times start here
+  if (sg.len == 0u || nseg + 2u > (uint32_t)SEGS || sh.total >= batch_items ||
+      off + (uint32_t)kChainCand > (uint32_t)(kEMax - kChainTimes))
+    return;
+  const uint32_t tau = sh.E[kChainTimes + off - 1u];
+  if ((md.prune && tau > sh.T) || tau > md.max_clock) return;
+  Key<W> fk;
+#pragma unroll
+  for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
+  St y = decode<W>(fk, L);
+  const uint32_t dt = tau - y.clock;
+  uint32_t freem = 0;
+#pragma unroll
+  for (int u = 0; u < kMaxCU; ++u) {
+    y.rem[u] = y.rem[u] > dt ? y.rem[u] - dt : 0u;
+    if (u < m && y.rem[u] == 0u) freem |= 1u << u;
+  }
+  y.clock = tau;
+  if (is_terminal(y, m)) return;
+  const uint32_t nfree = (uint32_t)__popc(freem);
+  const uint32_t kstar = y.pending < nfree ? y.pending : nfree;
+  if (kstar && kstar < nfree) return;  // C(nfree, kstar) > 1 leaves: a choice
+  const uint32_t dep = sg.fdep + sg.len;  // depth of the chain's last state
+  uint32_t total = sh.total;
+  if (kstar) {
+    SegDesc& cs = sh.seg[nseg];
+    const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      cs.fkey[w] = w < W ? yk.w[w] : 0ull;
+      cs.base[w] = 0ull;
+      cs.M[w] = 0ull;
+    }
+    cs.kstar = kstar;
+    cs.freem = freem;
+    cs.nfree = nfree;
+    cs.nclos = (1u << nfree) - 1u;
+    cs.nleaf = 1u;
+    cs.lock = 0u;
+    cs.aux = 0u;
+    cs.pad = 0u;
+    cs.len = 0u;
+    cs.e0 = 0u;
+    cs.idx0 = 0u;
+    cs.pend = y.pending - kstar;
+    cs.fclock = tau;
+    cs.fdep = dep;
+    cs.fslot = kParentNone;  // the chain's last state: its slot comes from that item
+    cs.start = total;
+    total += cs.nclos;
+    ++nseg;
+#pragma unroll
+    for (int u = 0; u < kMaxCU; ++u)
+      if ((freem >> u) & 1u) y.rem[u] = unit_dur<GEN>(r, L.speed, u);
+    y.pending -= kstar;
+  }
+  SegDesc& nx = sh.seg[nseg];
+  const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    nx.fkey[w] = w < W ? yk.w[w] : 0ull;
+    nx.base[w] = 0ull;
+    nx.M[w] = 0ull;
+  }
+  nx.kstar = 0u;
+  nx.freem = 0u;
+  nx.nfree = 0u;
+  nx.nclos = 0u;
+  nx.nleaf = 1u;
+  nx.lock = 0u;
+  nx.aux = 0u;
+  nx.pad = 1u;
+  nx.len = 0u;
+  nx.e0 = 0u;
+  nx.idx0 = off;
+  nx.pend = y.pending;
+  nx.fclock = tau;
+  nx.fdep = dep + kstar;
+  nx.fslot = kParentNone;
+  nx.start = total;
+  ++nseg;
+  sh.nseg = nseg;
+  sh.total = total;
+  sh.chain_more = 1u;
 }
 
 // Prune threshold: the query's T, or under branch and bound the least terminal clock
@@ -560,10 +663,10 @@ __device__ __forceinline__ uint32_t prune_T(const ModelDev& md) {
   return b < md.T ? b : md.T;
 }
 
-template <int W, int BLOCK, int NI, bool GEN, bool HET>
+template <int W, int BLOCK, int NI, bool GEN, bool HET, int SEGS>
 __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t batch_items,
                                   uint32_t slice, const PartQueue& pq,
-                                  SuperShared<BLOCK, NI>& sh) {
+                                  SuperShared<BLOCK, NI, SEGS>& sh) {
   Tally tl;
   const Layout& L = md.L;
   const int m = L.m;
@@ -832,7 +935,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             }
           }
           const bool more = sg.lock && sg.nleaf == 1u && sg.pend > 0u &&
-                            nseg < (uint32_t)kSegMax && total < batch_items &&
+                            nseg < (uint32_t)SEGS && total < batch_items &&
                             !(md.prune && end_clock > sh.T) && end_clock <= md.max_clock;
           if (!more) break;
           // the run end: every unit idle, `pend` workgroups pending
@@ -867,8 +970,13 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
       __syncthreads();
       if constexpr (HET) {
         if (sh.nseg && sh.seg[sh.nseg - 1].pad) {
-          build_chain<W, BLOCK, NI>(sh, r, L, m);
-          __syncthreads();
+          for (;;) {
+            build_chain<W, BLOCK, NI>(sh, r, L, m);
+            __syncthreads();
+            if (tid == 0) extend_chain<W, BLOCK, NI, SEGS, GEN>(sh, r, md, m, batch_items);
+            __syncthreads();
+            if (!sh.chain_more) break;
+          }
         }
       }
       const uint32_t nseg = sh.nseg;
@@ -928,7 +1036,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
           Item<W> x;
-          gen_item<W, BLOCK, NI, true, GEN, HET>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+          gen_item<W, BLOCK, NI, true, GEN, HET, SEGS>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                        e_lds, md, m, x);
           if (x.active && x.clk > md.max_clock) {
             set_error(md.ctrl, kDevErrOverflow);
@@ -947,7 +1055,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
-          gen_item<W, BLOCK, NI, false, GEN, HET>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
+          gen_item<W, BLOCK, NI, false, GEN, HET, SEGS>(base + (uint32_t)n * BLOCK + tid, n_items, nseg, sh, r,
                                         e_lds, md, m, it[n]);
           it[n].active = act[n];
           fresh[n] = false;
@@ -1081,8 +1189,8 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
 // not in a slice (the round's block claims that state).  Inserts are agent-scope like a
 // block's boundary states; no state of a slice has a (pending, clock) pair that another
 // partition's states have.
-template <int W, int BLOCK, int NI, bool GEN>
-__device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLOCK, NI>& sh) {
+template <int W, int BLOCK, int NI, bool GEN, int SEGS>
+__device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLOCK, NI, SEGS>& sh) {
   Tally tl;
   const Layout& L = md.L;
   const int m = L.m;
@@ -1194,7 +1302,7 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
 
 template <int W, int BLOCK, int NI, bool GEN, bool HET>
 __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
-  __shared__ SuperShared<BLOCK, NI> sh;
+  __shared__ SuperShared<BLOCK, NI, HET ? kSegMaxChain : kSegMax> sh;
   const uint32_t tid = threadIdx.x;
   for (;;) {
     if (tid == 0) {
@@ -1403,8 +1511,60 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
 // the choice of step t drawn from splitmix64(seed ^ splitmix64(t)); successors are
 // ordered by configuration (SELECT) and by unit index (DISPATCH).  A lock-step ADVANCE
 // run has one successor per step; it is taken in one jump that counts its steps.
+
+// Units of unequal speed with no DISPATCH enabled until clock H (the first workgroup end
+// while work is pending, else the last): the ADVANCE steps up to H are one per distinct
+// operation end of the busy units in (clock, H].  The wavefront counts them a window at a
+// time: lane l takes the (l mod p)-th next end of unit l / p (p = 64 / m); the window
+// closes at the least last-slot end of any unit (no end of any unit below it is missing),
+// an end counts unless a unit of lower index ends at the same time, and the state moves
+// to the window's close.  Returns the steps; x is left at clock H.
+__device__ uint32_t jump_unequal(St& x, const CfgRec& r, int m, const uint8_t* speed,
+                                 uint32_t H) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t per = 64u / (uint32_t)m;
+  const uint32_t u = lane / per, k = lane - u * per;
+  uint32_t steps = 0;
+  while (x.clock < H) {
+    uint32_t v = 0xFFFFFFFFu;
+    if (u < (uint32_t)m && x.rem[u]) {
+      const uint32_t sp = speed[u];
+      const uint32_t e = sp * r.d - x.rem[u];
+      const uint32_t kk = ends_upto(r, e / sp) + k;
+      if (kk < r.b) {
+        const uint32_t tau = x.clock + sp * end_at(r, kk) - e;
+        if (tau <= H) v = tau;
+      }
+    }
+    uint32_t lim = (k + 1u == per) ? v : 0xFFFFFFFFu;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t y = __shfl_xor(lim, o);
+      lim = y < lim ? y : lim;
+    }
+    lim = lim < H ? lim : H;
+    bool first = v <= lim;
+    for (uint32_t j = 0; j < u && first; ++j) {
+      // does unit j (busy until clock + rem_j) end an operation at time v?
+      if (x.rem[j] == 0u || v > x.clock + x.rem[j]) continue;
+      const uint32_t sj = speed[j];
+      const uint32_t diff = v - x.clock + (sj * r.d - x.rem[j]);
+      if (diff % sj) continue;
+      const uint32_t q = diff / sj;
+      if (q && ends_upto(r, q) != ends_upto(r, q - 1u)) first = false;
+    }
+    steps += (uint32_t)__popcll(__ballot(first));
+    const uint32_t dt = lim - x.clock;
+#pragma unroll
+    for (int i = 0; i < kMaxCU; ++i) x.rem[i] = x.rem[i] > dt ? x.rem[i] - dt : 0u;
+    x.clock = lim;
+  }
+  return steps;
+}
+
 __global__ void k_simulate(QueryArgs a, unsigned long long seed) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // every lane of the wavefront follows the same run; jump_unequal splits its windows
+  if (blockIdx.x != 0 || threadIdx.x >= 64) return;
   const int m = a.L.m;
   const uint8_t* speed = a.L.speed;
   unsigned long long step = 0;
@@ -1451,12 +1611,20 @@ __global__ void k_simulate(QueryArgs a, unsigned long long seed) {
       x.clock += brem;
       for (int u = 0; u < m; ++u) x.rem[u] = 0u;
     } else {
-      advance_once(x, r, m, speed);
-      ++step;
+      // no DISPATCH before the first workgroup end (work pending) or the last
+      uint32_t H = x.pending ? 0xFFFFFFFFu : 0u;
+      for (int u = 0; u < m; ++u) {
+        if (!x.rem[u]) continue;
+        const uint32_t t = x.clock + x.rem[u];
+        H = x.pending ? (t < H ? t : H) : (t > H ? t : H);
+      }
+      step += jump_unequal(x, r, m, speed, H);
     }
   }
-  a.ctrl->sim_t = x.clock;
-  a.ctrl->sim_cfg = c;
+  if (threadIdx.x == 0) {
+    a.ctrl->sim_t = x.clock;
+    a.ctrl->sim_cfg = c;
+  }
 }
 
 // ---- swarm search (Sec. 5) -----------------------------------------------------------

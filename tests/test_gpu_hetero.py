@@ -145,3 +145,41 @@ def test_hetero_batch_and_served(mc):
         else:
             assert res["violated"] == int(r["violated"])
     e.close()
+
+
+def _chain_models():
+    w = workloads
+    return [w.with_speeds(w.reduction_model(G, m, w.pow2_range(0, 3), w.pow2_range(0, 1),
+                                            *w.latencies(2)), sp)
+            for G, m, sp in ((128, 3, [1, 2, 3]), (256, 2, [1, 3]), (64, 4, [1, 1, 2, 5]))]
+
+
+@pytest.mark.parametrize("block,batch_items", [(256, 0), (512, 0), (1024, 0), (256, 64),
+                                               (512, 600)])
+def test_hetero_chains_across_dispatches(mc, block, batch_items):
+    """Workgroups of up to 257 operations: a batch lists chain after chain, through the
+    determined dispatches between them and past chains cut by their candidate window,
+    until a choice among units, a terminal, the threshold or the batch's room ends it."""
+    for model in _chain_models():
+        _say(f"chains block={block} batch_items={batch_items} {workloads.describe(model)}")
+        r = oracle.explore(model)
+        g = mc.Model(model, block=block, batch_items=batch_items)
+        check_min_time(g, model, r, ENGINES["superstep"])
+        for T in sorted({r["t_min"] - 1, r["t_min"], max(r["tc"]) // 2}):
+            check_threshold(mc, g, model, T)
+        assert g.mc_min_time_bb(0) == (r["t_min"], r["argmin"])
+        oracle.check_trace(model, g.mc_trace(), target_clock=r["t_min"], cfgs=r["argmin"])
+        g.close()
+
+
+def test_hetero_simulate_full_size(mc):
+    """The seeded run on the full-size workloads, whose stretches between dispatches the
+    wavefront crosses a window of operation ends at a time: the same terminal (clock and
+    configuration) as the oracle's one-step-at-a-time walk, hence the same step count
+    at every draw."""
+    for model in list(workloads.hetero_workloads().values()) + _chain_models():
+        g = mc.Model(model)
+        for seed in range(1, 9):
+            assert g.mc_simulate(seed) == oracle.simulate(model, seed), (
+                workloads.describe(model), seed)
+        g.close()
