@@ -207,7 +207,9 @@ def model_leg(mc, torch, models: dict, reps: int, cpu: bool):
                "t_min": steps[0]["t_min"], "argmin": steps[0]["argmin"],
                "ms_per_step": 1e3 * elapsed / reps, "states_per_s": states / elapsed,
                "min_time_engine_ms": eng_s * 1e3, "roofline_frac": achieved / HBM_PEAK_GBS,
-               "partitions": steps[0]["parts"]}
+               "partitions": steps[0]["parts"],
+               "step_breakdown_ms": {k: sum(s["breakdown_ms"][k] for s in steps) / reps
+                                     for k in steps[0]["breakdown_ms"]}}
         for k in ("S", "NP", "G", "M", "N", "K", "speed"):
             if k in model:
                 rec[k] = model[k]

@@ -302,6 +302,7 @@ constexpr int kMaxLeaves = 72;  // C(8, 4) = 70 leaves at most
 constexpr int kChainCand = 8 * 64;       // chain candidates: 512 / m ends to go per unit
 constexpr int kChainTimes = 1024;        // the chain's times, listed in E from here
 static_assert(kChainTimes >= kChainCand + 1 && kChainTimes + kChainCand <= kEMax, "E use");
+static_assert(kSegMax * 256 >= kChainCand + 1, "chain prefix sums fit in the closure slots");
 
 struct SegDesc {
   unsigned long long fkey[4];  // frontier state of the segment
@@ -471,9 +472,9 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
 // DISPATCH enabled) the clock visits the union of the busy units' operation ends, up to
 // the first workgroup end while work is pending (then a DISPATCH follows), or to the
 // terminal.  Every lane writes one candidate end (unit u, its k-th end to go, k < p =
-// 512 / m) into the LDS table E (unused on such models: no run is in lock step), the
-// workgroup sorts the candidates (bitonic), and one wavefront keeps the distinct times
-// up to the smallest p-th candidate of any unit (below it no end of any unit is missing), in
+// 512 / m) into the LDS table E (unused on such models: no run is in lock step), and the
+// workgroup merges the units' lists, keeping the distinct times up to the smallest p-th
+// candidate of any unit (below it no end of any unit is missing), in
 // order, as the chain's states, from E[kChainTimes + idx0] (the batch's chains are
 // listed one after another).  Their number is the segment's length.
 template <int W, int BLOCK, int NI, int SEGS>
@@ -512,45 +513,90 @@ __device__ __noinline__ void build_chain(SuperShared<BLOCK, NI, SEGS>& sh, const
     ct[i] = v;
   }
   __syncthreads();
-  for (uint32_t k = 2; k <= (uint32_t)kChainCand; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = tid; i < (uint32_t)kChainCand; i += BLOCK) {
-        const uint32_t ixj = i ^ j;
-        if (ixj > i) {
-          const uint32_t a = ct[i], b = ct[ixj];
-          if ((a > b) == ((i & k) == 0u)) {
-            ct[i] = b;
-            ct[ixj] = a;
+  // Each unit's candidates ascend with k (then the unset ones), so a binary search in
+  // unit j's list gives how many of its ends come before v and whether it ends at v.
+  // An end counts once, on the lowest unit that has it ("first"); the chain's time of
+  // rank q is the first end with q distinct ends before it: the first ends before it
+  // are counted per unit from an exclusive prefix sum of the first flags.
+  const uint32_t lim = ct[kChainCand];
+  uint32_t* cg = &sh.mslot[0][0];  // free while chains are listed: closures fill it later
+  constexpr int kPerThr = (kChainCand + BLOCK - 1) / BLOCK;
+  uint32_t pos[kPerThr][kMaxCU];
+  uint32_t val[kPerThr];
+  bool fst[kPerThr];
+#pragma unroll
+  for (int q = 0; q < kPerThr; ++q) {
+    const uint32_t i = tid + (uint32_t)q * BLOCK;
+    fst[q] = false;
+    val[q] = 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < kMaxCU; ++j) pos[q][j] = 0u;
+    if (i < (uint32_t)kChainCand) {
+      const uint32_t u = i / per, k = i - u * per, v = ct[i];
+      bool ok = u < (uint32_t)m && v <= lim && v != 0xFFFFFFFFu;
+      if (ok) {
+#pragma unroll
+        for (int j = 0; j < kMaxCU; ++j) {
+          if (j >= m) continue;
+          if ((uint32_t)j == u) {
+            pos[q][j] = k;
+            continue;
           }
+          const uint32_t* lj = ct + (uint32_t)j * per;
+          uint32_t lo = 0, n = per;  // lower bound: the first entry >= v
+          while (n) {
+            const uint32_t half = n >> 1;
+            if (lj[lo + half] < v) {
+              lo += half + 1u;
+              n -= half + 1u;
+            } else {
+              n = half;
+            }
+          }
+          pos[q][j] = lo;
+          if ((uint32_t)j < u && lo < per && lj[lo] == v) ok = false;
         }
       }
-      __syncthreads();
+      fst[q] = ok;
+      val[q] = v;
+      cg[i] = ok ? 1u : 0u;
     }
   }
-  if (tid < 64) {
-    const uint32_t lim = ct[kChainCand];
+  __syncthreads();
+  if (tid < 64) {  // exclusive prefix sum of the flags; cg[kChainCand] = their total
     constexpr int kPer = kChainCand / 64;
-    uint32_t cnt = 0;
+    uint32_t loc[kPer], sum = 0;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const uint32_t i = tid * kPer + q, v = ct[i];
-      cnt += (v <= lim && v != 0xFFFFFFFFu && (i == 0u || v != ct[i - 1])) ? 1u : 0u;
+      loc[q] = cg[tid * kPer + q];
+      sum += loc[q];
     }
-    uint32_t incl = cnt;
+    uint32_t incl = sum;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off);
       if ((int)tid >= off) incl += y;
     }
-    uint32_t j = kChainTimes + sg.idx0 + incl - cnt;
+    uint32_t run = incl - sum;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const uint32_t i = tid * kPer + q, v = ct[i];
-      if (v <= lim && v != 0xFFFFFFFFu && (i == 0u || v != ct[i - 1])) ct[j++] = v;
+      cg[tid * kPer + q] = run;
+      run += loc[q];
     }
     if (tid == 63) {
+      cg[kChainCand] = incl;
       sg.len = incl;
       sh.total = sg.start + incl;
     }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPerThr; ++q) {
+    if (!fst[q]) continue;
+    uint32_t rank = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxCU; ++j)
+      if (j < m) rank += cg[(uint32_t)j * per + pos[q][j]] - cg[(uint32_t)j * per];
+    ct[kChainTimes + sg.idx0 + rank] = val[q];
   }
 }
 

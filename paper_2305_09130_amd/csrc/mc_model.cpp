@@ -13,7 +13,9 @@
 #include "mc_model.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <thread>
 
 namespace mc {
 
@@ -250,6 +252,9 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   uint64_t total = 1, depth = 0, fb = d->n_cfg;
   uint64_t widest_sum = 0;
   uint32_t max_clock = 0, max_n = 0, max_d = 0;
+  // per configuration: latest terminal clock, state count (bound), longest path
+  std::vector<uint64_t> c_tc(d->n_cfg), c_depth(d->n_cfg);
+  uint64_t walk_work = 0;  // operation ends the walks of units of unequal speed visit
   for (uint32_t c = 0; c < d->n_cfg; ++c) {
     WaveSpec ws;
     int rc = phases(d, &h->params[4ull * c], &ws, err);
@@ -285,17 +290,14 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
     r.n = (uint32_t)n;
     r.d = (uint32_t)t;
     r.b = (uint32_t)b;
-    uint64_t cs, cdepth;
+    uint64_t cs = 0, cdepth = 0;
     if (h->hetero) {
       h->general = true;
       uint32_t smax = 1;
       for (uint32_t i = 0; i < m; ++i) smax = std::max(smax, h->speed[i]);
       if ((uint64_t)smax * t >= (1ull << 31)) return fail(err, "workgroup duration exceeds 2^31");
       if (rounds * b * m > (1ull << 26)) return fail(err, "model too long for units of unequal speed");
-      const ChainCount cc = walk_unequal(r, h->speed, m, ~0ull);
-      tc = cc.max_clock;  // the latest terminal clock of this configuration
-      cs = cc.states;
-      cdepth = 1 + cc.depth;
+      walk_work += rounds * b * m;  // walked below, every configuration on its own
     } else {
       const uint64_t q = n / m, p = n % m;
       cs = 1 + q * (((1ull << m) - 1) + b);
@@ -306,12 +308,9 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
       }
       cdepth = 1 + n + rounds * b;
     }
-    if (tc >= 0xFFFFFFFFull) return fail(err, "terminal clock exceeds 32 bits");
-    r.tc = (uint32_t)tc;
+    c_tc[c] = tc;
     h->cfg_states[c] = cs;
-    total += cs;
-    depth = std::max<uint64_t>(depth, cdepth);
-    max_clock = std::max<uint32_t>(max_clock, (uint32_t)tc);
+    c_depth[c] = cdepth;
     max_n = std::max<uint32_t>(max_n, (uint32_t)n);
     max_d = std::max<uint32_t>(max_d, (uint32_t)t);
     // widest level of this subgraph: dispatch levels C(m, j), partial-round runs C(m, p)
@@ -319,6 +318,35 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
     const uint32_t jmax = (uint32_t)std::min<uint64_t>(n, m);
     for (uint32_t j = 0; j <= jmax; ++j) w = std::max<uint64_t>(w, binom(m, j));
     widest_sum += w;
+  }
+  if (h->hetero) {
+    // the walks are independent: long ones share the host's cores
+    const auto walk = [&](uint32_t c) {
+      const ChainCount cc = walk_unequal(h->cfgs[c], h->speed, m, ~0ull);
+      c_tc[c] = cc.max_clock;  // the latest terminal clock of this configuration
+      h->cfg_states[c] = cc.states;
+      c_depth[c] = 1 + cc.depth;
+    };
+    const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const uint32_t nt = walk_work < (1ull << 17) ? 1u : std::min<uint32_t>({hw, 16u, d->n_cfg});
+    std::atomic<uint32_t> next{0};
+    const auto worker = [&] {
+      for (uint32_t c; (c = next.fetch_add(1)) < d->n_cfg;) walk(c);
+    };
+    std::vector<std::thread> pool;
+    try {
+      for (uint32_t i = 1; i < nt; ++i) pool.emplace_back(worker);
+    } catch (...) {  // no more threads: the ones started and this one share the rest
+    }
+    worker();
+    for (auto& th : pool) th.join();
+  }
+  for (uint32_t c = 0; c < d->n_cfg; ++c) {
+    if (c_tc[c] >= 0xFFFFFFFFull) return fail(err, "terminal clock exceeds 32 bits");
+    h->cfgs[c].tc = (uint32_t)c_tc[c];
+    total += h->cfg_states[c];
+    depth = std::max<uint64_t>(depth, c_depth[c]);
+    max_clock = std::max<uint32_t>(max_clock, (uint32_t)c_tc[c]);
   }
   fb = std::max<uint64_t>(fb, widest_sum);
   h->states = total;
