@@ -78,6 +78,10 @@ int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) 
 }
 
 constexpr uint32_t kWideParts = 256;
+// With thousands of partitions in flight a lane inserts one key per round trip: on
+// matmul128_vw_cu8 (3,828 partitions) two keys per lane took 8.4 ms against 6.5 ms with
+// one; on matmul64_cu4 (376 partitions) two keys per lane stay ahead (0.48 vs 0.50 ms).
+constexpr uint32_t kManyParts = 2048;
 
 mc_opts default_opts(const mc_opts* o) {
   mc_opts r;
@@ -104,14 +108,35 @@ std::vector<Part> model_parts(const ModelHost& mh, const mc_opts& o) {
   return parts;
 }
 
+// fields: cfg, pending, clock, then the time left on every unit (packed as a busy mask
+// and one shared time when the layout says so)
 void host_encode(const Layout& L, const uint32_t* fields, uint64_t* words) {
   for (int j = 0; j < 4; ++j) words[j] = 0;
-  for (int f = 0; f < 3 + L.m; ++f) words[L.word[f]] |= (uint64_t)fields[f] << L.shift[f];
+  uint32_t packed[kFields];
+  for (int f = 0; f < 3 + L.m; ++f) packed[f] = fields[f];
+  int nf = 3 + L.m;
+  if (L.shared_rem) {
+    uint32_t mask = 0, rem = 0;
+    for (int u = 0; u < L.m; ++u)
+      if (fields[kFRem + u]) {
+        mask |= 1u << u;
+        rem = fields[kFRem + u];
+      }
+    packed[kFRem] = mask;
+    packed[kFRem + 1] = rem;
+    nf = 5;
+  }
+  for (int f = 0; f < nf; ++f) words[L.word[f]] |= (uint64_t)packed[f] << L.shift[f];
 }
 
 void host_decode(const Layout& L, const uint64_t* words, uint32_t* fields) {
-  for (int f = 0; f < 3 + L.m; ++f)
+  const int nf = L.shared_rem ? 5 : 3 + L.m;
+  for (int f = 0; f < nf; ++f)
     fields[f] = (uint32_t)((words[L.word[f]] >> L.shift[f]) & ((1ull << L.width[f]) - 1ull));
+  if (L.shared_rem) {
+    const uint32_t mask = fields[kFRem], rem = fields[kFRem + 1];
+    for (int u = 0; u < L.m; ++u) fields[kFRem + u] = ((mask >> u) & 1u) ? rem : 0u;
+  }
 }
 
 
@@ -282,7 +307,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     pq.models = h->dmd;
     pq.parts = h->parts;
     pq.n_parts = h->n_parts;
-    const uint32_t li = lane_items_for(h->opts.lane_items, h->mh.W);
+    const uint32_t li = h->opts.lane_items || h->n_parts < kManyParts
+                            ? lane_items_for(h->opts.lane_items, h->mh.W)
+                            : 1u;
     pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
     pq.head = h->head;
     pq.slice = 0u;

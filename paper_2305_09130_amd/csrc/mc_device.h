@@ -111,8 +111,14 @@ __device__ __forceinline__ St decode(const Key<W>& k, const Layout& L) {
   s.cfg = key_get<W>(k, L, kFCfg);
   s.pending = key_get<W>(k, L, kFPending);
   s.clock = key_get<W>(k, L, kFClock);
+  if (L.shared_rem) {
+    const uint32_t mask = key_get<W>(k, L, kFRem), rem = key_get<W>(k, L, kFRem + 1);
 #pragma unroll
-  for (int i = 0; i < kMaxCU; ++i) s.rem[i] = (i < L.m) ? key_get<W>(k, L, kFRem + i) : 0u;
+    for (int i = 0; i < kMaxCU; ++i) s.rem[i] = ((mask >> i) & 1u) ? rem : 0u;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kMaxCU; ++i) s.rem[i] = (i < L.m) ? key_get<W>(k, L, kFRem + i) : 0u;
+  }
   return s;
 }
 
@@ -124,9 +130,21 @@ __device__ __forceinline__ Key<W> encode(const St& s, const Layout& L) {
   key_put<W>(k, L, kFCfg, s.cfg);
   key_put<W>(k, L, kFPending, s.pending);
   key_put<W>(k, L, kFClock, s.clock);
+  if (L.shared_rem) {  // every busy unit has the same time left
+    uint32_t mask = 0, rem = 0;
 #pragma unroll
-  for (int i = 0; i < kMaxCU; ++i)
-    if (i < L.m) key_put<W>(k, L, kFRem + i, s.rem[i]);
+    for (int i = 0; i < kMaxCU; ++i)
+      if (i < L.m && s.rem[i]) {
+        mask |= 1u << i;
+        rem = s.rem[i];
+      }
+    key_put<W>(k, L, kFRem, mask);
+    key_put<W>(k, L, kFRem + 1, rem);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kMaxCU; ++i)
+      if (i < L.m) key_put<W>(k, L, kFRem + i, s.rem[i]);
+  }
   return k;
 }
 

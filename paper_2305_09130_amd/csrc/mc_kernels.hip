@@ -393,17 +393,44 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
     const uint32_t ns = (uint32_t)__popc(it.rmask);
     if (ns > sg.kstar) it.active = false;
     if (KEY) {
+      if (L.shared_rem && sg.freem == (1u << m) - 1u) {
+        // from an all-idle state (every dispatch on equal units): the dispatched units
+        // are the mask's bits and all have time d
 #pragma unroll
-      for (int w = 0; w < W; ++w) it.key[w] = sg.fkey[w];
-      uint32_t t = 0;
+        for (int w = 0; w < W; ++w) it.key[w] = sg.fkey[w];
+        field_add<W>(it.key, L, kFRem, it.rmask);
+        field_add<W>(it.key, L, kFRem + 1, r.d);
+        field_add<W>(it.key, L, kFPending, (unsigned long long)(-(long long)ns));
+      } else if (L.shared_rem) {  // the dispatched units join the busy mask, all with time d
+        Key<W> fk;
 #pragma unroll
-      for (int u = 0; u < kMaxCU; ++u) {
-        if ((sg.freem >> u) & 1u) {
-          if ((it.rmask >> t) & 1u) field_add<W>(it.key, L, kFRem + u, unit_dur<GEN>(r, L.speed, u));
-          ++t;
+        for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
+        St y = decode<W>(fk, L);
+        uint32_t t = 0;
+#pragma unroll
+        for (int u = 0; u < kMaxCU; ++u) {
+          if ((sg.freem >> u) & 1u) {
+            if ((it.rmask >> t) & 1u) y.rem[u] = r.d;
+            ++t;
+          }
         }
+        y.pending -= ns;
+        const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+        for (int w = 0; w < W; ++w) it.key[w] = yk.w[w];
+      } else {
+#pragma unroll
+        for (int w = 0; w < W; ++w) it.key[w] = sg.fkey[w];
+        uint32_t t = 0;
+#pragma unroll
+        for (int u = 0; u < kMaxCU; ++u) {
+          if ((sg.freem >> u) & 1u) {
+            if ((it.rmask >> t) & 1u) field_add<W>(it.key, L, kFRem + u, unit_dur<GEN>(r, L.speed, u));
+            ++t;
+          }
+        }
+        field_add<W>(it.key, L, kFPending, (unsigned long long)(-(long long)ns));
       }
-      field_add<W>(it.key, L, kFPending, (unsigned long long)(-(long long)ns));
     }
     it.dep = sg.fdep + ns;
     return;
@@ -421,20 +448,30 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
       unsigned long long Mv[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) Mv[w] = sg.M[w];
+      // the run's busy units: the leaf's dispatched units, or the frontier's busy ones
+      uint32_t um = sg.kstar ? sg.freem : (((1u << m) - 1u) & ~sg.freem);
       if (sg.kstar && sg.nleaf > 1u) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) Mv[w] = 0ull;
+        um = 0u;
         uint32_t t = 0;
 #pragma unroll
         for (int u = 0; u < kMaxCU; ++u) {
           if ((sg.freem >> u) & 1u) {
-            if ((it.rmask >> t) & 1u) field_add<W>(Mv, L, kFRem + u, 1ull);
+            if ((it.rmask >> t) & 1u) um |= 1u << u;
             ++t;
           }
+        }
+        if (!L.shared_rem) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) Mv[w] = 0ull;
+#pragma unroll
+          for (int u = 0; u < kMaxCU; ++u)
+            if ((um >> u) & 1u) field_add<W>(Mv, L, kFRem + u, 1ull);
         }
       }
 #pragma unroll
       for (int w = 0; w < W; ++w) it.key[w] = sg.base[w] + rem * Mv[w];
+      // shared time left: the busy mask is set while the units are busy (rem > 0)
+      if (L.shared_rem && rem) field_add<W>(it.key, L, kFRem, um);
       field_add<W>(it.key, L, kFClock, it.clk);
     }
     it.term = sg.pend == 0u && e == r.d;
@@ -868,9 +905,13 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
 #pragma unroll
             for (int w = 0; w < W; ++w) Mv[w] = 0ull;
             const uint32_t busy_run = kstar ? freem : busy;  // single leaf: all free units start
+            if (L.shared_rem) {
+              field_add<W>(Mv, L, kFRem + 1, 1ull);  // one time left for every busy unit
+            } else {
 #pragma unroll
-            for (int u = 0; u < kMaxCU; ++u)
-              if (u < m && ((busy_run >> u) & 1u)) field_add<W>(Mv, L, kFRem + u, 1ull);
+              for (int u = 0; u < kMaxCU; ++u)
+                if (u < m && ((busy_run >> u) & 1u)) field_add<W>(Mv, L, kFRem + u, 1ull);
+            }
 #pragma unroll
             for (int w = 0; w < W; ++w) {
               sg.base[w] = bk.w[w];

@@ -361,15 +361,24 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   widths[kFCfg] = std::max<uint32_t>(1, bit_length((uint64_t)d->n_cfg + 1));
   widths[kFPending] = std::max<uint32_t>(1, bit_length(max_n));
   widths[kFClock] = std::max<uint32_t>(1, bit_length(max_clock));
-  for (uint32_t i = 0; i < m; ++i)
-    widths[kFRem + i] = std::max<uint32_t>(1, bit_length((uint64_t)h->speed[i] * max_d));
+  // equal units start their workgroups together (every dispatch is from an all-idle
+  // state), so every busy unit has the same time left: a mask and one field hold them
+  const bool shared = !h->hetero;
+  if (shared) {
+    widths[kFRem] = m;
+    widths[kFRem + 1] = std::max<uint32_t>(1, bit_length(max_d));
+  } else {
+    for (uint32_t i = 0; i < m; ++i)
+      widths[kFRem + i] = std::max<uint32_t>(1, bit_length((uint64_t)h->speed[i] * max_d));
+  }
+  const uint32_t nfields = shared ? 5u : 3u + m;
   Layout L;
   std::memset(&L, 0, sizeof(L));
   // every word after the first keeps its top bit clear, so that no valid key has a word
   // equal to the all-ones of a cleared slot (word 0 cannot be: its configuration field
   // is never all-ones); a reader of a wide key can then tell a word not yet written
   uint32_t word = 0, off = 0, used = 0;
-  for (uint32_t f = 0; f < 3 + m; ++f) {
+  for (uint32_t f = 0; f < nfields; ++f) {
     if (off + widths[f] > (word == 0 ? 64u : 63u)) {
       ++word;
       off = 0;
@@ -385,6 +394,7 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   L.W = (uint8_t)(words == 1 ? 1 : words == 2 ? 2 : 4);
   L.m = (uint8_t)m;
   L.hetero = h->hetero ? 1 : 0;
+  L.shared_rem = shared ? 1 : 0;
   for (int i = 0; i < kMaxCU; ++i) L.speed[i] = (uint8_t)h->speed[i];
   L.used_bits = (uint8_t)used;
   h->layout = L;

@@ -14,7 +14,9 @@
 namespace mc {
 
 constexpr int kMaxCU = (int)MC_MAX_CU;
-constexpr int kFields = 3 + kMaxCU;  // cfg, pending, clock, rem_0..rem_{m-1}
+// key fields: cfg, pending, clock, rem_0..rem_{m-1}; with Layout::shared_rem the
+// fields after the clock are the busy-unit mask and the one remaining time they share
+constexpr int kFields = 3 + kMaxCU;
 constexpr int kFCfg = 0, kFPending = 1, kFClock = 2, kFRem = 3;
 constexpr int kMaxPhases = 4;
 
@@ -34,7 +36,7 @@ struct Layout {
   uint8_t W;  // key words: 1, 2 or 4
   uint8_t used_bits;
   uint8_t hetero;            // units of unequal speed
-  uint8_t pad;
+  uint8_t shared_rem;        // equal units: busy mask + one remaining time (kFRem, kFRem + 1)
   uint8_t speed[kMaxCU];     // cycles per cycle of work of each unit (1 = full speed)
 };
 

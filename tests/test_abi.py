@@ -37,8 +37,9 @@ def test_describe_matches_closed_form(mc, name):
     s = cf.summary(model)
     assert d["states"] == s["reachable"]
     assert d["max_depth"] + 1 == s["levels"]
-    assert d["key_words"] == {"reduction_g256_cu2": 1, "matmul64_cu4": 2,
-                              "matmul128_vw_cu8": 4}[name]
+    # equal units: cfg, pending, clock, busy mask and one shared time left
+    assert d["key_words"] == {"reduction_g256_cu2": 1, "matmul64_cu4": 1,
+                              "matmul128_vw_cu8": 2}[name]
 
 
 def test_describe_tiny_sweep(mc):
@@ -52,8 +53,8 @@ def test_describe_tiny_sweep(mc):
 def test_workspace_sizes(mc):
     m = workloads.matmul_128_vw()
     n = mc.mc_workspace_bytes(m)
-    # 58M states at load factor <= 0.5 in 64-byte slots: 2^27 slots = 8 GiB
-    assert 8 * 2**30 <= n < 9 * 2**30
+    # 58M states at load factor <= 0.5 in 32-byte slots (two key words): 2^27 slots = 4 GiB
+    assert 4 * 2**30 <= n < 4.5 * 2**30
     small = mc.mc_workspace_bytes(m, mc.make_opts(load_factor=0.25))
     assert small > n
 
@@ -130,8 +131,8 @@ def test_unit_kinds_describe(mc):
         s = cf.summary(model, with_E=False)
         assert d["states"] == s["reachable"], workloads.describe(model)
         assert d["max_depth"] + 1 == s["levels"]
-    want = {"abstract_s1024_np4_cu1": (1868340, 1), "abstract_s1024_np4_cu4": (2266564, 2),
-            "minimum_s1024_np4_cu4": (1052986, 2)}
+    want = {"abstract_s1024_np4_cu1": (1868340, 1), "abstract_s1024_np4_cu4": (2266564, 1),
+            "minimum_s1024_np4_cu4": (1052986, 1)}
     for name, f in workloads.UNIT_WORKLOADS.items():
         d = mc.mc_describe(f())
         assert (d["states"], d["key_words"]) == want[name]
