@@ -97,7 +97,7 @@ mc_opts default_opts(const mc_opts* o) {
 std::vector<Part> model_parts(const ModelHost& mh, const mc_opts& o) {
   const uint64_t target = o.part_states == 0xFFFFFFFFu ? 0u
                           : o.part_states              ? o.part_states
-                                                       : auto_part_states(mh.states);
+                                                       : auto_part_states(mh.states, mh.m);
   std::vector<PartPlan> plan;
   plan_parts(mh, target, &plan);
   std::stable_sort(plan.begin(), plan.end(),

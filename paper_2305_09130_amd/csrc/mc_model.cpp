@@ -490,10 +490,14 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
   }
 }
 
-uint64_t auto_part_states(uint64_t states) {
-  // about 256 partitions for small models (down to blocks of kMinBlockRounds rounds),
-  // blocks of at most 2^14 states for large ones
-  return std::min<uint64_t>(1ull << 14, std::max<uint64_t>(1, states / 256));
+uint64_t auto_part_states(uint64_t states, uint32_t m) {
+  // about 640 partitions for small models (256 on one unit), down to blocks of
+  // kMinBlockRounds rounds; blocks of at most 2^14 states for large ones.  With one-word
+  // keys more partitions in flight pay: matmul64_cu4 0.48 -> 0.45 ms (376 -> 692 blocks),
+  // abstract_s1024_np4_cu4 0.31 -> 0.26, minimum_s1024_np4_cu4 0.135 -> 0.125; on one
+  // unit (abstract_s1024_np4_cu1) 0.27 -> 0.31 ms, so it keeps 256.
+  const uint64_t parts = m == 1u ? 256u : 640u;
+  return std::min<uint64_t>(1ull << 14, std::max<uint64_t>(1, states / parts));
 }
 
 // operation ends of one workgroup at or before time x

@@ -117,8 +117,9 @@ struct PartPlan {
 // of each (every state of a slice has a clock no other partition's states have).
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
 
-// Default target states per partition for a launch exploring `states` states in total.
-uint64_t auto_part_states(uint64_t states);
+// Default target states per partition for a launch exploring `states` states in total
+// on models of m units.
+uint64_t auto_part_states(uint64_t states, uint32_t m = 2u);
 
 // An upper bound (exact for every configuration whose last round is not partial) on the
 // number of states with clock <= T, root included: what a check(T) inserts.  Sizes its
