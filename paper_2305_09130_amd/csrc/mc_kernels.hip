@@ -299,8 +299,8 @@ constexpr uint32_t kNoItem = 0xFFFFFFFFu;
 constexpr int kEMax = 4096;  // operation ends kept in LDS
 constexpr int kFCap = 256;   // frontier states per super-step level (LDS)
 constexpr int kMaxLeaves = 72;  // C(8, 4) = 70 leaves at most
-constexpr int kChainCand = 8 * 64;       // chain candidates: 512 / m ends to go per unit
-constexpr int kChainTimes = 1024;        // the chain's times, listed in E from here
+constexpr int kChainCand = 1024;         // chain candidates: 1024 / m ends to go per unit
+constexpr int kChainTimes = 1280;        // the batch's chain times, listed in E from here
 static_assert(kChainTimes >= kChainCand + 1 && kChainTimes + kChainCand <= kEMax, "E use");
 static_assert(kSegMax * 256 >= kChainCand + 1, "chain prefix sums fit in the closure slots");
 
@@ -509,7 +509,7 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
 // DISPATCH enabled) the clock visits the union of the busy units' operation ends, up to
 // the first workgroup end while work is pending (then a DISPATCH follows), or to the
 // terminal.  Every lane writes one candidate end (unit u, its k-th end to go, k < p =
-// 512 / m) into the LDS table E (unused on such models: no run is in lock step), and the
+// 1024 / m) into the LDS table E (unused on such models: no run is in lock step), and the
 // workgroup merges the units' lists, keeping the distinct times up to the smallest p-th
 // candidate of any unit (below it no end of any unit is missing), in
 // order, as the chain's states, from E[kChainTimes + idx0] (the batch's chains are
