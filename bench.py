@@ -398,7 +398,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    model = workloads.WORKLOADS[args.workload]()
+    if args.workload in workloads.WORKLOADS:
+        model = workloads.WORKLOADS[args.workload]()
+    elif args.workload in workloads.UNIT_WORKLOADS:
+        model = workloads.UNIT_WORKLOADS[args.workload]()
+    else:
+        model = workloads.hetero_workloads()[args.workload]
     nbytes = max(mc.mc_workspace_bytes(model, mc.make_opts(engine=e, block=args.block,
                                                           load_factor=args.load_factor))
                  for e in (0, 1))
@@ -473,13 +478,13 @@ def main():
 
     cfg = {"workload": args.workload, "kind": model["kind"], "cu": model["m"],
            "configurations": len(model["params"]),
-           "Lg": model["Lg"], "Ll": model["Ll"], "Lc": model["Lc"], "Lb": model["Lb"],
+           "Lg": model["Lg"], "Ll": model["Ll"], "Lc": model.get("Lc", 1), "Lb": model.get("Lb", 0),
            "states_per_step": steps[0]["states"], "reachable": steps[0]["min_states"],
            "t_min": steps[0]["t_min"], "argmin": steps[0]["argmin"],
            "trace_len": steps[0]["trace_len"], "block": args.block,
            "load_factor": args.load_factor or 0.5,
            "step": "load + min_time + trace + check(T_min-1)"}
-    for k in ("G", "M", "N", "K"):
+    for k in ("G", "M", "N", "K", "S", "NP", "speed"):
         if k in model:
             cfg[k] = model[k]
     out = {
