@@ -24,7 +24,47 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 LINE_BYTES = 64          # HBM access granule assumed per random visited-set touch
-ALGO_BYTES_PER_STATE = 2 * LINE_BYTES   # one slot line read for the claim, one written
+
+
+def graph_edges(mc, model) -> int | None:
+    """Edges of the model's reachable state graph (root included), from its round
+    structure, for models whose units all work alike: every configuration runs
+    floor(n/m) full rounds (a closure over all 2^m unit subsets, m*2^(m-1) dispatch
+    edges, then b ADVANCE edges) and, when n mod m = p > 0, one partial round (subsets
+    of at most p units, then one b-step run from each of its C(m, p) leaves).  None for
+    units of unequal speed, which have no such structure."""
+    from math import comb
+    if model.get("speed") is not None and len(set(model["speed"])) > 1:
+        return None
+    m = model["m"]
+    edges = len(model["params"])  # SELECT
+    for c in range(len(model["params"])):
+        e = mc.mc_config_ends(model, c)
+        n, b = e["n"], e["b"]
+        q, p = divmod(n, m)
+        edges += q * (m * (1 << (m - 1)) + b)
+        if p:
+            edges += sum(j * comb(m, j) for j in range(1, p + 1)) + comb(m, p) * b
+    return edges
+
+
+def bytes_per_state(key_bytes: int, r_dup: float) -> float:
+    """Algorithmic HBM bytes per new state of a breadth-first exploration with an
+    open-addressing visited set: one random line read-modify-write for the claim (key
+    and parent in one line), the frontier write and read of the key, and one random
+    line read per duplicate edge: 2L + 2S + r_dup * L."""
+    return 2 * LINE_BYTES + 2 * key_bytes + r_dup * LINE_BYTES
+
+
+def algo_bytes_per_state(mc, model, step) -> float:
+    """bytes_per_state for the model's key width, with r_dup = duplicate edges of the
+    state graph per reachable state (graph_edges), or, on units of unequal speed, the
+    duplicate inserts the run counted."""
+    key_bytes = 8 * mc.mc_describe(model)["key_words"]
+    n = step["min_states"]
+    edges = graph_edges(mc, model)
+    dup = edges - (n - 1) if edges is not None else step["min_dups"]
+    return bytes_per_state(key_bytes, dup / n)
 
 
 def _progress(msg: str) -> None:
@@ -68,6 +108,7 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
     t4 = time.perf_counter()
     return {"t_min": t_min, "argmin": argmin, "trace_len": len(trace), "minimal": holds,
             "states": st_min["states"] + st_chk["states"], "min_states": st_min["states"],
+            "min_dups": st_min["dups"],
             "engine_ns": st_min["engine_ns"] + st_chk["engine_ns"],
             "engine_ns_min": st_min["engine_ns"], "seconds": t4 - t0, "levels": st_min["levels"],
             "parts": st_min["parts"],
@@ -79,21 +120,48 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
                              "check_clear": st_chk["clear_ns"] / 1e6}}
 
 
-def cpu_baseline(model, t_min, budget_s: float = 30.0):
-    """The oracle as it stands, single-threaded, on the same query (bounded)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(model, t_min=None, sample_every: int = 1):
+    """The oracle as it stands, single-threaded and pinned to one host core (the
+    process's affinity is narrowed for the call and restored), on the same query step:
+    min_time then check(T_min - 1).  With sample_every = k only every k-th
+    configuration is explored (a bounded sample of the same workload); t_min is then
+    the sample's own.  Exploration time is measured inside the oracle."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    r = oracle.explore(model, trace=True)
-    c = oracle.explore(model, T=t_min - 1, trace=False)
-    wall = time.perf_counter() - t0
+    sub = dict(model, params=model["params"][::sample_every]) if sample_every > 1 else model
+    before = os.sched_getaffinity(0)
+    core = min(before)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        r = oracle.explore(sub, trace=True)
+        c = oracle.explore(sub, T=r["t_min"] - 1, trace=False)
+        wall = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, before)
     states = r["reachable"] + c["reachable"]
+    what = ("the whole workload" if sample_every == 1 else
+            f"every {sample_every}th configuration ({len(sub['params'])} of "
+            f"{len(model['params'])})")
     return {"value": states / (r["seconds"] + c["seconds"]), "unit": "states/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"full step on the same workload: min_time ({r['reachable']} states) + "
-                      f"check(T_min-1) ({c['reachable']} states); exploration time "
-                      f"{r['seconds'] + c['seconds']:.2f} s, wall {wall:.2f} s",
-            "agrees": r["t_min"] == t_min}
+            "sample": f"{what}: min_time ({r['reachable']} states) + check(T_min-1) "
+                      f"({c['reachable']} states); exploration {r['seconds'] + c['seconds']:.2f} s, "
+                      f"wall {wall:.2f} s",
+            "pinned_core": core, "nproc": os.cpu_count(), "affinity_cores": len(before),
+            "cpu_model": _cpu_model(),
+            "agrees": (t_min is None or sample_every > 1 or r["t_min"] == t_min)}
 
 
 BATCH_BUDGET = 1 << 20
@@ -124,23 +192,36 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
     b.close()
     del ws
     torch.cuda.empty_cache()
-    # one at a time (fresh load per instance), on a sample
+    # one at a time on a sample: a load per instance into one preallocated workspace,
+    # the library's automatic launch options
     idx = list(range(0, n_inst, max(1, n_inst // sample_alone)))[:sample_alone]
+    ws1 = torch.empty(max(mc.mc_workspace_bytes(models[i]) for i in idx), dtype=torch.uint8,
+                      device="cuda:0")
+    g = mc.Model(models[idx[0]], workspace=ws1)  # warm
+    g.mc_min_time()
+    g.close()
+    torch.cuda.synchronize()
     t_alone, s_alone = 0.0, 0
     for i in idx:
         t1 = time.perf_counter()
-        g = mc.Model(models[i], block=512)
+        g = mc.Model(models[i], workspace=ws1)
         tm, _ = g.mc_min_time()
         s_alone += g.last_stats["states"]
         g.close()
         t_alone += time.perf_counter() - t1
         assert tm == t_min[i]
-    return {"instances": n_inst, "rejected_draws": rejected, "states": total,
+    del ws1
+    torch.cuda.empty_cache()
+    return {"instances": n_inst, "rejected_draws": rejected,
+            "draw_filter": f"instances above {BATCH_BUDGET} states redrawn "
+                           f"({rejected} of {rejected + n_inst} draws)",
+            "states": total,
             "value": total / el, "unit": "states/s", "queries_per_s": n_inst / el,
             "ms_per_batch": 1e3 * el, "gpu_ms": gpu_ms,
             "autotuned": best.as_dict(), "autotune_s": tune_s,
             "one_at_a_time": {"sample": len(idx), "value": s_alone / t_alone,
-                              "queries_per_s": len(idx) / t_alone},
+                              "queries_per_s": len(idx) / t_alone,
+                              "how": "preallocated workspace, automatic launch options"},
             "speedup_vs_one_at_a_time": (total / el) / (s_alone / t_alone)}
 
 
@@ -200,13 +281,15 @@ def model_leg(mc, torch, models: dict, reps: int, cpu: bool):
         del ws
         states = sum(s["states"] for s in steps)
         eng_s = sum(s["engine_ns_min"] for s in steps) * 1e-9 / reps
-        achieved = steps[0]["min_states"] * ALGO_BYTES_PER_STATE / eng_s / 1e9
+        bps = algo_bytes_per_state(mc, model, steps[0])
+        achieved = steps[0]["min_states"] * bps / eng_s / 1e9
         rec = {"kind": model["kind"], "cu": model["m"], "configurations": len(model["params"]),
                "Lg": model["Lg"], "Ll": model["Ll"],
                "reachable": steps[0]["min_states"], "levels": steps[0]["levels"],
                "t_min": steps[0]["t_min"], "argmin": steps[0]["argmin"],
                "ms_per_step": 1e3 * elapsed / reps, "states_per_s": states / elapsed,
                "min_time_engine_ms": eng_s * 1e3, "roofline_frac": achieved / HBM_PEAK_GBS,
+               "algo_bytes_per_state": bps,
                "partitions": steps[0]["parts"],
                "step_breakdown_ms": {k: sum(s["breakdown_ms"][k] for s in steps) / reps
                                      for k in steps[0]["breakdown_ms"]}}
@@ -278,52 +361,64 @@ def bb_leg(mc, torch, workloads, names, reps: int = 5):
 
 
 def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int = 32):
-    """Poisson arrivals of check(T)/min_time queries over a pool of models; continuous
-    batching engine vs FIFO one-query-at-a-time service (fresh load per query)."""
-    pool, _ = workloads.draw_batch(
+    """Poisson arrivals of check(T)/min_time queries over a pool of models: the
+    continuous-batching engine against FIFO one-query-at-a-time service, both run in
+    real time under the same arrival stream.  FIFO service loads each query's model
+    into one preallocated workspace with the library's automatic launch options."""
+    pool, rejected = workloads.draw_batch(
         4, pool_size, lambda x: (mc.state_count(x) or BATCH_BUDGET + 1) <= BATCH_BUDGET)
     mix = workloads.query_mix(4, n_queries, pool_size)
+    ws = torch.empty(max(mc.mc_workspace_bytes(m) for m in pool), dtype=torch.uint8,
+                     device="cuda:0")
     tmins = []  # the threshold recipe needs each model's T_min: one untimed GPU query each
     for m in pool:
-        g = mc.Model(m, block=512)
+        g = mc.Model(m, workspace=ws)
         tmins.append(g.mc_min_time()[0])
         g.close()
     qs = [(i, kind, int(u * tmins[i])) for i, kind, u in mix]
-    # FIFO one-at-a-time service times (super-step engine alone, fresh load per query)
-    svc = {}
-    for i, kind, T in qs[:min(len(qs), 200)]:
-        key = (i, kind, T)
-        if key in svc:
-            continue
-        t1 = time.perf_counter()
-        g = mc.Model(pool[i], block=512)
+
+    def serve_one(i, kind, T):
+        g = mc.Model(pool[i], workspace=ws)
         if kind == "min_time":
             g.mc_min_time()
         else:
             g.mc_check(T)
         g.close()
-        svc[key] = time.perf_counter() - t1
-    mean_svc = sum(svc.values()) / len(svc)
-    fifo_capacity = 1.0 / mean_svc
-    out = {"queries": n_queries, "pool": pool_size, "fifo_capacity_qps": fifo_capacity,
-           "runs": []}
+
+    # FIFO capacity: every query of the stream served back to back
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in qs:
+        serve_one(*q)
+    fifo_capacity = n_queries / (time.perf_counter() - t0)
+    out = {"queries": n_queries, "pool": pool_size, "rejected_draws": rejected,
+           "draw_filter": f"models above {BATCH_BUDGET} states redrawn",
+           "fifo_capacity_qps": fifo_capacity, "runs": []}
 
     def pct(xs, p):
         xs = sorted(xs)
         return xs[min(len(xs) - 1, int(p * len(xs)))]
 
+    def wait_until(t0, a):
+        while True:
+            d = a - (time.perf_counter() - t0)
+            if d <= 0:
+                return
+            if d > 2e-3:
+                time.sleep(d - 1e-3)
+
     for f in qps_factors:
         _progress(f"served run at {f}x the FIFO capacity")
         qps = f * fifo_capacity
         arr = workloads.poisson_arrivals(4, n_queries, qps)
-        # FIFO one at a time: exact single-server simulation from measured service times
-        svc_list = list(svc.values())
-        done, lat_fifo = 0.0, []
-        for k, a in enumerate(arr):
-            s_k = svc.get(qs[k], svc_list[k % len(svc_list)])
-            start = max(a, done)
-            done = start + s_k
-            lat_fifo.append(done - a)
+        # FIFO one at a time, in real time
+        lat_fifo = []
+        t0 = time.perf_counter()
+        for k, q in enumerate(qs):
+            wait_until(t0, arr[k])
+            serve_one(*q)
+            lat_fifo.append(time.perf_counter() - t0 - arr[k])
+        fifo_wall = time.perf_counter() - t0
         # continuous batching engine, driven in real time
         e = mc.Engine(arena_bytes=24 << 30, max_active=128, max_cfg=512, block=512, slice=16)
         tickets = []
@@ -358,8 +453,16 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
             "qps_offered": qps, "factor": f, "queries_per_s": n_queries / wall,
             "p50_ms": 1e3 * pct(lat, 0.5), "p99_ms": 1e3 * pct(lat, 0.99),
             "fifo_p50_ms": 1e3 * pct(lat_fifo, 0.5), "fifo_p99_ms": 1e3 * pct(lat_fifo, 0.99),
-            "fifo_queries_per_s": n_queries / max(done, arr[-1])})
+            "fifo_queries_per_s": n_queries / fifo_wall})
+    del ws
+    torch.cuda.empty_cache()
     return out
+
+
+def peak_leg(buf_bytes: int) -> dict:
+    """Random-access peaks of the device on a buffer of the visited set's size class."""
+    from paper_2305_09130_amd import peak
+    return peak.measure(buf_bytes=buf_bytes)
 
 
 def main():
@@ -367,15 +470,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="matmul64_cu4")
+    ap.add_argument("--workload", default="matmul128_vw_cu8")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--load-factor", type=float, default=0.0)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--legs", default="plain,cpu,batch,serve,swarm,units,bb,hetero",
+    ap.add_argument("--legs", default="peak,plain,cpu,batch,serve,swarm,units,bb,hetero",
                     help="extra legs beside the timed single-query step")
+    ap.add_argument("--cpu-sample-states", type=int, default=16_000_000,
+                    help="largest state count the CPU oracle explores: every k-th "
+                         "configuration of the workload, k the least that fits")
+    ap.add_argument("--peak-buffer-gib", type=int, default=8,
+                    help="buffer of the random-access peak probes (GiB, a power of two)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -425,15 +533,22 @@ def main():
     def pct(p):
         return lat[min(len(lat) - 1, int(p * len(lat)))]
 
-    # roofline of the dominant kernel (the persistent super-step engine), per launch
+    # roofline of the dominant kernel (the persistent super-step engine), per launch:
+    # the min_time launch, timed with HIP events on the query's stream
     eng_s = sum(s["engine_ns_min"] for s in steps) * 1e-9 / len(steps)
-    algo_bytes = steps[-1]["min_states"] * ALGO_BYTES_PER_STATE
+    bps = algo_bytes_per_state(mc, model, steps[-1])
+    algo_bytes = steps[-1]["min_states"] * bps
     achieved = algo_bytes / eng_s / 1e9
     src_hash = kernel_source_hash()
     traffic = read_traffic(args.workload, "k_superstep", src_hash)
 
     legs = set(x for x in args.legs.split(",") if x)
     _progress(f"timed step done: {1e3 * elapsed / args.steps:.3f} ms/step")
+    peak = None
+    if "peak" in legs:
+        peak = peak_leg(args.peak_buffer_gib << 30)
+        _progress(f"peak leg: random CAS {peak['random_cas_per_s'] / 1e9:.2f} G/s, random 64-B "
+                  f"reads {peak['random_read_GBps']:.0f} GB/s, copy {peak['copy_GBps']:.0f} GB/s")
     plain = None
     if args.plain_steps > 0 and "plain" in legs:
         ps = [run_step(mc, model, mc.MC_ENGINE_LEVEL, workspace, args.block, args.load_factor)
@@ -450,7 +565,11 @@ def main():
     _progress("plain BFS leg done" if plain else "plain BFS leg skipped")
     cpu = None
     if not args.no_cpu and "cpu" in legs:
-        cpu = cpu_baseline(model, steps[0]["t_min"])
+        k = 1
+        while (mc.state_count(dict(model, params=model["params"][::k])) or 0) > \
+                args.cpu_sample_states:
+            k += 1
+        cpu = cpu_baseline(model, steps[0]["t_min"], sample_every=k)
     batched = served = None
     if "batch" in legs:
         _progress("cpu leg done; batched leg")
@@ -461,12 +580,15 @@ def main():
     swarm = None
     if "swarm" in legs:
         _progress("swarm leg")
-        swarm = swarm_leg(mc, workloads, [args.workload, "matmul128_vw_cu8"])
+        swarm = swarm_leg(mc, workloads, ["reduction_g256_cu4_s1123", "matmul32_cu4_s1123",
+                                          args.workload])
     bbr = None
     if "bb" in legs:
         _progress("branch-and-bound leg")
-        bbr = bb_leg(mc, torch, workloads, [args.workload, "matmul128_vw_cu8",
-                                            "abstract_s1024_np4_cu4", "matmul32_cu4_s1123"])
+        bbr = bb_leg(mc, torch, workloads,
+                     list(dict.fromkeys([args.workload, "reduction_g256_cu2", "matmul64_cu4",
+                                         "matmul128_vw_cu8", "abstract_s1024_np4_cu4",
+                                         "matmul32_cu4_s1123"])))
     hetero = None
     if "hetero" in legs:
         _progress("unequal-units leg")
@@ -476,6 +598,21 @@ def main():
         _progress("unit-model leg")
         units = units_leg(mc, torch, workloads, cpu=not args.no_cpu and "cpu" in legs)
 
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_superstep", "launch": "min_time exploration",
+                "algo_bytes_per_state": bps, "algo_bytes_per_launch": algo_bytes,
+                "states_per_launch": steps[-1]["min_states"],
+                "avg_launch_ms": eng_s * 1e3, "kernel_source_hash": src_hash}
+    if peak:
+        # the measured random-access ceiling: random 64-byte line reads (the granule of
+        # every visited-set touch) and random 64-bit CAS (one per claim)
+        roofline["peak_measured"] = peak["random_read_GBps"]
+        roofline["frac_measured"] = achieved / peak["random_read_GBps"]
+        roofline["states_per_s_launch"] = steps[-1]["min_states"] / eng_s
+        roofline["cas_peak_per_s"] = peak["random_cas_per_s"]
+        roofline["states_over_cas_peak"] = roofline["states_per_s_launch"] / peak["random_cas_per_s"]
+        roofline["peak_probe"] = peak
     cfg = {"workload": args.workload, "kind": model["kind"], "cu": model["m"],
            "configurations": len(model["params"]),
            "Lg": model["Lg"], "Ll": model["Ll"], "Lc": model.get("Lc", 1), "Lb": model.get("Lb", 0),
@@ -506,10 +643,7 @@ def main():
                               for k in steps[0]["breakdown_ms"]},
         "partitions": steps[0]["parts"],
         "latency_ms": {"p50": 1e3 * pct(0.5), "p99": 1e3 * pct(0.99)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_superstep", "algo_bytes_per_launch": algo_bytes,
-                     "avg_launch_ms": eng_s * 1e3, "kernel_source_hash": src_hash},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_bfs": plain,
         "batched": batched,

@@ -91,6 +91,8 @@ extern "C" {
 #define MC_E_NOTFOUND (-9)   /* no such ticket / state */
 #define MC_E_INTERNAL (-10)  /* an internal consistency check failed (a round block of a
                                 configuration did not end on its predicted state) */
+#define MC_E_ABORTED (-11)   /* the query was stopped by mc_abort / mc_batch_abort before
+                                it finished; it has no result */
 
 /* ---- model descriptor ---------------------------------------------------------- */
 #define MC_KIND_REDUCTION 0u
@@ -270,6 +272,17 @@ int mc_tune_bisect(mc_model *h, uint64_t seed, uint32_t *t_min, uint32_t *n_chec
 /* Select the exploration engine used by later queries (MC_ENGINE_*); both engines
  * compute identical results. */
 int mc_set_engine(mc_model *h, uint32_t engine);
+
+/* Asks the query running on h (or, when none runs, the next one started) to stop.  It
+ * is the one call that may come from another host thread while a query runs on h: it
+ * stores to a pinned host word that the exploration kernels read when a workgroup takes
+ * its next partition (super-step engine) or a launch starts (level engine).  Partitions
+ * already being explored finish, the rest are skipped, and every kernel exits
+ * normally; the query then returns MC_E_ABORTED with no result, which consumes the
+ * request.  A request made after the exploration kernel has finished stays pending
+ * for the next query.  Not a paper operation: it serves callers (servers, test
+ * harnesses) that must bound a query's time. */
+int mc_abort(mc_model *h);
 
 /* Parameters of configuration cfg (4 values, as in the descriptor). */
 int mc_config(const mc_model *h, uint32_t cfg, uint32_t *params4);

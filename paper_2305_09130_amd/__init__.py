@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmctune.so")
 MC_OK = 0
 MC_E_INVAL, MC_E_NOMEM, MC_E_DEVICE, MC_E_TABLE_FULL = -1, -2, -3, -4
 MC_E_BUFFER, MC_E_STATE, MC_E_OVERFLOW, MC_E_ADMIT, MC_E_NOTFOUND = -5, -6, -7, -8, -9
-MC_E_INTERNAL = -10
+MC_E_INTERNAL, MC_E_ABORTED = -10, -11
 NEVER_CUT = 0xFFFFFFFF
 MC_KIND_REDUCTION, MC_KIND_MATMUL, MC_KIND_ABSTRACT, MC_KIND_MINIMUM = 0, 1, 2, 3
 MC_ENGINE_SUPERSTEP, MC_ENGINE_LEVEL = 0, 1
@@ -145,6 +145,7 @@ _SIGS = {
     "mc_model_free": ([_vp], ctypes.c_int),
     "mc_model_info_get": ([_vp, _P(McModelInfo)], ctypes.c_int),
     "mc_set_engine": ([_vp, ctypes.c_uint32], ctypes.c_int),
+    "mc_abort": ([_vp], ctypes.c_int),
     "mc_min_time": ([_vp, _u32p, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t), _P(McStats)],
                     ctypes.c_int),
     "mc_check": ([_vp, ctypes.c_uint32, _P(ctypes.c_int), _P(McStats)], ctypes.c_int),
@@ -324,6 +325,11 @@ class Model:
 
     def mc_set_engine(self, engine: int) -> None:
         _check("mc_set_engine", _lib.mc_set_engine(self._h, engine))
+
+    def mc_abort(self) -> None:
+        """Stop request for the running (or the next) query of this model; safe to call
+        from another thread while a query runs."""
+        _check("mc_abort", _lib.mc_abort(self._h))
 
     def mc_min_time(self) -> tuple[int, list[int]]:
         t = ctypes.c_uint32()

@@ -1,41 +1,78 @@
-"""Build step of the HIP library: compiles csrc/ into libmctune.so for gfx950."""
+"""Build step of the HIP libraries for gfx950: csrc/ into libmctune.so (the explorer)
+and libmcpeak.so (the random-access peak probes used by the benchmark)."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmctune.so")
-SOURCES = ["mc_model.cpp", "mc_host_pool.cpp", "mc_kernels.hip", "mc_api.hip", "mc_batch.hip", "mc_engine.hip"]
+PEAK_LIB = os.path.join(HERE, "libmcpeak.so")
+SOURCES = ["mc_model.cpp", "mc_host_pool.cpp", "mc_kernels.hip", "mc_api.hip", "mc_batch.hip",
+           "mc_engine.hip"]
+PEAK_SOURCES = ["mc_peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+          "-Wno-unused-command-line-argument"]
+DEV = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
-    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-              "-Wno-unused-command-line-argument"]
-    dev = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    outdir = os.path.join(HERE, "_build")
-    os.makedirs(outdir, exist_ok=True)
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(outdir, src + ".o")
-        if src.endswith(".hip"):
-            cmd = [HIPCC, *common, *dev, "-x", "hip", "-c", path, "-o", obj]
+# mc_kernels.hip is compiled once per part (MC_PART): the k_superstep instances of each
+# key width in a part of their own, everything else in part 0
+KERNEL_PARTS = (0, 1, 2, 4)
+
+
+def _units(srcs: list[str]) -> list[tuple[str, int | None]]:
+    out = []
+    for s in srcs:
+        if s == "mc_kernels.hip":
+            out += [(s, p) for p in KERNEL_PARTS]
         else:
-            cmd = [HIPCC, *common, "-c", path, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
-    tmp = LIB + ".tmp"
+            out.append((s, None))
+    return out
+
+
+def _compile(unit: tuple[str, int | None], outdir: str, verbose: bool) -> str:
+    src, part = unit
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(outdir, src + ("" if part is None else f".part{part}") + ".o")
+    extra = [] if part is None else [f"-DMC_PART={part}"]
+    if src.endswith(".hip"):
+        cmd = [HIPCC, *COMMON, *DEV, *extra, "-x", "hip", "-c", path, "-o", obj]
+    else:
+        cmd = [HIPCC, *COMMON, *extra, "-c", path, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
+def _link(objs: list[str], lib: str, verbose: bool) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compiles every source (in parallel: the kernel file dominates) and links both
+    libraries.  Returns the explorer library's path."""
+    outdir = os.path.join(HERE, "_build")
+    os.makedirs(outdir, exist_ok=True)
+    units = _units(SOURCES)
+    peak_units = _units(PEAK_SOURCES)
+    jobs = jobs or min(len(units) + len(peak_units), max(1, (os.cpu_count() or 2) - 1), 8)
+    # the heaviest units first, so that they start at once
+    order = sorted(units + peak_units, key=lambda u: u[1] is None)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = dict(zip(order, ex.map(lambda u: _compile(u, outdir, verbose), order)))
+    _link([objs[u] for u in units], LIB, verbose)
+    _link([objs[u] for u in peak_units], PEAK_LIB, verbose)
     return LIB
 
 

@@ -175,6 +175,9 @@ struct mc_model {
   unsigned char* table = nullptr;
   Ctrl* hctrl = nullptr;  // pinned host copy
   uint32_t* hpoll = nullptr;
+  // stop request of mc_abort: a pinned host word the kernels read at system scope; the
+  // query that returns MC_E_ABORTED clears it
+  unsigned int* habort = nullptr;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool dirty = true;
   int last = kQueryNone;
@@ -232,6 +235,7 @@ int level_loop(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   LevelArgs la;
   la.q = q;
   la.fcap = (uint32_t)fcap;
+  la.abort = h->habort;
   const uint64_t limit = h->mh.max_depth + 64;
   const uint32_t batch = 64;
   uint64_t L = 0;
@@ -316,6 +320,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     pq.reverse = bb ? 1u : 0u;
     pq.yielded = nullptr;
     pq.n_yielded = nullptr;
+    pq.abort = h->habort;
     const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
     HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general, h->mh.hetero));
     HIPCHK(hipEventRecord(h->ev[5], s));
@@ -339,6 +344,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   HIPCHK(hipMemcpyAsync(h->tc_host, h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int derr = dev_error_code(h->hctrl->error);
+  if (derr == MC_E_ABORTED) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
   if (derr != MC_OK) return derr;
   float ms_explore = 0.f, ms_clear = 0.f, ms_engine = 0.f;
   HIPCHK(hipEventElapsedTime(&ms_explore, h->ev[2], h->ev[3]));
@@ -423,6 +429,7 @@ const char* mc_strerror(int code) {
     case MC_E_ADMIT: return "query cannot fit the memory budget";
     case MC_E_NOTFOUND: return "not found";
     case MC_E_INTERNAL: return "internal consistency check failed";
+    case MC_E_ABORTED: return "query stopped by an abort request";
     default: return "unknown error";
   }
 }
@@ -552,6 +559,8 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     }
     h->hctrl = reinterpret_cast<Ctrl*>(h->pin);
     h->hpoll = reinterpret_cast<uint32_t*>(h->pin + 256);
+    h->habort = reinterpret_cast<unsigned int*>(h->pin + 256 + 128);
+    __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
     h->hmd = reinterpret_cast<ModelDev*>(h->pin + 512);
     h->tc_host = reinterpret_cast<uint32_t*>(h->pin + tc_off);
     for (uint32_t c = 0; c < h->mh.n_cfg; ++c) h->tc_host[c] = kNoClock;
@@ -594,6 +603,12 @@ int mc_model_info_get(const mc_model* h, mc_model_info* info) {
   info->slot_bytes = h->plan.slot_bytes;
   info->bound_states = h->mh.states;
   info->max_depth = h->mh.max_depth;
+  return MC_OK;
+}
+
+int mc_abort(mc_model* h) {
+  if (!h || !h->habort) return MC_E_INVAL;
+  __atomic_store_n(h->habort, 1u, __ATOMIC_RELEASE);
   return MC_OK;
 }
 

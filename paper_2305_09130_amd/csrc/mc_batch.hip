@@ -191,6 +191,7 @@ int enqueue_query(mc_batch* b) {
     pq[w].reverse = 0u;
     pq[w].yielded = nullptr;
     pq[w].n_yielded = nullptr;
+    pq[w].abort = nullptr;
   }
   bool general = false, hetero = false;
   for (const ModelHost& mh : b->ms) {

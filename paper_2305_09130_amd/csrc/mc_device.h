@@ -43,6 +43,7 @@ constexpr unsigned int kDevErrOverflow = 2;
 constexpr unsigned int kDevErrPublish = 3;
 constexpr unsigned int kDevErrTrace = 4;
 constexpr unsigned int kDevErrSplit = 5;  // a round block did not end on its predicted state
+constexpr unsigned int kDevErrAbort = 6;  // the host asked the query to stop
 
 constexpr uint32_t kMaxProbeIters = 1u << 16;
 
@@ -325,6 +326,7 @@ __device__ __forceinline__ uint32_t* slot_jump(unsigned char* base, unsigned lon
 
 constexpr int kScopeWG = __HIP_MEMORY_SCOPE_WORKGROUP;
 constexpr int kScopeAgent = __HIP_MEMORY_SCOPE_AGENT;
+constexpr int kScopeSystem = __HIP_MEMORY_SCOPE_SYSTEM;
 
 enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 

@@ -452,6 +452,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       pq[g].reverse = 0u;
       pq[g].yielded = next;
       pq[g].n_yielded = ny;
+      pq[g].abort = nullptr;
       grid[g] = std::max<uint32_t>(1u, std::min<uint32_t>(gn[g], e->opts.grid ? e->opts.grid : 1024u));
       off += gn[g];
     }

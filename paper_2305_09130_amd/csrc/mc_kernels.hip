@@ -14,10 +14,17 @@
 
 #include "mc_launch.h"
 
+// The file is compiled once per part, so that the many instances of the persistent
+// kernel build in parallel: MC_PART 0 holds every kernel and launch helper except the
+// k_superstep instances; MC_PART 1, 2 and 4 hold the k_superstep instances of that key
+// width (launch_super_w).
+#ifndef MC_PART
+#define MC_PART 0
+#endif
+
 namespace mc {
 
-
-
+#if MC_PART == 0
 __global__ void k_clear(uint4* p, unsigned long long n16) {
   const uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
@@ -34,6 +41,7 @@ __global__ void k_reset(Ctrl* ctrl, uint32_t* tc, uint32_t n_cfg) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_cfg; i += gridDim.x * blockDim.x)
     tc[i] = kNoClock;
 }
+#endif  // MC_PART == 0
 
 __device__ __forceinline__ void set_error(Ctrl* ctrl, unsigned int e) { atomicCAS(&ctrl->error, 0u, e); }
 
@@ -133,14 +141,27 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
   __shared__ uint32_t s_par[STAGE];
   __shared__ uint32_t s_dep[STAGE];
   __shared__ uint32_t s_cnt;
+  __shared__ uint32_t s_n_in;
   const QueryArgs& q = a.q;
-  uint32_t n_in = __hip_atomic_load(&q.ctrl->fcount[a.in_idx], __ATOMIC_RELAXED, kScopeAgent);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    q.ctrl->fcount[a.clr_idx] = 0u;
-    if (n_in) atomicAdd(&q.ctrl->levels, 1u);
+  if (threadIdx.x == 0) {
+    // one read of the frontier size and of the error and abort flags per workgroup: the
+    // flags are set concurrently by other workgroups (or the host), and every wave must
+    // run the same number of barrier-separated iterations below
+    uint32_t n = __hip_atomic_load(&q.ctrl->fcount[a.in_idx], __ATOMIC_RELAXED, kScopeAgent);
+    if (blockIdx.x == 0) {
+      q.ctrl->fcount[a.clr_idx] = 0u;
+      if (n) atomicAdd(&q.ctrl->levels, 1u);
+    }
+    if (__hip_atomic_load(&q.ctrl->error, __ATOMIC_RELAXED, kScopeAgent)) n = 0;  // stop
+    if (n && a.abort && __hip_atomic_load(a.abort, __ATOMIC_RELAXED, kScopeSystem)) {
+      set_error(q.ctrl, kDevErrAbort);
+      n = 0;
+    }
+    if (n > a.fcap) n = a.fcap;  // appends beyond the capacity were dropped (error set)
+    s_n_in = n;
   }
-  if (__hip_atomic_load(&q.ctrl->error, __ATOMIC_RELAXED, kScopeAgent)) n_in = 0;  // stop
-  if (n_in > a.fcap) n_in = a.fcap;  // appends beyond the capacity were dropped (error set)
+  __syncthreads();
+  const uint32_t n_in = s_n_in;
   const int m = q.L.m;
   unsigned long long n_states = 0, n_terms = 0, n_edges = 0, n_dups = 0, depth_max = 0;
   uint32_t probes = 0;
@@ -327,6 +348,7 @@ struct SuperShared {
   uint32_t fdep[2][kFCap];
   uint32_t fcount[2];
   uint32_t part, carry, stop, nseg, total;
+  uint32_t skip;        // the partition is not explored (an error, or an abort from the host)
   uint32_t chain_more;  // another chain joined the batch: list it
   // end of a block of rounds: the state B_r1, its clock and depth, the batch item that
   // generates it, and whether it was reached
@@ -1400,10 +1422,21 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     const uint32_t part = sh.part;
     if (part >= a.n_parts) break;
     const Part pc = a.parts[a.reverse ? a.n_parts - 1u - part : part];
-    if (tid == 0) sh.md = a.models[pc.model];
+    if (tid == 0) {
+      sh.md = a.models[pc.model];
+      // one read of the model's error flag for the whole workgroup: other workgroups set
+      // it concurrently, and every wave must take the same branch around the barriers
+      // of the exploration
+      bool stop = __hip_atomic_load(&sh.md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
+      if (!stop && a.abort && __hip_atomic_load(a.abort, __ATOMIC_RELAXED, kScopeSystem) != 0u) {
+        set_error(sh.md.ctrl, kDevErrAbort);
+        stop = true;
+      }
+      sh.skip = stop ? 1u : 0u;
+    }
     __syncthreads();
     const ModelDev& md = sh.md;
-    const bool skip = __hip_atomic_load(&md.ctrl->error, __ATOMIC_RELAXED, kScopeAgent) != 0u;
+    const bool skip = sh.skip != 0u;
     const unsigned long long t_part = __builtin_amdgcn_s_memrealtime();
     if (!skip && pc.r0 == kRunSlice) explore_slice<W, BLOCK, NI, GEN>(md, pc, sh);
     else if (!skip) explore_partition<W, BLOCK, NI, GEN, HET>(md, pc, a.batch_items, a.slice, a, sh);
@@ -1415,6 +1448,48 @@ __global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
     __syncthreads();
   }
 }
+
+// k_superstep instances: built in the part of their key width only
+template <int W, bool GEN, bool HET>
+void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32_t items,
+                    const PartQueue& pq);
+
+#if MC_PART != 0
+template <int W, bool GEN, bool HET>
+void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32_t items,
+                    const PartQueue& pq) {
+#define MC_LAUNCH_SUPER(B, N) \
+  hipLaunchKernelGGL((k_superstep<W, B, N, GEN, HET>), dim3(grid), dim3(B), 0, st, pq)
+  if (block == 256) {
+    if (items >= 2) MC_LAUNCH_SUPER(256, 2);
+    else MC_LAUNCH_SUPER(256, 1);
+  } else if (block == 1024) {
+    if (items >= 2) MC_LAUNCH_SUPER(1024, 2);
+    else MC_LAUNCH_SUPER(1024, 1);
+  } else {
+    if (items >= 2) MC_LAUNCH_SUPER(512, 2);
+    else MC_LAUNCH_SUPER(512, 1);
+  }
+#undef MC_LAUNCH_SUPER
+}
+template void launch_super_w<MC_PART, false, false>(hipStream_t, uint32_t, uint32_t, uint32_t,
+                                                    const PartQueue&);
+template void launch_super_w<MC_PART, true, false>(hipStream_t, uint32_t, uint32_t, uint32_t,
+                                                   const PartQueue&);
+template void launch_super_w<MC_PART, true, true>(hipStream_t, uint32_t, uint32_t, uint32_t,
+                                                  const PartQueue&);
+#else
+#define MC_EXTERN_SUPER(W)                                                                   \
+  extern template void launch_super_w<W, false, false>(hipStream_t, uint32_t, uint32_t,     \
+                                                       uint32_t, const PartQueue&);          \
+  extern template void launch_super_w<W, true, false>(hipStream_t, uint32_t, uint32_t,      \
+                                                      uint32_t, const PartQueue&);           \
+  extern template void launch_super_w<W, true, true>(hipStream_t, uint32_t, uint32_t,       \
+                                                     uint32_t, const PartQueue&);
+MC_EXTERN_SUPER(1)
+MC_EXTERN_SUPER(2)
+MC_EXTERN_SUPER(4)
+#undef MC_EXTERN_SUPER
 
 // Root and SELECT successors of every model of a queue, one workgroup per model.
 template <int W>
@@ -1922,24 +1997,6 @@ hipError_t launch_level(hipStream_t st, uint32_t grid, const LevelArgs& la, cons
   return hipGetLastError();
 }
 
-template <int W, bool GEN, bool HET>
-static void launch_super_w(hipStream_t st, uint32_t grid, uint32_t block, uint32_t items,
-                           const PartQueue& pq) {
-#define MC_LAUNCH_SUPER(B, N) \
-  hipLaunchKernelGGL((k_superstep<W, B, N, GEN, HET>), dim3(grid), dim3(B), 0, st, pq)
-  if (block == 256) {
-    if (items >= 2) MC_LAUNCH_SUPER(256, 2);
-    else MC_LAUNCH_SUPER(256, 1);
-  } else if (block == 1024) {
-    if (items >= 2) MC_LAUNCH_SUPER(1024, 2);
-    else MC_LAUNCH_SUPER(1024, 1);
-  } else {
-    if (items >= 2) MC_LAUNCH_SUPER(512, 2);
-    else MC_LAUNCH_SUPER(512, 1);
-  }
-#undef MC_LAUNCH_SUPER
-}
-
 hipError_t launch_super(hipStream_t st, uint32_t W, uint32_t grid, uint32_t block,
                         uint32_t items, const PartQueue& pq, bool general, bool hetero) {
   items = lane_items_for(items, W);
@@ -2056,5 +2113,7 @@ hipError_t launch_simulate(hipStream_t st, const QueryArgs& q, unsigned long lon
   hipLaunchKernelGGL(k_simulate, dim3(1), dim3(64), 0, st, q, seed);
   return hipGetLastError();
 }
+
+#endif  // MC_PART == 0
 
 }  // namespace mc

@@ -36,6 +36,7 @@ inline int dev_error_code(unsigned int e) {
     case kDevErrTableFull: return MC_E_TABLE_FULL;
     case kDevErrOverflow: return MC_E_OVERFLOW;
     case kDevErrSplit: return MC_E_INTERNAL;
+    case kDevErrAbort: return MC_E_ABORTED;
     default: return MC_E_DEVICE;
   }
 }
@@ -44,6 +45,7 @@ struct LevelArgs {
   QueryArgs q;
   uint32_t in_idx, out_idx, clr_idx;  // rotating frontier counters
   uint32_t fcap;
+  const unsigned int* abort;  // host-set stop request (pinned host word), or null
 };
 
 // Saved frontier of a partition explored across several launches.
@@ -98,6 +100,10 @@ struct PartQueue {
   uint32_t reverse;      // take the partitions smallest first
   Part* yielded;         // partitions that yielded, for the next launch
   unsigned int* n_yielded;
+  // host-set stop request (a pinned host word read at system scope), or null: a
+  // partition taken after it is set is not explored, so the launch drains quickly and
+  // every workgroup still exits normally
+  const unsigned int* abort;
 };
 
 template <int W>

@@ -175,3 +175,17 @@ def test_invalid_speeds(mc):
         with pytest.raises(mc.McError) as e:
             mc.mc_describe(workloads.with_speeds(base, speeds))
         assert e.value.code == mc.MC_E_INVAL
+
+
+def test_peak_library_exports_its_header():
+    from paper_2305_09130_amd import peak
+    names = peak.exported_symbols()
+    assert names == ["mcp_random_cas", "mcp_random_read"]
+    lib = ctypes.CDLL(peak.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/mcpeak.h but not exported"
+
+
+def test_abort_code(mc):
+    assert mc.MC_E_ABORTED == -11
+    assert "abort" in mc.mc_strerror(mc.MC_E_ABORTED)
