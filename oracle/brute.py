@@ -41,6 +41,57 @@ def _ticked_pex(S: int, TS: int, gmt: int, loc: int) -> list[int]:
     return spent
 
 
+def _ticked_minimum(WG: int, TS: int, NP: int, gmt: int, loc: int) -> list[int]:
+    """Ticks between consecutive operation ends of one workgroup of the Minimum model,
+    found by running its unit (Listing 14) and processing elements (Listing 15) one
+    tick at a time.
+
+    The unit starts min(WG, NP) elements on iteration 0.  While WG > NP it answers
+    WG - NP status messages: an element that has not reached its last iteration,
+    (iter + 1) >= WG/NP, is launched again on the unit's current iteration number,
+    which advances after every NP answers; the last statuses are collected by its
+    final loop.  An element's MAP makes TS global accesses, one after another, each
+    a wait of GMT ticks (the reading of its long_work(GMT) per access); the running
+    elements report every tick together, so the clock moves with all of them.  After
+    the workgroup, element 0 folds the minima that the other elements left in local
+    memory, Ll ticks per element, and writes the result to global memory in GMT."""
+    time = 0
+    ends = []
+    nwe = WG if WG <= NP else NP
+    last_iter = WG // NP                      # the listing's integer WG/NP
+    running = {e: 0 for e in range(nwe)}      # element -> iteration it runs
+    answers_left = WG - NP if WG > NP else 0  # statuses the unit's loop receives
+    it, num = 1, 0
+    while running:
+        left = {e: TS * gmt for e in running}  # ticks of global access work left
+        while any(left.values()):
+            time += 1                          # every running element reported: tick
+            ended = False
+            for e in left:
+                if left[e]:
+                    left[e] -= 1
+                    ended = ended or left[e] % gmt == 0
+            if ended:
+                ends.append(time)              # an access ended
+        relaunch = {}
+        for e in sorted(running):
+            done_wg = running[e] + 1 >= last_iter
+            if answers_left:
+                answers_left -= 1
+                if not done_wg:
+                    relaunch[e] = it
+                num += 1
+                if num >= NP:
+                    it, num = it + 1, 0
+        running = relaunch
+    for other in range(1, nwe):                # element 0 folds loc[myloc + other]
+        time += loc
+        ends.append(time)
+    time += gmt                                # the workgroup's minimum to global memory
+    ends.append(time)
+    return [b - a for a, b in zip([0] + ends[:-1], ends)]
+
+
 def workgroup_program(model: dict, row) -> tuple[int, list[int]]:
     """(number of workgroups, latency of every operation of one workgroup, in order)."""
     if model["kind"] in ("abstract", "minimum"):
@@ -49,9 +100,7 @@ def workgroup_program(model: dict, row) -> tuple[int, list[int]]:
         waves = max(1, wg // NP)
         if model["kind"] == "abstract":
             return n, _ticked_pex(S, ts, model["Lg"], model["Ll"]) * waves
-        # Minimum: every map access is a global access, then element 0 folds the other
-        # min(WG, NP) - 1 local minima and writes the workgroup's minimum
-        return n, [model["Lg"]] * (ts * waves) + [model["Ll"]] * (min(wg, NP) - 1) + [model["Lg"]]
+        return n, _ticked_minimum(wg, ts, NP, model["Lg"], model["Ll"])
     if model["kind"] == "reduction":
         G, wg, ts = model["G"], row[0], row[1]
         local_steps = 0

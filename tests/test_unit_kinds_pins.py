@@ -7,8 +7,9 @@ What fixes them, other than the oracle itself:
   * Table 1's printed model times (tests/golden/table1_abstract.txt): the per-item
     operation lengths of the abstract pex and the wave count, with GMT = 4;
   * three derivations of the operation lists that share nothing: the oracle's
-    start-time bookkeeping, closed_form's formulas and brute's one-tick-at-a-time run
-    of long_work;
+    start-time bookkeeping, closed_form's formulas and brute's one-tick-at-a-time runs
+    (of long_work for the abstract pex; of the Minimum model's unit and elements, with
+    their relaunch bookkeeping, for the Minimum kind);
   * brute-force enumeration of every configuration x dispatch order on tiny models;
   * the closed-form round structure on the full paper-shaped workloads;
 and planted mistakes in a copy of the oracle must fail one of these.
@@ -63,6 +64,11 @@ def test_table1_rows_are_whole_workgroups(oracle_lib):
         assert row["T"] % d == 0, row
         quotients.append(row["T"] // d)
     assert quotients == [1, 1, 1, 1, 1, 33, 65, 33]
+    # every row runs 2*floor(S/(WG*NP)) + 1 workgroups of its printed (WG, TS): a count
+    # that fits all eight rows but that the printed host and device processes do not
+    # give (with one unit they run WGs + 1 workgroups per device activation and
+    # activate the device WGs + 1 times), so rows 6-8 pin the workgroup time only
+    assert quotients == [2 * (r["S"] // (r["WG"] * workloads.PAPER_NP)) + 1 for r in _table1()]
 
 
 def test_table1_fixes_gmt(oracle_lib):
@@ -221,6 +227,14 @@ UNIT_MUTANTS = {
     # the map costs one access per item, not TS
     "map_one_access": ("        for (uint64_t i = 0; i < TS; i++)",
                        "        for (uint64_t i = 0; i < 1; i++)"),
+    # element 0 folds the minima of all WG items, not of the min(WG, NP) elements
+    "reduce_wg_steps": ("    uint64_t nwe = WG < NP ? WG : NP;", "    uint64_t nwe = WG;"),
+    # the workgroup's minimum is never written to global memory
+    "write_dropped": ("    return ops_push(o, mo->Lg);                     /* the minimum to global memory */",
+                      "    return OR_OK;"),
+    # one MAP per workgroup instead of one per wave
+    "map_once_per_workgroup": ("    for (uint64_t w = 0; w < waves; w++)            /* MAP, wave by wave */",
+                               "    for (uint64_t w = 0; w < 1; w++)"),
 }
 
 
