@@ -111,6 +111,9 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
             "min_dups": st_min["dups"],
             "engine_ns": st_min["engine_ns"] + st_chk["engine_ns"],
             "engine_ns_min": st_min["engine_ns"], "seconds": t4 - t0, "levels": st_min["levels"],
+            "min_stats": {k: st_min[k] for k in ("probes", "max_probe", "dups", "edges",
+                                                 "supersteps", "batches", "critical_ns",
+                                                 "critical_cfg", "parts")},
             "parts": st_min["parts"],
             "breakdown_ms": {"load": 1e3 * (t1 - t0), "min_time": 1e3 * (t2 - t1),
                              "min_time_engine": st_min["engine_ns"] / 1e6,
@@ -642,6 +645,7 @@ def main():
         "step_breakdown_ms": {k: sum(s["breakdown_ms"][k] for s in steps) / len(steps)
                               for k in steps[0]["breakdown_ms"]},
         "partitions": steps[0]["parts"],
+        "min_time_stats": steps[-1]["min_stats"],
         "latency_ms": {"p50": 1e3 * pct(0.5), "p99": 1e3 * pct(0.99)},
         "roofline": roofline,
         "cpu_baseline": cpu,

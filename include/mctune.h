@@ -284,6 +284,23 @@ int mc_set_engine(mc_model *h, uint32_t engine);
  * harnesses) that must bound a query's time. */
 int mc_abort(mc_model *h);
 
+/* ---- min_time without allocation ------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mc_min_time of the descriptor d
+ * with its whole workspace in a static device array of MC_STATIC_SCRATCH_BYTES (one
+ * array per device, held from the first call on that device until the process ends).
+ * The call allocates no device or pinned memory and creates no event or stream: it
+ * loads d into the scratch, runs the query on `stream` (a hipStream_t, NULL = null
+ * stream), waits for it and returns the results as mc_min_time does (argmin, cap,
+ * n_argmin and st likewise; st's timings are host wall-clock only).  MC_E_NOMEM if
+ * mc_workspace_bytes(d, o) exceeds MC_STATIC_SCRATCH_BYTES, with nothing run.  Calls
+ * on one device share its array: calls that overlap on one device (from several host
+ * threads or streams) race and must not be made; successive calls are independent
+ * (each clears what it reads). */
+#define MC_STATIC_SCRATCH_BYTES (128u << 20)
+int mc_min_time_static(const mc_desc *d, const mc_opts *o, void *stream, uint32_t *t_min,
+                       uint32_t *argmin, size_t cap, size_t *n_argmin, mc_stats *st);
+
 /* Parameters of configuration cfg (4 values, as in the descriptor). */
 int mc_config(const mc_model *h, uint32_t cfg, uint32_t *params4);
 

@@ -146,6 +146,8 @@ _SIGS = {
     "mc_model_info_get": ([_vp, _P(McModelInfo)], ctypes.c_int),
     "mc_set_engine": ([_vp, ctypes.c_uint32], ctypes.c_int),
     "mc_abort": ([_vp], ctypes.c_int),
+    "mc_min_time_static": ([_P(McDesc), _P(McOpts), _vp, _u32p, _u32p, ctypes.c_size_t,
+                            _P(ctypes.c_size_t), _P(McStats)], ctypes.c_int),
     "mc_min_time": ([_vp, _u32p, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t), _P(McStats)],
                     ctypes.c_int),
     "mc_check": ([_vp, ctypes.c_uint32, _P(ctypes.c_int), _P(McStats)], ctypes.c_int),
@@ -268,6 +270,29 @@ def state_count(model: dict) -> int | None:
         return mc_describe(model)["states"]
     except McError:
         return None
+
+
+MC_STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def mc_min_time_static(model: dict, opts: McOpts | None = None, stream=None) -> tuple:
+    """min_time of a model in the library's static device scratch (no allocation):
+    (T_min, argmin list, stats dict).  stream: a torch stream (default: the current
+    stream of the current device)."""
+    import torch
+    d, keep = make_desc(model)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    t = ctypes.c_uint32()
+    n = ctypes.c_size_t()
+    st = McStats()
+    cap = len(model["params"])
+    arg = (ctypes.c_uint32 * cap)()
+    _check("mc_min_time_static",
+           _lib.mc_min_time_static(ctypes.byref(d), ctypes.byref(opts) if opts else None,
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(t), arg,
+                                   cap, ctypes.byref(n), ctypes.byref(st)))
+    return t.value, [int(arg[i]) for i in range(n.value)], st.as_dict()
 
 
 def mc_workspace_bytes(model: dict, opts: McOpts | None = None) -> int:

@@ -149,6 +149,14 @@ void host_decode(const Layout& L, const uint64_t* words, uint32_t* fields) {
     }                                  \
   } while (0)
 
+// Timing events are optional: a handle bound to the static scratch has none (it creates
+// no runtime objects), and its stats then carry host wall-clock times only.
+hipError_t ev_record(hipEvent_t e, hipStream_t s) { return e ? hipEventRecord(e, s) : hipSuccess; }
+hipError_t ev_ms(float* ms, hipEvent_t a, hipEvent_t b) {
+  *ms = 0.f;
+  return a && b ? hipEventElapsedTime(ms, a, b) : hipSuccess;
+}
+
 }  // namespace
 
 enum { kQueryNone = 0, kQueryMin = 1, kQueryCheck = 2 };
@@ -191,6 +199,9 @@ struct mc_model {
   uint64_t q_slots = 0;          // visited-set slots of the last query (a prefix of the table)
   bool trace_ready = false;
   std::vector<uint32_t> trace_rows;
+  // unpooled binding (the static scratch): host staging in ordinary memory, no events
+  bool pooled = true;
+  std::vector<unsigned char> host_stage;
 };
 
 namespace {
@@ -218,9 +229,9 @@ int explore_w(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   hipStream_t s = h->stream;
   HIPCHK(launch_seed<W>(s, q, h->seeds, h->front[0]));
   *launches = 1;
-  HIPCHK(hipEventRecord(h->ev[4], s));
+  HIPCHK(ev_record(h->ev[4], s));
   const int rc = level_loop<W>(h, q, launches);
-  HIPCHK(hipEventRecord(h->ev[5], s));
+  HIPCHK(ev_record(h->ev[5], s));
   return rc;
 }
 
@@ -278,9 +289,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   h->q_slots = q_slots;
   bool cleared = false;
   if (h->dirty) {
-    HIPCHK(hipEventRecord(h->ev[0], s));
+    HIPCHK(ev_record(h->ev[0], s));
     HIPCHK(launch_clear(s, h->table, h->q_slots * h->plan.slot_bytes));
-    HIPCHK(hipEventRecord(h->ev[1], s));
+    HIPCHK(ev_record(h->ev[1], s));
     cleared = true;
   }
   const QueryArgs q = make_args(h, prune, T);
@@ -304,9 +315,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     md.pstate = nullptr;
     HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
     HIPCHK(launch_reset_models(s, h->dmd, 1, h->head, 1));
-    HIPCHK(hipEventRecord(h->ev[2], s));
+    HIPCHK(ev_record(h->ev[2], s));
     HIPCHK(launch_seed_models(s, h->dmd, 1));
-    HIPCHK(hipEventRecord(h->ev[4], s));
+    HIPCHK(ev_record(h->ev[4], s));
     PartQueue pq;
     pq.models = h->dmd;
     pq.parts = h->parts;
@@ -323,11 +334,11 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     pq.abort = h->habort;
     const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
     HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general, h->mh.hetero));
-    HIPCHK(hipEventRecord(h->ev[5], s));
+    HIPCHK(ev_record(h->ev[5], s));
     launches = 2;
   } else {
     HIPCHK(launch_reset(s, h->ctrl, h->tc, h->mh.n_cfg));
-    HIPCHK(hipEventRecord(h->ev[2], s));
+    HIPCHK(ev_record(h->ev[2], s));
     switch (h->mh.W) {
       case 1: rc = explore_w<1>(h, q, &launches); break;
       case 2: rc = explore_w<2>(h, q, &launches); break;
@@ -339,17 +350,17 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     (void)hipStreamSynchronize(s);
     return rc;
   }
-  HIPCHK(hipEventRecord(h->ev[3], s));
+  HIPCHK(ev_record(h->ev[3], s));
   HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(h->tc_host, h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int derr = dev_error_code(h->hctrl->error);
-  if (derr == MC_E_ABORTED) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
+  if (derr == MC_E_ABORTED && h->habort) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
   if (derr != MC_OK) return derr;
   float ms_explore = 0.f, ms_clear = 0.f, ms_engine = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms_explore, h->ev[2], h->ev[3]));
-  HIPCHK(hipEventElapsedTime(&ms_engine, h->ev[4], h->ev[5]));
-  if (cleared) HIPCHK(hipEventElapsedTime(&ms_clear, h->ev[0], h->ev[1]));
+  HIPCHK(ev_ms(&ms_explore, h->ev[2], h->ev[3]));
+  HIPCHK(ev_ms(&ms_engine, h->ev[4], h->ev[5]));
+  if (cleared) HIPCHK(ev_ms(&ms_clear, h->ev[0], h->ev[1]));
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->states = h->hctrl->states;
@@ -490,19 +501,31 @@ int mc_workspace_bytes(const mc_desc* d, const mc_opts* o, size_t* bytes) {
 
 int mc_model_free(mc_model* h) {
   if (!h) return MC_E_INVAL;
-  for (auto& e : h->ev) event_put(e);
-  pinned_put(h->pin, h->pin_bytes);
+  if (h->pooled) {
+    for (auto& e : h->ev)
+      if (e) event_put(e);
+    if (h->pin) pinned_put(h->pin, h->pin_bytes);
+  }
   delete h;
   return MC_OK;
 }
 
-int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes, void* stream,
-                  mc_model** out) {
+}  // extern "C"
+
+namespace {
+
+// Builds a handle over a caller's workspace.  pooled: counters, descriptor and clocks
+// are staged in a pooled pinned block and the query is timed with pooled events (the
+// ordinary handle); otherwise they are staged in ordinary host memory and no runtime
+// object is created (the handle over the static scratch).
+int bind_model(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes, void* stream,
+               bool pooled, mc_model** out) {
   if (!out || !dev_ws) return MC_E_INVAL;
   *out = nullptr;
   mc_model* h = nullptr;
   try {
     h = new mc_model();
+    h->pooled = pooled;
     std::string err;
     int rc = build_model(d, &h->mh, &err);
     if (rc) {
@@ -540,37 +563,45 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     // the launch time, which 512 threads shorten; with many, 256 keeps more of them
     // resident
     if (!h->opts.block) h->opts.block = h->n_parts < kWideParts ? 512u : 256u;
-    // one pooled pinned block: counters, poll words, descriptor, clocks and, when small,
-    // the staging of the uploads below
-    static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "pinned block layout");
+    // one staging block: counters, poll words, descriptor, clocks and, when small, the
+    // staging of the uploads below
+    static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "staging block layout");
     const size_t tc_off = 768, up_off = align_up(tc_off + 4ull * h->mh.n_cfg);
     const size_t cfg_bytes = sizeof(CfgRec) * h->mh.n_cfg, part_bytes = sizeof(Part) * parts.size();
     const bool stage = cfg_bytes + part_bytes <= (4u << 20);
     h->pin_bytes = stage ? up_off + cfg_bytes + part_bytes : up_off;
-    h->pin = static_cast<unsigned char*>(pinned_get(h->pin_bytes));
-    bool ok = h->pin != nullptr;
-    for (auto& e : h->ev) {
-      e = event_get();
-      ok = ok && e != nullptr;
+    unsigned char* blk = nullptr;
+    if (pooled) {
+      h->pin = static_cast<unsigned char*>(pinned_get(h->pin_bytes));
+      bool ok = h->pin != nullptr;
+      for (auto& e : h->ev) {
+        e = event_get();
+        ok = ok && e != nullptr;
+      }
+      if (!ok) {
+        mc_model_free(h);
+        return MC_E_DEVICE;
+      }
+      blk = h->pin;
+    } else {
+      h->host_stage.assign(h->pin_bytes, 0);
+      blk = h->host_stage.data();
     }
-    if (!ok) {
-      mc_model_free(h);
-      return MC_E_DEVICE;
-    }
-    h->hctrl = reinterpret_cast<Ctrl*>(h->pin);
-    h->hpoll = reinterpret_cast<uint32_t*>(h->pin + 256);
-    h->habort = reinterpret_cast<unsigned int*>(h->pin + 256 + 128);
-    __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
-    h->hmd = reinterpret_cast<ModelDev*>(h->pin + 512);
-    h->tc_host = reinterpret_cast<uint32_t*>(h->pin + tc_off);
+    h->hctrl = reinterpret_cast<Ctrl*>(blk);
+    h->hpoll = reinterpret_cast<uint32_t*>(blk + 256);
+    // the stop request is a word the kernels read at system scope: pinned memory only
+    h->habort = pooled ? reinterpret_cast<unsigned int*>(blk + 256 + 128) : nullptr;
+    if (h->habort) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
+    h->hmd = reinterpret_cast<ModelDev*>(blk + 512);
+    h->tc_host = reinterpret_cast<uint32_t*>(blk + tc_off);
     for (uint32_t c = 0; c < h->mh.n_cfg; ++c) h->tc_host[c] = kNoClock;
     const void* up_cfg = h->mh.cfgs.data();
     const void* up_part = parts.data();
     if (stage) {
-      std::memcpy(h->pin + up_off, up_cfg, cfg_bytes);
-      std::memcpy(h->pin + up_off + cfg_bytes, up_part, part_bytes);
-      up_cfg = h->pin + up_off;
-      up_part = h->pin + up_off + cfg_bytes;
+      std::memcpy(blk + up_off, up_cfg, cfg_bytes);
+      std::memcpy(blk + up_off + cfg_bytes, up_part, part_bytes);
+      up_cfg = blk + up_off;
+      up_part = blk + up_off + cfg_bytes;
     }
     hipStream_t s = h->stream;
     if (hipMemcpyAsync(h->cfgs, up_cfg, cfg_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -590,6 +621,31 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
     if (h) mc_model_free(h);
     return MC_E_INVAL;
   }
+}
+
+}  // namespace
+
+namespace mc {
+
+int min_time_in_place(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes,
+                      void* stream, uint32_t* t_min, uint32_t* argmin, size_t cap,
+                      size_t* n_argmin, mc_stats* st) {
+  if (!t_min || !n_argmin) return MC_E_INVAL;
+  mc_model* h = nullptr;
+  int rc = bind_model(d, o, dev_ws, ws_bytes, stream, false, &h);
+  if (rc) return rc;
+  rc = mc_min_time(h, t_min, argmin, cap, n_argmin, st);
+  mc_model_free(h);
+  return rc;
+}
+
+}  // namespace mc
+
+extern "C" {
+
+int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes, void* stream,
+                  mc_model** out) {
+  return bind_model(d, o, dev_ws, ws_bytes, stream, true, out);
 }
 
 int mc_model_info_get(const mc_model* h, mc_model_info* info) {
@@ -807,15 +863,15 @@ int mc_swarm(mc_model* h, const mc_swarm_opts* o, mc_swarm_result* r) {
   h->swarm_best = false;
   const SwarmArgs a = swarm_args(h, *o, p);
   HIPCHK(hipMemsetAsync(a.bits, 0, p.total - p.bits, s));
-  HIPCHK(hipEventRecord(h->ev[4], s));
+  HIPCHK(ev_record(h->ev[4], s));
   HIPCHK(launch_swarm(s, a));
-  HIPCHK(hipEventRecord(h->ev[5], s));
+  HIPCHK(ev_record(h->ev[5], s));
   std::vector<SwarmMember> rec(o->members);
   HIPCHK(hipMemcpyAsync(rec.data(), a.out, sizeof(SwarmMember) * o->members,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, h->ev[4], h->ev[5]));
+  HIPCHK(ev_ms(&ms, h->ev[4], h->ev[5]));
   std::memset(r, 0, sizeof(*r));
   r->best_clock = r->first_clock = kNoClock;
   r->best_cfg = r->first_cfg = r->best_member = kParentNone;

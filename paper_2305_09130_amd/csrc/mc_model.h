@@ -121,9 +121,6 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
 // on models of m units.
 uint64_t auto_part_states(uint64_t states, uint32_t m = 2u);
 
-// An upper bound (exact for every configuration whose last round is not partial) on the
-// number of states with clock <= T, root included: what a check(T) inserts.  Sizes its
-// visited set only.
 // Operation ends of one workgroup of configuration r at or before time x.
 uint64_t ends_le(const CfgRec& r, uint64_t x);
 
@@ -137,9 +134,18 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
 // Time of the k-th operation end (0-based, k < r.b) of one workgroup.
 uint64_t end_at_host(const CfgRec& r, uint64_t k);
 
+// An upper bound (exact for every configuration whose last round is not partial) on the
+// number of states with clock <= T, root included: what a check(T) inserts.  Sizes its
+// visited set only.
 uint64_t count_le_bound(const ModelHost& h, uint64_t T);
 
 uint64_t binom(uint32_t n, uint32_t k);
 uint32_t bit_length(uint64_t x);
+
+// min_time of a descriptor over a caller's device workspace, with no pinned staging and
+// no runtime objects created (mc_api.hip): the query path of mc_min_time_static.
+int min_time_in_place(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes,
+                      void* stream, uint32_t* t_min, uint32_t* argmin, size_t cap,
+                      size_t* n_argmin, mc_stats* st);
 
 }  // namespace mc
