@@ -170,6 +170,16 @@ def cpu_baseline(model, t_min=None, sample_every: int = 1):
 BATCH_BUDGET = 1 << 20
 
 
+def named_workload(workloads, name: str) -> dict:
+    """A single-query workload by name: the three plain ones, the paper's unit models,
+    or the models on units of unequal speed."""
+    if name in workloads.WORKLOADS:
+        return workloads.WORKLOADS[name]()
+    if name in workloads.UNIT_WORKLOADS:
+        return workloads.UNIT_WORKLOADS[name]()
+    return workloads.hetero_workloads()[name]
+
+
 def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int):
     """The seeded mix of uneven instances explored in one persistent launch (hipGraph
     replay, autotuned options), against the same instances explored one at a time."""
@@ -234,9 +244,14 @@ def swarm_leg(mc, workloads, names, members: int = 16384, bits_log2: int = 16,
     (time to its first trail, that trail's optimality T_min / T_first), then the search
     loop with the over-time property; against the exact min_time on the same GPU."""
     out = {}
+    # the swarm's bit arrays and member records live in the visited-set region
+    need = members * ((1 << bits_log2) // 8 + 128)
     for name in names:
-        model = workloads.WORKLOADS[name]()
+        model = named_workload(workloads, name)
         g = mc.Model(model)
+        if g.mc_model_info_get()["slots"] * g.mc_model_info_get()["slot_bytes"] < need:
+            g.close()
+            g = mc.Model(model, log2_slots=max(10, (need // 16 - 1).bit_length()))
         t_min, _ = g.mc_min_time()
         exact_ms = g.last_stats["engine_ns"] / 1e6
         r = g.mc_swarm(members, bits_log2, budget, 1)
@@ -316,8 +331,7 @@ def bb_leg(mc, torch, workloads, names, reps: int = 5):
     synchronous) and the states each claimed."""
     out = {}
     for name in names:
-        make = workloads.WORKLOADS.get(name) or workloads.UNIT_WORKLOADS.get(name)
-        model = make() if make else workloads.hetero_workloads()[name]
+        model = named_workload(workloads, name)
         g = mc.Model(model)
         g.mc_min_time()
         g.mc_min_time_bb(0)
@@ -422,44 +436,64 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
             serve_one(*q)
             lat_fifo.append(time.perf_counter() - t0 - arr[k])
         fifo_wall = time.perf_counter() - t0
-        # continuous batching engine, driven in real time
-        e = mc.Engine(arena_bytes=24 << 30, max_active=128, max_cfg=512, block=512, slice=16)
-        tickets = []
-        t0 = time.perf_counter()
-        nxt = 0
-        busy = True
-        while nxt < n_queries or busy:
-            now = time.perf_counter() - t0
-            while nxt < n_queries and arr[nxt] <= now:
-                i, kind, T = qs[nxt]
-                tickets.append(e.mc_engine_submit(
-                    pool[i], mc.MC_QUERY_MIN_TIME if kind == "min_time" else mc.MC_QUERY_CHECK,
-                    T))
-                nxt += 1
-            a_, w_ = e.mc_engine_step()
-            busy = a_ + w_ > 0
-            if not busy and nxt < n_queries:
-                time.sleep(max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.001)))
-        e.drain()
-        wall = time.perf_counter() - t0
-        lat = []
-        base_ns = None
-        for k, t in enumerate(tickets):
-            r = e.mc_engine_poll(t)
-            assert r is not None and r["status"] == 0
-            if base_ns is None:
-                base_ns = r["submit_ns"] - int(arr[0] * 1e9)
-            lat.append((r["done_ns"] - base_ns) * 1e-9 - arr[k])
-        e.close()
-        torch.cuda.empty_cache()
-        out["runs"].append({
-            "qps_offered": qps, "factor": f, "queries_per_s": n_queries / wall,
-            "p50_ms": 1e3 * pct(lat, 0.5), "p99_ms": 1e3 * pct(lat, 0.99),
-            "fifo_p50_ms": 1e3 * pct(lat_fifo, 0.5), "fifo_p99_ms": 1e3 * pct(lat_fifo, 0.99),
-            "fifo_queries_per_s": n_queries / fifo_wall})
+        # continuous batching engine, driven in real time: with each model's state kept
+        # resident between its queries, and (at 1x) with every query explored afresh
+        run = {"qps_offered": qps, "factor": f,
+               "fifo_p50_ms": 1e3 * pct(lat_fifo, 0.5), "fifo_p99_ms": 1e3 * pct(lat_fifo, 0.99),
+               "fifo_queries_per_s": n_queries / fifo_wall}
+        for no_reuse in ((False, True) if f == 1.0 else (False,)):
+            r_ = serve_engine(mc, torch, pool, qs, arr, no_reuse)
+            if no_reuse:
+                run["no_reuse"] = r_
+            else:
+                run.update(r_)
+        out["runs"].append(run)
     del ws
     torch.cuda.empty_cache()
     return out
+
+
+def serve_engine(mc, torch, pool, qs, arr, no_reuse: bool) -> dict:
+    """Drives the engine in real time under the arrival stream `arr`; latency from
+    arrival to completion on the host's monotonic clock."""
+    n_queries = len(qs)
+    e = mc.Engine(arena_bytes=24 << 30, max_active=128, max_cfg=512, block=512, slice=16,
+                  no_reuse=no_reuse)
+    tickets = []
+    t0 = time.perf_counter()
+    nxt = 0
+    busy = True
+    while nxt < n_queries or busy:
+        now = time.perf_counter() - t0
+        while nxt < n_queries and arr[nxt] <= now:
+            i, kind, T = qs[nxt]
+            tickets.append(e.mc_engine_submit(
+                pool[i], mc.MC_QUERY_MIN_TIME if kind == "min_time" else mc.MC_QUERY_CHECK, T))
+            nxt += 1
+        a_, w_ = e.mc_engine_step()
+        busy = a_ + w_ > 0
+        if not busy and nxt < n_queries:
+            time.sleep(max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.001)))
+    e.drain()
+    wall = time.perf_counter() - t0
+    lat = []
+    base_ns = None
+    reuse = [0, 0, 0]
+    for k, t in enumerate(tickets):
+        r = e.mc_engine_poll(t)
+        assert r is not None and r["status"] == 0
+        reuse[r["reuse"]] += 1
+        if base_ns is None:
+            base_ns = r["submit_ns"] - int(arr[0] * 1e9)
+        lat.append((r["done_ns"] - base_ns) * 1e-9 - arr[k])
+    e.close()
+    torch.cuda.empty_cache()
+    lat.sort()
+    return {"queries_per_s": n_queries / wall,
+            "p50_ms": 1e3 * lat[min(len(lat) - 1, int(0.5 * len(lat)))],
+            "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+            "explored_fresh": reuse[0], "resumed": reuse[1], "answered_from_resident": reuse[2],
+            "hit_rate": (reuse[1] + reuse[2]) / n_queries}
 
 
 def peak_leg(buf_bytes: int) -> dict:
@@ -509,12 +543,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if args.workload in workloads.WORKLOADS:
-        model = workloads.WORKLOADS[args.workload]()
-    elif args.workload in workloads.UNIT_WORKLOADS:
-        model = workloads.UNIT_WORKLOADS[args.workload]()
-    else:
-        model = workloads.hetero_workloads()[args.workload]
+    model = named_workload(workloads, args.workload)
     nbytes = max(mc.mc_workspace_bytes(model, mc.make_opts(engine=e, block=args.block,
                                                           load_factor=args.load_factor))
                  for e in (0, 1))

@@ -265,7 +265,13 @@ int mc_simulate(mc_model *h, uint64_t seed, uint32_t *t_end, uint32_t *cfg);
 
 /* The search of Sec. 2 (Fig. 1) and Step 3: T_ini from mc_simulate(seed), then integer
  * bisection keeping check(lo) holding and check(hi) failing, lo = 0.  Returns T_min,
- * the number of check calls, and leaves the trace of the last failing check. */
+ * the number of check calls, and leaves the trace of the last failing check.  With the
+ * super-step engine on units that all work alike the checks share one visited set
+ * (sized for T_ini): a check at or below the largest threshold explored so far is
+ * answered from the per-configuration least clocks, a check above it continues that
+ * exploration instead of starting over (the repeated verifier runs that Sec. 8 names);
+ * st->states is then the number of states explored in all, once each.  Otherwise every
+ * check is a fresh mc_check and st->states sums their counts. */
 int mc_tune_bisect(mc_model *h, uint64_t seed, uint32_t *t_min, uint32_t *n_checks,
                    mc_stats *st);
 
@@ -417,16 +423,28 @@ int mc_batch_autotune(const mc_desc *models, uint32_t n, void *dev_ws, size_t ws
                       void *stream, mc_batch_opts *best, float *best_ms);
 
 /* ---- serving: continuous batching of queries ------------------------------------ */
-/* A query server over the persistent engine.  Queries (min_time or check(T) of a
- * model) are submitted at any time.  Each mc_engine_step:
- *   1. admits waiting queries in arrival order while their footprint (visited set,
- *      tables, saved frontiers) fits the engine's arena and a model slot is free;
+/* A query server over the persistent engine (Sec. 4 Steps 2-4 for each query).
+ * Queries (min_time or check(T) of a model) are submitted at any time.  Each model
+ * keeps its explored state on the device between queries: its visited set (sized for
+ * all its states), per-configuration least clocks and the threshold T_done up to which
+ * every state is in the set (min_time: all of them).  Each mc_engine_step:
+ *   1. admits waiting queries in arrival order.  A query on a model whose state is
+ *      resident and covers it (min_time after a min_time; check(T) with T <= T_done) is
+ *      answered from that state: its count by a scan of the set, no exploration.  A
+ *      check above T_done continues the exploration from the rounds that hold T_done
+ *      (units that all work alike; otherwise it starts over in the same memory).  A
+ *      model seen for the first time needs an arena region and a model slot: idle
+ *      models are evicted, least recently used first, to make room; a query that still
+ *      does not fit waits, and so do later queries needing new memory (queries on a
+ *      model whose previous query still runs wait for it without blocking others);
  *   2. runs one persistent launch over the unfinished partitions of every active
  *      query; while queries wait for admission, a partition explores at most `slice`
  *      super-step levels, then saves its frontier and yields;
- *   3. retires the queries whose partitions are all explored, freeing their memory.
+ *   3. retires the queries whose partitions are all explored.
  * Queries admitted later therefore share the device with queries already running.
- * Every query owns its visited set, so its result is the same alone and in the mix. */
+ * Each model has its own visited set and every count is that of the query's threshold,
+ * so a result is the same alone, in the mix, resumed or answered from resident state
+ * (`levels` excepted: 0 when answered from resident state without exploring). */
 #define MC_QUERY_MIN_TIME 0u
 #define MC_QUERY_CHECK 1u
 
@@ -449,7 +467,10 @@ typedef struct mc_engine_opts {
                                 are cut into blocks of whole rounds (0 = automatic: about
                                 states/256, at most 256 more partitions than
                                 configurations; UINT32_MAX = never cut) */
-    uint32_t reserved[3];
+    uint32_t no_reuse;       /* 1: free a model's state when its query retires (every
+                                query explores from scratch, in a visited set sized for
+                                its own threshold); 0: keep it (the default) */
+    uint32_t reserved[2];
 } mc_engine_opts;
 
 typedef struct mc_query_result {
@@ -464,8 +485,12 @@ typedef struct mc_query_result {
     uint64_t levels;         /* BFS levels */
     uint64_t submit_ns, admit_ns, done_ns;  /* host monotonic clock */
     uint32_t steps;          /* engine steps the query was active */
-    uint32_t pad;
+    uint32_t reuse;          /* MC_REUSE_*: how the model's resident state served it */
 } mc_query_result;
+
+#define MC_REUSE_NONE 0u     /* explored from scratch */
+#define MC_REUSE_RESUMED 1u  /* continued the model's resident exploration */
+#define MC_REUSE_ANSWERED 2u /* answered from the resident state without exploring */
 
 /* Device bytes for an engine whose query arena holds arena_bytes. */
 int mc_engine_bytes(const mc_engine_opts *o, size_t arena_bytes, size_t *bytes);
@@ -483,6 +508,17 @@ int mc_engine_submit(mc_engine *e, const mc_desc *model, uint32_t kind, uint32_t
 int mc_engine_step(mc_engine *e, uint32_t *n_active, uint32_t *n_waiting);
 /* Result of a ticket: MC_OK when done, MC_E_STATE while pending, MC_E_NOTFOUND. */
 int mc_engine_poll(mc_engine *e, uint64_t ticket, mc_query_result *out);
+/* The configurations attaining a finished query's t_min, ascending (Sec. 4 Step 4; as
+ * mc_min_time's argmin): argmin may be NULL with cap 0 to query *n; MC_E_BUFFER if
+ * cap < *n (the first cap are written).  MC_E_STATE while pending, MC_E_NOTFOUND. */
+int mc_engine_argmin(mc_engine *e, uint64_t ticket, uint32_t *argmin, size_t cap, size_t *n);
+/* Counterexample of a finished query whose t_min exists: a path from the root to a
+ * terminal of its smallest argmin configuration at clock t_min, rows as mc_trace.  It is
+ * read from the model's visited set, so the model's state must still be resident and
+ * idle: MC_E_STATE otherwise (evicted, freed with no_reuse, or a later query on the
+ * model running), or when the query has no terminal; MC_E_BUFFER if cap < *len;
+ * MC_E_NOMEM if the arena has no room for the path's staging. */
+int mc_engine_trace(mc_engine *e, uint64_t ticket, uint32_t *rows, size_t cap, size_t *len);
 /* Forget a finished ticket. */
 int mc_engine_release(mc_engine *e, uint64_t ticket);
 int mc_engine_destroy(mc_engine *e);

@@ -21,6 +21,7 @@ MC_OK = 0
 MC_E_INVAL, MC_E_NOMEM, MC_E_DEVICE, MC_E_TABLE_FULL = -1, -2, -3, -4
 MC_E_BUFFER, MC_E_STATE, MC_E_OVERFLOW, MC_E_ADMIT, MC_E_NOTFOUND = -5, -6, -7, -8, -9
 MC_E_INTERNAL, MC_E_ABORTED = -10, -11
+MC_REUSE_NONE, MC_REUSE_RESUMED, MC_REUSE_ANSWERED = 0, 1, 2
 NEVER_CUT = 0xFFFFFFFF
 MC_KIND_REDUCTION, MC_KIND_MATMUL, MC_KIND_ABSTRACT, MC_KIND_MINIMUM = 0, 1, 2, 3
 MC_ENGINE_SUPERSTEP, MC_ENGINE_LEVEL = 0, 1
@@ -87,7 +88,8 @@ class McEngineOpts(ctypes.Structure):
                 ("block", ctypes.c_uint32), ("slice", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("load_factor", ctypes.c_float), ("lane_items", ctypes.c_uint32),
-                ("part_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("part_states", ctypes.c_uint32), ("no_reuse", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class McSwarmOpts(ctypes.Structure):
@@ -127,7 +129,7 @@ class McQueryResult(ctypes.Structure):
                 ("states", ctypes.c_uint64), ("levels", ctypes.c_uint64),
                 ("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
                 ("done_ns", ctypes.c_uint64), ("steps", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("reuse", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "pad"}
@@ -173,6 +175,10 @@ _SIGS = {
                          ctypes.c_int),
     "mc_engine_step": ([_vp, _u32p, _u32p], ctypes.c_int),
     "mc_engine_poll": ([_vp, ctypes.c_uint64, _P(McQueryResult)], ctypes.c_int),
+    "mc_engine_argmin": ([_vp, ctypes.c_uint64, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t)],
+                         ctypes.c_int),
+    "mc_engine_trace": ([_vp, ctypes.c_uint64, _u32p, ctypes.c_size_t, _P(ctypes.c_size_t)],
+                        ctypes.c_int),
     "mc_engine_release": ([_vp, ctypes.c_uint64], ctypes.c_int),
     "mc_engine_destroy": ([_vp], ctypes.c_int),
     "mc_swarm": ([_vp, _P(McSwarmOpts), _P(McSwarmResult)], ctypes.c_int),
@@ -570,12 +576,13 @@ class Engine:
     def __init__(self, arena_bytes: int, max_active: int = 64, max_cfg: int = 512,
                  block: int = 512, slice: int = 16, chunk: int = 0, grid: int = 0,
                  load_factor: float = 0.5, device: str = "cuda:0", stream=None,
-                 lane_items: int = 0, part_states: int = 0):
+                 lane_items: int = 0, part_states: int = 0, no_reuse: bool = False):
         import torch
         o = McEngineOpts()
         o.max_active, o.max_cfg, o.block, o.slice = max_active, max_cfg, block, slice
         o.chunk, o.grid, o.load_factor = chunk, grid, load_factor
         o.lane_items, o.part_states = lane_items, part_states
+        o.no_reuse = 1 if no_reuse else 0
         self._o = o
         n = ctypes.c_size_t()
         _check("mc_engine_bytes", _lib.mc_engine_bytes(ctypes.byref(o), arena_bytes,
@@ -618,6 +625,27 @@ class Engine:
             return None
         _check("mc_engine_poll", rc)
         return r.as_dict()
+
+    def mc_engine_argmin(self, ticket: int) -> list[int]:
+        n = ctypes.c_size_t()
+        _check("mc_engine_argmin", _lib.mc_engine_argmin(self._h, ticket, None, 0,
+                                                         ctypes.byref(n)))
+        out = (ctypes.c_uint32 * max(1, n.value))()
+        _check("mc_engine_argmin", _lib.mc_engine_argmin(self._h, ticket, out, n.value,
+                                                         ctypes.byref(n)))
+        return [int(out[i]) for i in range(n.value)]
+
+    def mc_engine_trace(self, ticket: int, m: int) -> np.ndarray:
+        """Counterexample rows (cfg, clock, pending, rem...) root first, as mc_trace;
+        m = the model's unit count."""
+        n = ctypes.c_size_t()
+        _check("mc_engine_trace", _lib.mc_engine_trace(self._h, ticket, None, 0,
+                                                       ctypes.byref(n)))
+        rows = np.zeros((max(1, n.value), 3 + m), dtype=np.uint32)
+        _check("mc_engine_trace", _lib.mc_engine_trace(self._h, ticket,
+                                                       rows.ctypes.data_as(_u32p), n.value,
+                                                       ctypes.byref(n)))
+        return rows[:n.value]
 
     def mc_engine_release(self, ticket: int) -> None:
         _check("mc_engine_release", _lib.mc_engine_release(self._h, ticket))

@@ -43,7 +43,7 @@ def _compile(unit: tuple[str, int | None], outdir: str, verbose: bool) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *DEV, *extra, "-x", "hip", "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, *extra, "-c", path, "-o", obj]
+        cmd = [HIPCC, *COMMON, *DEV, *extra, "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -108,38 +108,6 @@ std::vector<Part> model_parts(const ModelHost& mh, const mc_opts& o) {
   return parts;
 }
 
-// fields: cfg, pending, clock, then the time left on every unit (packed as a busy mask
-// and one shared time when the layout says so)
-void host_encode(const Layout& L, const uint32_t* fields, uint64_t* words) {
-  for (int j = 0; j < 4; ++j) words[j] = 0;
-  uint32_t packed[kFields];
-  for (int f = 0; f < 3 + L.m; ++f) packed[f] = fields[f];
-  int nf = 3 + L.m;
-  if (L.shared_rem) {
-    uint32_t mask = 0, rem = 0;
-    for (int u = 0; u < L.m; ++u)
-      if (fields[kFRem + u]) {
-        mask |= 1u << u;
-        rem = fields[kFRem + u];
-      }
-    packed[kFRem] = mask;
-    packed[kFRem + 1] = rem;
-    nf = 5;
-  }
-  for (int f = 0; f < nf; ++f) words[L.word[f]] |= (uint64_t)packed[f] << L.shift[f];
-}
-
-void host_decode(const Layout& L, const uint64_t* words, uint32_t* fields) {
-  const int nf = L.shared_rem ? 5 : 3 + L.m;
-  for (int f = 0; f < nf; ++f)
-    fields[f] = (uint32_t)((words[L.word[f]] >> L.shift[f]) & ((1ull << L.width[f]) - 1ull));
-  if (L.shared_rem) {
-    const uint32_t mask = fields[kFRem], rem = fields[kFRem + 1];
-    for (int u = 0; u < L.m; ++u) fields[kFRem + u] = ((mask >> u) & 1u) ? rem : 0u;
-  }
-}
-
-
 #define HIPCHK(x)                      \
   do {                                 \
     hipError_t e_ = (x);               \
@@ -199,6 +167,12 @@ struct mc_model {
   uint64_t q_slots = 0;          // visited-set slots of the last query (a prefix of the table)
   bool trace_ready = false;
   std::vector<uint32_t> trace_rows;
+  // the visited set holds every state with clock <= resident_T (an incremental
+  // bisection's pruned exploration), which run_resume continues
+  bool resident = false;
+  uint32_t resident_T = 0;
+  std::vector<Part> parts_host;  // the load's partition plan (run_resume overwrites parts)
+  bool parts_resumed = false;
   // unpooled binding (the static scratch): host staging in ordinary memory, no events
   bool pooled = true;
   std::vector<unsigned char> host_stage;
@@ -267,10 +241,14 @@ int level_loop(mc_model* h, const QueryArgs& q, uint64_t* launches) {
   return MC_OK;
 }
 
+int finish_query(mc_model* h, std::chrono::steady_clock::time_point t0, bool cleared,
+                 uint64_t launches, mc_stats* st);
+
 // prune: drop states with clock > T.  bb (super-step engine): branch and bound, the
 // threshold falls to the least terminal clock found so far and partitions are taken
 // smallest first.
-int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false) {
+int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false,
+              uint32_t T_size = 0) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = h->stream;
   h->trace_ready = false;
@@ -282,11 +260,17 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   if (prune && !h->opts.log2_slots) {
     const double lf =
         (h->opts.load_factor > 0.f && h->opts.load_factor < 1.f) ? h->opts.load_factor : 0.5;
-    const uint64_t need = count_le_bound(h->mh, T);
+    const uint64_t need = count_le_bound(h->mh, std::max(T, T_size));
     q_slots = std::min<uint64_t>(
         h->plan.slots, std::max<uint64_t>(1024, next_pow2((uint64_t)((double)need / lf) + 1)));
   }
   h->q_slots = q_slots;
+  h->resident = false;
+  if (h->parts_resumed) {
+    HIPCHK(hipMemcpyAsync(h->parts, h->parts_host.data(), sizeof(Part) * h->parts_host.size(),
+                          hipMemcpyHostToDevice, s));
+    h->parts_resumed = false;
+  }
   bool cleared = false;
   if (h->dirty) {
     HIPCHK(ev_record(h->ev[0], s));
@@ -350,6 +334,13 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     (void)hipStreamSynchronize(s);
     return rc;
   }
+  return finish_query(h, t0, cleared, launches, st);
+}
+
+// Waits for a query's launches and reads its counters and clocks back.
+int finish_query(mc_model* h, std::chrono::steady_clock::time_point t0, bool cleared,
+                 uint64_t launches, mc_stats* st) {
+  hipStream_t s = h->stream;
   HIPCHK(ev_record(h->ev[3], s));
   HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(h->tc_host, h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
@@ -386,6 +377,59 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   return MC_OK;
 }
 
+// Continues the last pruned exploration (every state with clock <= h->resident_T is in
+// the visited set) up to T > resident_T on the same set: no clear, no seeding; each
+// configuration not yet at its terminals is re-explored from the start of the round
+// holding resident_T.  Counters and clocks accumulate, so the result is that of
+// check(T).  Super-step engine and resumable models only (the caller checks).
+int run_resume(mc_model* h, uint32_t T, mc_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = h->stream;
+  h->trace_ready = false;
+  h->last = kQueryNone;
+  std::vector<PartPlan> plan;
+  plan_resume(h->mh, h->resident_T, &plan);
+  std::vector<Part> parts(plan.size());
+  for (size_t i = 0; i < plan.size(); ++i)
+    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1, (uint32_t)i, 0u, 0u, 0u};
+  h->parts_resumed = true;
+  if (!parts.empty())
+    HIPCHK(hipMemcpyAsync(h->parts, parts.data(), sizeof(Part) * parts.size(),
+                          hipMemcpyHostToDevice, s));
+  ModelDev& md = *h->hmd;
+  md.prune = 1u;
+  md.T = T;
+  md.bb = 0u;
+  md.n_parts = (uint32_t)parts.size();
+  HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_resume_models(s, h->dmd, 1, h->head, 1));
+  HIPCHK(ev_record(h->ev[2], s));
+  HIPCHK(ev_record(h->ev[4], s));
+  uint64_t launches = 1;
+  if (!parts.empty()) {
+    PartQueue pq;
+    pq.models = h->dmd;
+    pq.parts = h->parts;
+    pq.n_parts = (uint32_t)parts.size();
+    const uint32_t li = lane_items_for(h->opts.lane_items, h->mh.W);
+    pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
+    pq.head = h->head;
+    pq.slice = 0u;
+    pq.reverse = 0u;
+    pq.yielded = nullptr;
+    pq.n_yielded = nullptr;
+    pq.abort = h->habort;
+    const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(pq.n_parts, 4096u);
+    HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general, h->mh.hetero));
+    ++launches;
+  }
+  HIPCHK(ev_record(h->ev[5], s));
+  const int rc = finish_query(h, t0, false, launches, st);
+  if (rc == MC_OK) h->resident_T = T;
+  else h->resident = false;
+  return rc;
+}
+
 template <int W>
 int trace_w(mc_model* h, uint32_t cfg, uint32_t clock) {
   hipStream_t s = h->stream;
@@ -393,7 +437,7 @@ int trace_w(mc_model* h, uint32_t cfg, uint32_t clock) {
   fields[kFCfg] = cfg;
   fields[kFClock] = clock;
   uint64_t words[4];
-  host_encode(h->mh.layout, fields, words);
+  encode_key_host(h->mh.layout, fields, words);
   const QueryArgs q = make_args(h, false, 0);
   HIPCHK(launch_find<W>(s, q, reinterpret_cast<const unsigned long long*>(words)));
   HIPCHK(launch_chase<W>(s, q, h->trace_buf, (uint32_t)h->plan.trace_cap));
@@ -412,7 +456,7 @@ int trace_w(mc_model* h, uint32_t cfg, uint32_t clock) {
     uint64_t w[4] = {0, 0, 0, 0};
     for (int j = 0; j < W; ++j) w[j] = keys[(size_t)(n - 1 - i) * W + j];
     uint32_t f[kFields];
-    host_decode(h->mh.layout, w, f);
+    decode_key_host(h->mh.layout, w, f, h->mh.cfgs.data());
     uint32_t* row = &h->trace_rows[(size_t)i * S];
     row[0] = f[kFCfg] == h->mh.n_cfg ? 0xFFFFFFFFu : f[kFCfg];
     row[1] = f[kFClock];
@@ -556,7 +600,8 @@ int bind_model(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes
     h->trace_buf = reinterpret_cast<unsigned long long*>(h->ws + h->plan.trace);
     h->table = h->ws + h->plan.table;
     h->q_slots = h->plan.slots;
-    const std::vector<Part> parts = model_parts(h->mh, h->opts);
+    h->parts_host = model_parts(h->mh, h->opts);
+    const std::vector<Part>& parts = h->parts_host;
     h->n_parts = (uint32_t)parts.size();
     // automatic workgroup size: with fewer partitions than a wide launch has workgroups,
     // each runs nearly alone on its compute unit and its chain of insert round trips is
@@ -977,6 +1022,40 @@ int mc_swarm_trace(mc_model* h, uint32_t* rows, size_t cap, size_t* len) {
   return MC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// check(T) inside an incremental bisection: the visited set is kept from check to check
+// and holds every state with clock <= h->resident_T.  A check at or below that is
+// answered from the per-configuration least clocks (a terminal with clock <= T is one of
+// them); a check above it continues the exploration (run_resume).  The first check sizes
+// the set for T_size, the largest threshold the bisection can reach.
+int inc_check(mc_model* h, uint32_t T, uint32_t T_size, int* violated, mc_stats* st) {
+  if (st) std::memset(st, 0, sizeof(*st));
+  int rc = MC_OK;
+  if (!h->resident) {
+    rc = run_query(h, true, T, st, false, T_size);
+    if (rc) return rc;
+    h->resident = true;
+    h->resident_T = T;
+  } else if (T > h->resident_T) {
+    rc = run_resume(h, T, st);
+    if (rc) return rc;
+  }
+  uint32_t best = kNoClock;
+  for (uint32_t c = 0; c < h->mh.n_cfg; ++c) best = std::min(best, h->tc_host[c]);
+  *violated = best <= T ? 1 : 0;
+  h->last = kQueryCheck;
+  h->last_T = T;
+  h->last_violated = *violated;
+  return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mc_tune_bisect(mc_model* h, uint64_t seed, uint32_t* t_min, uint32_t* n_checks, mc_stats* st) {
   if (!h || !t_min || !n_checks) return MC_E_INVAL;
   uint32_t t_ini = 0, c0 = 0;
@@ -985,31 +1064,37 @@ int mc_tune_bisect(mc_model* h, uint64_t seed, uint32_t* t_min, uint32_t* n_chec
   mc_stats acc;
   std::memset(&acc, 0, sizeof(acc));
   mc_stats one;
+  // one visited set for the whole bisection where the exploration can be continued
+  const bool inc = h->opts.engine == MC_ENGINE_SUPERSTEP && resumable(h->mh);
+  h->resident = false;
   // check(lo) holds (clock >= 1 at every terminal), check(hi) fails (the simulated run)
   uint32_t lo = 0, hi = t_ini, n = 0;
   int last_violated = -1;
   while (hi - lo > 1) {
     const uint32_t mid = lo + (hi - lo) / 2;
     int v = 0;
-    rc = mc_check(h, mid, &v, &one);
+    rc = inc ? inc_check(h, mid, t_ini, &v, &one) : mc_check(h, mid, &v, &one);
     if (rc) return rc;
     ++n;
     acc.explore_ns += one.explore_ns;
     acc.clear_ns += one.clear_ns;
     acc.engine_ns += one.engine_ns;
     acc.launches += one.launches;
-    acc.states += one.states;
+    // an incremental bisection's counters run on: its states are the last total
+    if (inc) acc.states = std::max<uint64_t>(acc.states, one.states);
+    else acc.states += one.states;
     if (v) hi = mid;
     else lo = mid;
     last_violated = v;
   }
   if (last_violated != 1) {  // leave the counterexample of check(T_min) behind
     int v = 0;
-    rc = mc_check(h, hi, &v, &one);
+    rc = inc ? inc_check(h, hi, t_ini, &v, &one) : mc_check(h, hi, &v, &one);
     if (rc) return rc;
     acc.explore_ns += one.explore_ns;
     acc.clear_ns += one.clear_ns;
     acc.launches += one.launches;
+    if (inc) acc.states = std::max<uint64_t>(acc.states, one.states);
     if (!v) return MC_E_STATE;
   }
   *t_min = hi;

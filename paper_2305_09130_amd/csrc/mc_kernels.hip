@@ -178,7 +178,7 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
       Key<W> k;
 #pragma unroll
       for (int j = 0; j < W; ++j) k.w[j] = e.k[j];
-      x = decode<W>(k, q.L);
+      x = decode<W>(k, q.L, q.cfgs);
       pslot = e.slot;
       pdepth = e.depth;
       r = q.cfgs[x.cfg];
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
           *slot_parent<W>(q.table, slot) = s_par[t];
           ++n_states;
           depth_max = dep > depth_max ? dep : depth_max;
-          const St y = decode<W>(k, q.L);
+          const St y = decode<W>(k, q.L, q.cfgs);
           term = is_terminal(y, m);
           if (term) {
             ++n_terms;
@@ -349,6 +349,9 @@ struct SuperShared {
   uint32_t fcount[2];
   uint32_t part, carry, stop, nseg, total;
   uint32_t skip;        // the partition is not explored (an error, or an abort from the host)
+  // a chain slice of units of unequal speed ends at clock `cut` (kNoClock: no cut);
+  // `pr` = states past T are dropped (a check, branch and bound, or a cut)
+  uint32_t cut, pr;
   uint32_t chain_more;  // another chain joined the batch: list it
   // end of a block of rounds: the state B_r1, its clock and depth, the batch item that
   // generates it, and whether it was reached
@@ -374,6 +377,7 @@ struct Tally {
 template <int W>
 __device__ __forceinline__ void field_add(unsigned long long* k, const Layout& L, int f,
                                           unsigned long long v) {
+  if (L.width[f] == 0) return;  // a field the key does not store (an implied clock)
   const unsigned long long x = v << L.shift[f];
   const int wf = L.word[f];
 #pragma unroll
@@ -427,7 +431,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
         Key<W> fk;
 #pragma unroll
         for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
-        St y = decode<W>(fk, L);
+        St y = decode<W>(fk, L, md.cfgs);
         uint32_t t = 0;
 #pragma unroll
         for (int u = 0; u < kMaxCU; ++u) {
@@ -502,7 +506,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
     Key<W> fk;
 #pragma unroll
     for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
-    St y = decode<W>(fk, L);
+    St y = decode<W>(fk, L, md.cfgs);
     const uint32_t tau = sh.E[kChainTimes + sg.idx0 + it.j], dt = tau - y.clock;
 #pragma unroll
     for (int u = 0; u < kMaxCU; ++u) y.rem[u] = y.rem[u] > dt ? y.rem[u] - dt : 0u;
@@ -522,7 +526,7 @@ __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t ns
       for (int w = 0; w < W; ++w) it.key[w] = sh.gkey[leaf][w];
     }
   }
-  if (md.prune && it.clk > sh.T) it.active = false;
+  if (sh.pr && it.clk > sh.T) it.active = false;
 }
 
 __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl);
@@ -544,7 +548,7 @@ __device__ __noinline__ void build_chain(SuperShared<BLOCK, NI, SEGS>& sh, const
   Key<W> fk;
 #pragma unroll
   for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
-  const St x = decode<W>(fk, L);
+  const St x = decode<W>(fk, L, nullptr)  /* unequal units store the clock */;
   uint32_t H = 0xFFFFFFFFu;  // with work pending the chain stops at the first workgroup end
   if (x.pending)
     for (int u = 0; u < m; ++u)
@@ -677,11 +681,11 @@ __device__ __noinline__ void extend_chain(SuperShared<BLOCK, NI, SEGS>& sh, cons
       off + (uint32_t)kChainCand > (uint32_t)(kEMax - kChainTimes))
     return;
   const uint32_t tau = sh.E[kChainTimes + off - 1u];
-  if ((md.prune && tau > sh.T) || tau > md.max_clock) return;
+  if ((sh.pr && tau > sh.T) || tau > md.max_clock) return;
   Key<W> fk;
 #pragma unroll
   for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
-  St y = decode<W>(fk, L);
+  St y = decode<W>(fk, L, md.cfgs);
   const uint32_t dt = tau - y.clock;
   uint32_t freem = 0;
 #pragma unroll
@@ -781,15 +785,18 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
   const bool e_lds = r.b <= (uint32_t)kEMax;
   if (e_lds)
     for (uint32_t k = tid; k < r.b; k += BLOCK) sh.E[k] = end_at_t<GEN>(r, k);
+  const bool chain_slice = HET && pt.r0 == kChainSlice;
   if (tid == 0) {
     sh.has_stop = 0u;
     sh.handed = 0u;
     sh.stop_capped = 0u;
     sh.stop_item = kNoItem;
-    sh.T = prune_T(md);
+    sh.cut = chain_slice ? pt.r1 : kNoClock;
+    sh.pr = (md.prune || sh.cut != kNoClock) ? 1u : 0u;
+    sh.T = min(prune_T(md), sh.cut);
     const Seed sd = md.seeds[c];
     const uint32_t round_dep = (uint32_t)m + r.b;  // m dispatches, b advances
-    if (pt.r1 != kRoundsToEnd) {
+    if (!chain_slice && pt.r1 != kRoundsToEnd) {
       unsigned long long k1[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) k1[w] = sd.k[w];
@@ -814,7 +821,41 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
       for (int w = 0; w < W; ++w) k0[w] = sd.k[w];
       uint32_t slot0 = sd.slot, dep0 = sd.depth;
       sh.fcount[0] = sd.slot == kParentNone ? 0u : 1u;
-      if (pt.r0 != 0u && sh.fcount[0]) {
+      if (chain_slice && pt.j0 != 0u && sh.fcount[0]) {
+        // a chain slice after the first starts at clock j0 of the configuration's
+        // determined part, an instant at which no workgroup ends: every unit has run
+        // workgroups back to back since clock 0, so unit u is in its floor(j0/(s_u d))-th
+        // workgroup; the slice before ends on the same state
+        St x{};
+        x.cfg = c;
+        x.clock = pt.j0;
+        uint32_t started = 0;
+#pragma unroll
+        for (int u = 0; u < kMaxCU; ++u) {
+          if (u < m) {
+            const uint32_t per = unit_dur<GEN>(r, L.speed, u), w = pt.j0 / per;
+            x.rem[u] = (w + 1u) * per - pt.j0;
+            started += w + 1u;
+          }
+        }
+        x.pending = r.n - started;
+        dep0 = pt.j1;
+        if (sh.pr && pt.j0 > sh.T) {
+          sh.fcount[0] = 0u;
+        } else {
+          const Key<W> k = encode<W>(x, L);
+#pragma unroll
+          for (int w = 0; w < W; ++w) k0[w] = k.w[w];
+          const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot0, tl.probes);
+          if (res == kInsFail) {
+            set_error(md.ctrl, kDevErrTableFull);
+            sh.fcount[0] = 0u;
+          } else if (res == kInsNew) {
+            ++tl.states;
+            tl.depth = dep0 > tl.depth ? dep0 : tl.depth;
+          }
+        }
+      } else if (!chain_slice && pt.r0 != 0u && sh.fcount[0]) {
         // B_r0: r0 full rounds after the configuration's SELECT state
         field_add<W>(k0, L, kFClock, (unsigned long long)pt.r0 * r.d);
         field_add<W>(k0, L, kFPending, (unsigned long long)(-(long long)pt.r0 * m));
@@ -869,7 +910,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     for (uint32_t fi = 0; fi < nf; ++fi) {
       // ---- segments of this super-step (one thread builds them) ----
       if (tid == 0) {
-        sh.T = prune_T(md);
+        sh.T = min(prune_T(md), sh.cut);
         Key<W> ck;
 #pragma unroll
         for (int w = 0; w < W; ++w) ck.w[w] = sh.fkey[cur][fi][w];
@@ -881,7 +922,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         for (;;) {
           SegDesc& sg = sh.seg[nseg];
           if (!decoded) {
-            const St x = decode<W>(ck, L);
+            const St x = decode<W>(ck, L, md.cfgs);
             uint32_t freem = 0, busy = 0, brem = 0;
             bool bsame = true;
 #pragma unroll
@@ -963,7 +1004,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             Key<W> lk;
 #pragma unroll
             for (int w = 0; w < W; ++w) lk.w[w] = sg.fkey[w];
-            St y = decode<W>(lk, L);
+            St y = decode<W>(lk, L, md.cfgs);
 #pragma unroll
             for (int u = 0; u < kMaxCU; ++u)
               if ((sg.freem >> u) & 1u) y.rem[u] = unit_dur<GEN>(r, L.speed, u);
@@ -1021,7 +1062,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
               if (!ok) {
                 set_error(md.ctrl, kDevErrSplit);
                 sh.stop = 1u;
-              } else if (!(md.prune && end_clock > sh.T)) {
+              } else if (!(sh.pr && end_clock > sh.T)) {
                 // shared with the next block: agent-scope ordering
                 uint32_t slot = kParentNone;
                 const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, tl.probes);
@@ -1045,7 +1086,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           }
           const bool more = sg.lock && sg.nleaf == 1u && sg.pend > 0u &&
                             nseg < (uint32_t)SEGS && total < batch_items &&
-                            !(md.prune && end_clock > sh.T) && end_clock <= md.max_clock;
+                            !(sh.pr && end_clock > sh.T) && end_clock <= md.max_clock;
           if (!more) break;
           // the run end: every unit idle, `pend` workgroups pending
           unsigned long long ek[W];
@@ -1119,7 +1160,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           Key<W> fk;
 #pragma unroll
           for (int w = 0; w < W; ++w) fk.w[w] = sg.fkey[w];
-          St y = decode<W>(fk, L);
+          St y = decode<W>(fk, L, md.cfgs);
           uint32_t t = 0;
 #pragma unroll
           for (int u = 0; u < kMaxCU; ++u) {
@@ -1158,9 +1199,14 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         uint32_t slot[NI];
         int res[NI];
         const uint32_t p0 = tl.probes;
-        table_insert_n<W, kScopeWG, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+        // a chain slice shares its last state with the next slice's workgroup: its
+        // inserts are at device scope
+        if (chain_slice)
+          table_insert_n<W, kScopeAgent, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+        else
+          table_insert_n<W, kScopeWG, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
         tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
-        bool fresh[NI];
+        bool fresh[NI], cutlink[NI];
         Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
@@ -1168,6 +1214,9 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
                                         e_lds, md, m, it[n]);
           it[n].active = act[n];
           fresh[n] = false;
+          // the state a chain slice ends on gets its parent from this slice even when
+          // the next slice, which knows only its key, inserted it first
+          cutlink[n] = chain_slice && act[n] && res[n] == kInsDup && it[n].clk == sh.cut;
           if (it[n].active) {
             ++tl.edges;
             if (res[n] == kInsFail) {
@@ -1204,7 +1253,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         __syncthreads();
 #pragma unroll
         for (int n = 0; n < NI; ++n) {
-          if (!fresh[n]) continue;
+          if (!fresh[n] && !cutlink[n]) continue;
           const Item<W>& x = it[n];
           const SegDesc& sg = sh.seg[x.sgi];
           const uint32_t segf = x.sgi ? sh.segfslot[x.sgi] : sg.fslot;
@@ -1225,6 +1274,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             *slot_parent<W>(md.table, slot[n]) = par;
             if (jmp != kParentNone) *slot_jump<W>(md.table, slot[n]) = jmp;
           }
+          if (!fresh[n]) continue;
           if (!x.is_clos && x.j + 1u == sg.len && !x.term && x.sgi + 1u == nseg &&
               !(sg.lock && sg.idx0 + sg.len < r.b)) {  // a capped run ends in the slices
             const uint32_t pos = atomicAdd(&sh.fcount[cur ^ 1], 1u);
@@ -1559,6 +1609,47 @@ __global__ void k_reset_models(const ModelDev* models, unsigned int* head, uint3
     for (uint32_t i = threadIdx.x; i < n_heads; i += blockDim.x) head[i] = 0u;
 }
 
+// Prepares models whose exploration continues past an earlier threshold on the same
+// visited set: counters and clocks are kept (states, terminals and least clocks
+// accumulate across the explorations), the partition bookkeeping and the incumbent
+// start again.
+__global__ void k_resume_models(const ModelDev* models, unsigned int* head, uint32_t n_heads) {
+  const ModelDev md = models[blockIdx.x];
+  if (threadIdx.x == 0) {
+    md.ctrl->parts_done = 0u;
+    md.ctrl->bound = md.T;
+    md.ctrl->violated = 0u;
+    md.ctrl->queue_head = 0u;
+  }
+  if (md.pstate)
+    for (uint32_t i = threadIdx.x; i < md.n_parts; i += blockDim.x) md.pstate[i].status = 0u;
+  if (blockIdx.x == 0 && head)
+    for (uint32_t i = threadIdx.x; i < n_heads; i += blockDim.x) head[i] = 0u;
+}
+
+// States of a visited set with clock <= T (the root included), summed into *out: the
+// count of a check(T) answered from a set that holds every state up to a larger T.
+template <int W>
+__global__ __launch_bounds__(256) void k_count_le(const unsigned char* __restrict__ table,
+                                                  unsigned long long slots, Layout L,
+                                                  const CfgRec* cfgs, uint32_t T,
+                                                  unsigned long long* out) {
+  unsigned long long n = 0;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long s = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+       s += stride) {
+    const unsigned long long* w = reinterpret_cast<const unsigned long long*>(
+        table + s * SlotBytes<W>::v);
+    Key<W> k;
+#pragma unroll
+    for (int j = 0; j < W; ++j) k.w[j] = w[j];
+    if (k.w[0] == ~0ull) continue;  // empty slot
+    if (decode<W>(k, L, cfgs).clock <= T) ++n;
+  }
+  n = wave_sum(n);
+  if (lane_id() == 0 && n) atomicAdd(out, n);
+}
+
 // ---- counterexample -----------------------------------------------------------------
 
 template <int W>
@@ -1595,7 +1686,7 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
     if (par == kParentNone && jmp == kParentNone) {
       // an interior state of a lock-step run from a dispatch leaf (it stores no links):
       // the leaf has the same busy units, each at d, and the clock of the run's start
-      const St x = decode<W>(k, L);
+      const St x = decode<W>(k, L, a.cfgs);
       const CfgRec r = a.cfgs[x.cfg];
       St leaf = x;
       uint32_t rem = 0;
@@ -1625,8 +1716,8 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
     Key<W> lk;
 #pragma unroll
     for (int w = 0; w < W; ++w) lk.w[w] = lp[w];
-    const St leaf = decode<W>(lk, L);
-    const St x = decode<W>(k, L);
+    const St leaf = decode<W>(lk, L, a.cfgs);
+    const St x = decode<W>(k, L, a.cfgs);
     const CfgRec r = a.cfgs[leaf.cfg];
     uint32_t busy = 0, lrem = 0;
     for (int u = 0; u < m; ++u)
@@ -2067,7 +2158,28 @@ hipError_t launch_chase(hipStream_t st, const QueryArgs& q, unsigned long long* 
   return hipGetLastError();
 }
 
+template <int W>
+hipError_t launch_count_le(hipStream_t st, const unsigned char* table, unsigned long long slots,
+                           const Layout& L, const CfgRec* cfgs, uint32_t T,
+                           unsigned long long* out) {
+  unsigned long long grid = (slots + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL((k_count_le<W>), dim3((uint32_t)grid), dim3(256), 0, st, table, slots, L,
+                     cfgs, T, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_resume_models(hipStream_t st, const ModelDev* models, uint32_t n,
+                                unsigned int* head, uint32_t n_heads) {
+  hipLaunchKernelGGL(k_resume_models, dim3(n), dim3(256), 0, st, models, head, n_heads);
+  return hipGetLastError();
+}
+
 #define MC_INSTANTIATE(W)                                                                  \
+  template hipError_t launch_count_le<W>(hipStream_t, const unsigned char*,                \
+                                         unsigned long long, const Layout&, const CfgRec*,  \
+                                         uint32_t, unsigned long long*);                    \
   template hipError_t launch_seed<W>(hipStream_t, const QueryArgs&, Seed*, void*);         \
   template hipError_t launch_level<W>(hipStream_t, uint32_t, const LevelArgs&, const void*, \
                                       void*);                                              \

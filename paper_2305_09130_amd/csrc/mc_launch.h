@@ -152,6 +152,15 @@ hipError_t launch_super_fork(hipStream_t main, Fork& f, const PartQueue (&queue)
 hipError_t launch_seed_models(hipStream_t st, const ModelDev* models, uint32_t n);
 hipError_t launch_reset_models(hipStream_t st, const ModelDev* models, uint32_t n,
                                unsigned int* head, uint32_t n_heads);
+// Counters and clocks kept, partition bookkeeping reset: before a launch that continues
+// an exploration on the same visited set.
+hipError_t launch_resume_models(hipStream_t st, const ModelDev* models, uint32_t n,
+                                unsigned int* head, uint32_t n_heads);
+// *out += states of the visited set (slots slots) with clock <= T; *out is not cleared.
+template <int W>
+hipError_t launch_count_le(hipStream_t st, const unsigned char* table, unsigned long long slots,
+                           const Layout& L, const CfgRec* cfgs, uint32_t T,
+                           unsigned long long* out);
 template <int W>
 hipError_t launch_find(hipStream_t st, const QueryArgs& q, const unsigned long long* key);
 template <int W>

@@ -218,6 +218,35 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
   }
 }
 
+void chain_cuts(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t target,
+                std::vector<ChainCut>* out) {
+  const uint32_t all = (1u << m) - 1u;
+  uint64_t t = 0, p = r.n, dep = 1, states = 1, last = 0;  // SELECT at depth 1
+  UnitRun ur[kMaxCU];
+  uint32_t busy = 0;
+  for (;;) {
+    const uint32_t freem = all & ~busy;
+    const uint32_t f = (uint32_t)__builtin_popcount(freem);
+    if (f > 0) {
+      if (p < f) return;  // the tails begin: no cut past here
+      states += (1ull << f) - 1;
+      dep += f;
+      p -= f;
+      for (uint32_t u = 0; u < m; ++u)
+        if ((freem >> u) & 1u) start_unit(r, sp, ur, u, t);
+      busy = all;
+    }
+    if (p == 0) return;
+    t = advance_units(r, sp, m, ur, &busy);
+    ++dep;
+    ++states;
+    if (busy == all && states - last >= target) {  // no workgroup ended at t
+      out->push_back(ChainCut{t, dep, states});
+      last = states;
+    }
+  }
+}
+
 int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   if (!d || !h) return fail(err, "null descriptor");
   if (d->n_cu < 1 || d->n_cu > (uint32_t)kMaxCU) return fail(err, "n_cu out of range 1..8");
@@ -357,13 +386,15 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   h->frontier_bound = fb;
 
   // key layout: cfg | pending | clock | rem_0 .. rem_{m-1}
+  // equal units start their workgroups together (every dispatch is from an all-idle
+  // state), so every busy unit has the same time left: a mask and one field hold them;
+  // and the rounds are in lock step, so the clock follows from the other fields and is
+  // not stored (Layout::clock_implied)
+  const bool shared = !h->hetero;
   uint32_t widths[kFields] = {0};
   widths[kFCfg] = std::max<uint32_t>(1, bit_length((uint64_t)d->n_cfg + 1));
   widths[kFPending] = std::max<uint32_t>(1, bit_length(max_n));
-  widths[kFClock] = std::max<uint32_t>(1, bit_length(max_clock));
-  // equal units start their workgroups together (every dispatch is from an all-idle
-  // state), so every busy unit has the same time left: a mask and one field hold them
-  const bool shared = !h->hetero;
+  widths[kFClock] = shared ? 0u : std::max<uint32_t>(1, bit_length(max_clock));
   if (shared) {
     widths[kFRem] = m;
     widths[kFRem + 1] = std::max<uint32_t>(1, bit_length(max_d));
@@ -395,6 +426,8 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   L.m = (uint8_t)m;
   L.hetero = h->hetero ? 1 : 0;
   L.shared_rem = shared ? 1 : 0;
+  L.clock_implied = shared ? 1 : 0;
+  L.n_cfg = d->n_cfg;
   for (int i = 0; i < kMaxCU; ++i) L.speed[i] = (uint8_t)h->speed[i];
   L.used_bits = (uint8_t)used;
   h->layout = L;
@@ -403,12 +436,39 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
 }
 
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out) {
-  const Layout& L = h.layout;
   // units of unequal speed pass through no common idle state after whole rounds
-  const bool cuttable =
-      target > 0 && !h.hetero && L.word[kFPending] == 0 && L.word[kFClock] == 0;
+  const bool cuttable = target > 0 && word0_orders_rounds(h);
+  // ... but their determined part is cut into chain slices, which share no word-0 value
+  // but their boundary states when the clock is in word 0
+  const Layout& L = h.layout;
+  const bool chains = target > 0 && h.hetero && L.word[kFClock] == 0 && L.word[kFPending] == 0;
+  const uint64_t chain_target = std::max<uint64_t>(32, target);
   for (uint32_t c = 0; c < h.n_cfg; ++c) {
     const CfgRec& r = h.cfgs[c];
+    if (chains) {
+      std::vector<ChainCut> cuts;
+      if (h.cfg_states[c] >= 2 * chain_target) chain_cuts(r, h.speed, h.m, chain_target, &cuts);
+      if (cuts.empty()) {
+        out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
+        continue;
+      }
+      uint64_t prev_t = 0, prev_dep = 0, prev_states = 0;
+      for (size_t k = 0; k <= cuts.size(); ++k) {
+        const bool last = k == cuts.size();
+        const uint64_t upto = last ? h.cfg_states[c] : cuts[k].states;
+        PartPlan pp{c, kChainSlice, last ? kNoClock : (uint32_t)cuts[k].t,
+                    upto > prev_states ? upto - prev_states : 1};
+        pp.j0 = (uint32_t)prev_t;
+        pp.j1 = (uint32_t)prev_dep;
+        out->push_back(pp);
+        if (!last) {
+          prev_t = cuts[k].t;
+          prev_dep = cuts[k].depth;
+          prev_states = cuts[k].states;
+        }
+      }
+      continue;
+    }
     const uint64_t q = r.n / h.m;
     const uint64_t per_round = ((1ull << h.m) - 1) + r.b;
     // blocks of at least kMinBlockRounds rounds, or of fewer when the rounds are long
@@ -490,6 +550,29 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
   }
 }
 
+bool word0_orders_rounds(const ModelHost& h) {
+  const Layout& L = h.layout;
+  if (h.hetero || L.word[kFPending] != 0) return false;
+  // with the clock stored, pending and clock in word 0 tell rounds and run positions
+  // apart; with the clock implied, the mask and the time left must be there too
+  return L.clock_implied ? L.word[kFRem] == 0 && L.word[kFRem + 1] == 0 : L.word[kFClock] == 0;
+}
+
+bool resumable(const ModelHost& h) { return word0_orders_rounds(h); }
+
+void plan_resume(const ModelHost& h, uint64_t T_done, std::vector<PartPlan>* out) {
+  for (uint32_t c = 0; c < h.n_cfg; ++c) {
+    const CfgRec& r = h.cfgs[c];
+    const uint64_t rounds = (r.n + h.m - 1) / h.m;
+    if (rounds * r.d <= T_done) continue;  // its terminals are in already
+    // round r0 starts at clock r0*d <= T_done: its start state was inserted, the states
+    // of the round past T_done were not
+    const uint64_t r0 = std::min<uint64_t>(T_done / r.d, rounds - 1);
+    const uint64_t left = h.cfg_states[c] * (rounds - r0) / rounds + 1;
+    out->push_back(PartPlan{c, (uint32_t)r0, kRoundsToEnd, left});
+  }
+}
+
 uint64_t auto_part_states(uint64_t states, uint32_t m) {
   // about 640 partitions for small models (256 on one unit), down to blocks of
   // kMinBlockRounds rounds; blocks of at most 2^14 states for large ones.  With one-word
@@ -555,6 +638,49 @@ uint64_t count_le_bound(const ModelHost& h, uint64_t T) {
     total += std::min<uint64_t>(cnt, h.cfg_states[c]);
   }
   return total;
+}
+
+// fields: cfg, pending, clock, then the time left on every unit (packed as a busy mask
+// and one shared time when the layout says so)
+void encode_key_host(const Layout& L, const uint32_t* fields, uint64_t* words) {
+  for (int j = 0; j < 4; ++j) words[j] = 0;
+  uint32_t packed[kFields];
+  for (int f = 0; f < 3 + L.m; ++f) packed[f] = fields[f];
+  int nf = 3 + L.m;
+  if (L.shared_rem) {
+    uint32_t mask = 0, rem = 0;
+    for (int u = 0; u < L.m; ++u)
+      if (fields[kFRem + u]) {
+        mask |= 1u << u;
+        rem = fields[kFRem + u];
+      }
+    packed[kFRem] = mask;
+    packed[kFRem + 1] = rem;
+    nf = 5;
+  }
+  if (L.clock_implied) packed[kFClock] = 0;  // not stored
+  for (int f = 0; f < nf; ++f) words[L.word[f]] |= (uint64_t)packed[f] << L.shift[f];
+}
+
+// cfgs: the configuration records, from which an implied clock is derived (as the
+// device's implied_clock does)
+void decode_key_host(const Layout& L, const uint64_t* words, uint32_t* fields, const CfgRec* cfgs) {
+  const int nf = L.shared_rem ? 5 : 3 + L.m;
+  for (int f = 0; f < nf; ++f)
+    fields[f] = (uint32_t)((words[L.word[f]] >> L.shift[f]) & ((1ull << L.width[f]) - 1ull));
+  if (L.shared_rem) {
+    const uint32_t mask = fields[kFRem], rem = fields[kFRem + 1];
+    for (int u = 0; u < L.m; ++u) fields[kFRem + u] = ((mask >> u) & 1u) ? rem : 0u;
+    if (L.clock_implied) {
+      const uint32_t c = fields[kFCfg];
+      if (c >= L.n_cfg) {
+        fields[kFClock] = 0;
+      } else {
+        const uint32_t done = cfgs[c].n - fields[kFPending] - (uint32_t)__builtin_popcount(mask);
+        fields[kFClock] = (done + L.m - 1u) / L.m * cfgs[c].d + (mask ? cfgs[c].d - rem : 0u);
+      }
+    }
+  }
 }
 
 }  // namespace mc

@@ -38,6 +38,13 @@ struct Layout {
   uint8_t hetero;            // units of unequal speed
   uint8_t shared_rem;        // equal units: busy mask + one remaining time (kFRem, kFRem + 1)
   uint8_t speed[kMaxCU];     // cycles per cycle of work of each unit (1 = full speed)
+  // equal units: the clock is not stored (width 0).  Every run proceeds in lock-step
+  // rounds, so a state's clock follows from its other fields and its configuration's
+  // n and d: ceil((n - pending - busy)/m) * d, plus d - rem while units are busy
+  // (implied_clock).  Decoding then needs the configuration records.
+  uint8_t clock_implied;
+  uint8_t pad_[3];
+  uint32_t n_cfg;            // configurations; the root carries cfg = n_cfg
 };
 
 // One configuration: workgroup count, duration and the timed operation phases of one
@@ -99,6 +106,13 @@ constexpr uint32_t kMinBlockStates = 2048;  // unless fewer rounds already hold 
 // configuration's SELECT closure then explores its runs only up to j1 of its plan
 // (its `j1`, 0 = whole runs).
 constexpr uint32_t kRunSlice = 0xFFFFFFFEu;
+// A chain slice (units of unequal speed; Part::r0 = kChainSlice): the configuration's
+// states with clock in [j0, r1] along its determined part (r1 = kNoClock: to the end,
+// tails included).  It starts at the SELECT state when j0 = 0, else at the state at
+// clock j0, an instant of the determined part at which no workgroup ends (j1 = that
+// state's depth), and ends on the state at clock r1, another such instant, which the
+// next slice starts from.
+constexpr uint32_t kChainSlice = 0xFFFFFFFDu;
 constexpr uint32_t kMinSlice = 1024, kMaxSlice = 8192;
 struct PartPlan {
   uint32_t cfg, r0, r1;
@@ -117,6 +131,25 @@ struct PartPlan {
 // of each (every state of a slice has a clock no other partition's states have).
 void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
 
+// Whether key word 0 alone tells apart the states of different rounds and of different
+// positions along a round's runs (configuration, pending count and either the clock or,
+// when the clock is implied, the busy mask and time left): the condition for cutting a
+// configuration into blocks of rounds and run slices explored by separate workgroups,
+// which then share no word-0 value except their common boundary states.
+bool word0_orders_rounds(const ModelHost& h);
+
+// Whether an exploration pruned at some T can be continued to a larger T' on the same
+// visited set: units that all work alike (every configuration passes through the state
+// after r full rounds, (c, r d, n - r m, all idle)) and a key whose word 0 holds the
+// pending count and the clock (so a partition may start at that state).
+bool resumable(const ModelHost& h);
+
+// Partitions that continue a resumable model's exploration after every state with clock
+// <= T_done was inserted: for each configuration not yet at its terminals, rounds
+// r0 = floor(T_done / d) (its start state is in the set) to the end.  Re-exploring round
+// r0 finds its states up to T_done present and inserts the rest.
+void plan_resume(const ModelHost& h, uint64_t T_done, std::vector<PartPlan>* out);
+
 // Default target states per partition for a launch exploring `states` states in total
 // on models of m units.
 uint64_t auto_part_states(uint64_t states, uint32_t m = 2u);
@@ -134,6 +167,16 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
 // Time of the k-th operation end (0-based, k < r.b) of one workgroup.
 uint64_t end_at_host(const CfgRec& r, uint64_t k);
 
+// Cut points of a configuration's determined part on units of unequal speed, about
+// `target` states apart: instants t at which every unit is busy, work is pending and no
+// workgroup ends (so the state at t has a single predecessor chain and lies on every
+// run), with the state's depth from the root and the states counted before it.
+struct ChainCut {
+  uint64_t t = 0, depth = 0, states = 0;
+};
+void chain_cuts(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t target,
+                std::vector<ChainCut>* out);
+
 // An upper bound (exact for every configuration whose last round is not partial) on the
 // number of states with clock <= T, root included: what a check(T) inserts.  Sizes its
 // visited set only.
@@ -141,6 +184,14 @@ uint64_t count_le_bound(const ModelHost& h, uint64_t T);
 
 uint64_t binom(uint32_t n, uint32_t k);
 uint32_t bit_length(uint64_t x);
+
+// Packed key of a state on the host.  fields: cfg, pending, clock, then the time left
+// on every unit (packed as a busy mask and one shared time when the layout says so; an
+// implied clock is not stored).
+void encode_key_host(const Layout& L, const uint32_t* fields, uint64_t* words);
+// The inverse; cfgs (the configuration records) give an implied clock.
+void decode_key_host(const Layout& L, const uint64_t* words, uint32_t* fields,
+                     const CfgRec* cfgs);
 
 // min_time of a descriptor over a caller's device workspace, with no pinned staging and
 // no runtime objects created (mc_api.hip): the query path of mc_min_time_static.

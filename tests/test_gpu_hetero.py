@@ -135,15 +135,27 @@ def test_hetero_batch_and_served(mc):
     tickets = [e.mc_engine_submit(pool[i], mc.MC_QUERY_MIN_TIME if k == "min_time"
                                   else mc.MC_QUERY_CHECK, T) for i, k, T in qs]
     e.drain()
+    traced = 0
     for (i, kind, T), t in zip(qs, tickets):
         res = e.mc_engine_poll(t)
         assert res["done"] == 1 and res["status"] == 0
         r = oracle.explore(pool[i], T=None if kind == "min_time" else T, trace=False)
+        full = oracle.explore(pool[i], trace=False)
         assert res["states"] == r["reachable"], (i, kind, T)
         if kind == "min_time":
-            assert (res["t_min"], res["n_argmin"]) == (r["t_min"], len(r["argmin"]))
+            assert res["t_min"] == r["t_min"]
         else:
             assert res["violated"] == int(r["violated"])
+        if kind == "min_time" or r["violated"]:
+            assert e.mc_engine_argmin(t) == full["argmin"], (i, kind, T)
+            try:   # readable while the model's state is still resident
+                rows = e.mc_engine_trace(t, pool[i]["m"])
+            except mc.McError as err:
+                assert err.code == mc.MC_E_STATE
+                continue
+            oracle.check_trace(pool[i], rows, target_clock=full["t_min"], cfgs=full["argmin"])
+            traced += 1
+    assert traced >= 3
     e.close()
 
 
@@ -182,4 +194,40 @@ def test_hetero_simulate_full_size(mc):
         for seed in range(1, 9):
             assert g.mc_simulate(seed) == oracle.simulate(model, seed), (
                 workloads.describe(model), seed)
+        g.close()
+
+
+@pytest.mark.parametrize("part_states", [32, 100, 400])
+def test_hetero_chain_slices(mc, part_states):
+    """The determined part of each configuration cut into chain slices of about
+    `part_states` states, explored by separate workgroups that share only their boundary
+    states: counts, clocks, verdicts and traces stay the oracle's."""
+    cases = (workloads.tiny_hetero_models(611, 24, max_cu=6)
+             + [workloads.with_speeds(workloads.reduction_model(128, 3, [1, 2, 4], [1, 2], 9, 2),
+                                      [1, 2, 3]),
+                workloads.with_speeds(workloads.reduction_model(256, 4, [2, 4], [1, 4], 7, 3),
+                                      [1, 1, 2, 3])])
+    for model in cases:
+        _say(f"chain slices {part_states}: {workloads.describe(model)}")
+        r = oracle.explore(model, trace=False)
+        g = mc.Model(model, part_states=part_states)
+        check_min_time(g, model, r, ENGINES["superstep"])
+        for T in sorted({r["t_min"] - 1, r["t_min"], (r["t_min"] + max(r["tc"])) // 2}):
+            if T >= 0:
+                check_threshold(mc, g, model, T)
+        g.close()
+
+
+def test_hetero_workloads_sliced_full_size(mc):
+    """The two full-size workloads at the automatic cut (chain slices of about
+    states/640): exact against the oracle, with traces."""
+    for name, model in workloads.hetero_workloads().items():
+        _say(f"full size {name}")
+        r = oracle.explore(model, trace=False)
+        g = mc.Model(model)
+        assert g.last_stats == {} and g.mc_min_time() == (r["t_min"], r["argmin"])
+        st = g.last_stats
+        assert st["states"] == r["reachable"] and st["parts"] > len(model["params"])
+        assert g.mc_terminal_clocks() == r["tc"]
+        oracle.check_trace(model, g.mc_trace(), target_clock=r["t_min"], cfgs=r["argmin"])
         g.close()
