@@ -435,10 +435,12 @@ int mc_batch_autotune(const mc_desc *models, uint32_t n, void *dev_ws, size_t ws
  *      (units that all work alike; otherwise it starts over in the same memory).  A
  *      model seen for the first time needs an arena region and a model slot: idle
  *      models are evicted, least recently used first, to make room; a query that still
- *      does not fit waits, and so do later queries needing new memory (queries on a
- *      model whose previous query still runs wait for it without blocking others);
+ *      does not fit waits, and so do later queries needing new memory.  A query on a
+ *      model whose previous query still explores is answered at once if the set
+ *      already covers it (that exploration only adds states past T_done), else it
+ *      waits for it without blocking others;
  *   2. runs one persistent launch over the unfinished partitions of every active
- *      query; while queries wait for admission, a partition explores at most `slice`
+ *      query; while queries wait for memory, a partition explores at most `slice`
  *      super-step levels, then saves its frontier and yields;
  *   3. retires the queries whose partitions are all explored.
  * Queries admitted later therefore share the device with queries already running.
@@ -455,7 +457,7 @@ typedef struct mc_engine_opts {
     uint32_t max_cfg;        /* largest configuration count a query may have (>= 1) */
     uint32_t block;          /* threads per workgroup: 256, 512, 1024 (0 = 512) */
     uint32_t slice;          /* super-step levels per partition per step while queries
-                                wait for admission (0 = no limit); with none waiting a
+                                wait for memory (0 = no limit); with none waiting a
                                 step runs its partitions to the end */
     uint32_t chunk;          /* states per super-step batch (0 = 2 x block x lane_items) */
     uint32_t grid;           /* persistent workgroups per step (0 = up to 1024) */

@@ -114,7 +114,8 @@ struct Resident {
   uint32_t T_done = 0;
   std::vector<uint32_t> tc;  // least terminal clocks after the last exploration
   uint64_t states = 0, levels = 0;
-  Query* busy = nullptr;  // the query using the model now
+  Query* busy = nullptr;  // the query exploring the model now
+  Query* counting = nullptr;  // a query answered from the set in the current step
   uint64_t last_used = 0;
 };
 
@@ -256,7 +257,8 @@ bool place(mc_engine* e, Resident* r) {
     }
     Resident* victim = nullptr;
     for (Resident* x : e->slots)
-      if (x && !x->busy && (!victim || x->last_used < victim->last_used)) victim = x;
+      if (x && !x->busy && !x->counting && (!victim || x->last_used < victim->last_used))
+        victim = x;
     if (!victim) return false;
     drop_resident(e, victim);
   }
@@ -453,18 +455,44 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
   std::vector<Query*> counts;  // check queries answered by a scan of the set
   std::deque<Query*> still;
   bool blocked = false;  // a query needing new memory did not fit: later ones wait too
+  bool wait_memory = false;  // some query waits for arena room or a model slot
   try {
     while (!e->waiting.empty()) {
       Query* q = e->waiting.front();
       e->waiting.pop_front();
       auto it = e->by_key.find(q->key);
       Resident* r = it == e->by_key.end() ? nullptr : it->second;
-      if (r && r->busy) {  // the model's previous query still runs
-        still.push_back(q);
+      if (r && (r->busy || r->counting)) {
+        // a query the set already covers is answered while the model's previous query
+        // continues the exploration past T_done: that exploration only adds states with
+        // larger clocks (and a scan skips a slot whose key is still being written)
+        const bool covered = r->explored && (r->complete || (q->kind == MC_QUERY_CHECK &&
+                                                             q->T <= r->T_done));
+        const bool resuming = !r->busy || r->busy->mode == kResume;
+        if (covered && resuming && !r->counting) {
+          q->resident = r->id;
+          q->admit_ns = now_ns();
+          r->last_used = ++e->clock;
+          if (q->kind == MC_QUERY_MIN_TIME) {
+            q->mode = kKnown;
+            fill_result(q, r->tc);
+            q->res.status = MC_OK;
+            q->res.states = r->states;
+            q->res.levels = r->levels;
+            finish(e, q);
+          } else {
+            q->mode = kCount;
+            r->counting = q;
+            counts.push_back(q);
+          }
+          continue;
+        }
+        still.push_back(q);  // the model's previous query still runs
         continue;
       }
       if (!r) {
         if (blocked) {
+          wait_memory = true;
           still.push_back(q);
           continue;
         }
@@ -495,7 +523,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
         if (!place(e, r)) {
           q->mh = std::move(r->mh);
           delete r;
-          blocked = true;
+          blocked = wait_memory = true;
           still.push_back(q);
           continue;
         }
@@ -506,16 +534,26 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       }
       q->resident = r->id;
       q->admit_ns = now_ns();
-      r->busy = q;
       r->last_used = ++e->clock;
       const bool covered = r->explored && (r->complete || (q->kind == MC_QUERY_CHECK &&
                                                            q->T <= r->T_done));
       if (covered && q->kind == MC_QUERY_MIN_TIME) {
         q->mode = kKnown;
-      } else if (covered) {
+        fill_result(q, r->tc);
+        q->res.status = MC_OK;
+        q->res.states = r->states;
+        q->res.levels = r->levels;
+        finish(e, q);
+        continue;
+      }
+      if (covered) {
         q->mode = kCount;
+        r->counting = q;
         counts.push_back(q);
-      } else if (r->explored && resumable(r->mh)) {
+        continue;
+      }
+      r->busy = q;
+      if (r->explored && resumable(r->mh)) {
         q->mode = kResume;
         Start st{q, r, {}};
         plan_resume(r->mh, r->T_done, &st.plan);
@@ -530,17 +568,6 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
     return MC_E_NOMEM;
   }
   e->waiting.swap(still);
-  // answered at once from a complete set: min_time after min_time
-  for (Resident* r : e->slots) {
-    if (!r || !r->busy || r->busy->mode != kKnown) continue;
-    Query* q = r->busy;
-    fill_result(q, r->tc);
-    q->res.status = MC_OK;
-    q->res.states = r->states;
-    q->res.levels = r->levels;
-    finish(e, q);
-    r->busy = nullptr;
-  }
   // ---- device work of the admitted queries ----
   if (!starts.empty()) {
     std::vector<ModelDev> fresh_md, resume_md;
@@ -612,14 +639,14 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
   // ---- one persistent launch over every unfinished partition ----
   bool any_active = false;
   uint32_t hi = 0;  // one past the highest slot in use
-  for (size_t i = 0; i < e->slots.size(); ++i)
-    if (e->slots[i] && e->slots[i]->busy) {
-      any_active = true;
-      hi = (uint32_t)i + 1u;
-    }
-  // partitions are cut into slices only while queries wait for admission: otherwise the
-  // launch runs everything admitted to the end, with no host round trip per slice
-  const uint32_t slice = e->waiting.empty() ? 0u : e->opts.slice;
+  for (size_t i = 0; i < e->slots.size(); ++i) {
+    if (e->slots[i] && e->slots[i]->busy) any_active = true;
+    if (e->slots[i] && (e->slots[i]->busy || e->slots[i]->counting)) hi = (uint32_t)i + 1u;
+  }
+  // partitions are cut into slices only while queries wait for memory to be admitted:
+  // otherwise the launch runs everything admitted to the end, with no host round trip
+  // per slice (a query waiting for its model's running query gains nothing from slices)
+  const uint32_t slice = wait_memory ? e->opts.slice : 0u;
   const bool launch = any_active && !e->pending_parts.empty();
   if (launch) {
     const int cur = e->cur;
@@ -693,21 +720,22 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
   // ---- retire finished queries ----
   for (size_t i = 0; i < e->slots.size(); ++i) {
     Resident* r = e->slots[i];
+    if (!r || !r->counting) continue;
+    Query* q = r->counting;
+    fill_result(q, r->tc);  // terminals within T <= T_done: those of the resident clocks
+    q->res.status = MC_OK;
+    q->res.states = e->hcount[i];
+    q->res.levels = 0;  // not known without exploring
+    finish(e, q);
+    r->counting = nullptr;
+  }
+  for (size_t i = 0; i < e->slots.size(); ++i) {
+    Resident* r = e->slots[i];
     if (!r || !r->busy) continue;
     Query* q = r->busy;
     const Ctrl* c = reinterpret_cast<const Ctrl*>(e->hctrl + kCtrlStride * i);
     const uint32_t* tc = e->htc + (size_t)e->opts.max_cfg * i;
     mc_query_result& res = q->res;
-    if (q->mode == kCount) {
-      fill_result(q, r->tc);
-      res.status = MC_OK;
-      res.states = e->hcount[i];
-      res.levels = 0;  // not known without exploring
-      finish(e, q);
-      r->busy = nullptr;
-      if (e->opts.no_reuse) drop_resident(e, r);
-      continue;
-    }
     const bool failed = c->error != 0u;
     if (c->parts_done < q->n_parts && !failed) continue;
     res.status = dev_error_code(c->error);
@@ -741,6 +769,9 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
   }
   uint32_t na = 0;
   for (Resident* r : e->slots) na += r && r->busy;
+  if (e->opts.no_reuse)  // nothing is kept: every idle model is dropped
+    for (Resident* r : e->slots)
+      if (r && !r->busy && !r->counting) drop_resident(e, r);
   if (n_active) *n_active = na;
   if (n_waiting) *n_waiting = (uint32_t)e->waiting.size();
   return MC_OK;
@@ -843,7 +874,7 @@ int mc_engine_trace(mc_engine* e, uint64_t ticket, uint32_t* rows, size_t cap, s
   const Query* q = it->second;
   if (!q->res.done || q->res.status != MC_OK || !q->has_target) return MC_E_STATE;
   auto rt = e->by_id.find(q->resident);
-  if (rt == e->by_id.end() || rt->second->busy) return MC_E_STATE;
+  if (rt == e->by_id.end() || rt->second->busy || rt->second->counting) return MC_E_STATE;
   Resident* r = rt->second;
   std::vector<uint32_t> out;
   int rc;

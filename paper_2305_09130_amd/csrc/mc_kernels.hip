@@ -1628,7 +1628,9 @@ __global__ void k_resume_models(const ModelDev* models, unsigned int* head, uint
 }
 
 // States of a visited set with clock <= T (the root included), summed into *out: the
-// count of a check(T) answered from a set that holds every state up to a larger T.
+// count of a check(T) answered from a set that holds every state up to a larger T
+// (between the launches of an exploration that continues past that T: the states it
+// adds all have larger clocks).
 template <int W>
 __global__ __launch_bounds__(256) void k_count_le(const unsigned char* __restrict__ table,
                                                   unsigned long long slots, Layout L,
@@ -1641,9 +1643,13 @@ __global__ __launch_bounds__(256) void k_count_le(const unsigned char* __restric
     const unsigned long long* w = reinterpret_cast<const unsigned long long*>(
         table + s * SlotBytes<W>::v);
     Key<W> k;
+    bool ready = true;
 #pragma unroll
-    for (int j = 0; j < W; ++j) k.w[j] = w[j];
-    if (k.w[0] == ~0ull) continue;  // empty slot
+    for (int j = 0; j < W; ++j) {
+      k.w[j] = w[j];
+      ready &= k.w[j] != ~0ull;
+    }
+    if (!ready) continue;  // an empty slot (or a key whose words are not all written)
     if (decode<W>(k, L, cfgs).clock <= T) ++n;
   }
   n = wave_sum(n);

@@ -196,13 +196,16 @@ def test_matmul64_block_sizes(mc, part_states):
     g.close()
 
 
-def test_matmul128_vw_full_size(mc):
+@pytest.mark.parametrize("block", [0, 1024])
+def test_matmul128_vw_full_size(mc, block):
     """The large workload: closed forms (pinned to the oracle) give the counts, the
-    per-configuration clocks and the argmin; the trace is replayed through the oracle."""
+    per-configuration clocks and the argmin; the trace is replayed through the oracle.
+    block 0 is the automatic launch that the benchmark times (256 threads, one key per
+    lane at its 3,828 partitions); 1024 the widest workgroup."""
     model = workloads.matmul_128_vw()
-    _say("matmul128_vw superstep")
+    _say(f"matmul128_vw superstep block {block}")
     s = cf.summary(model, with_E=False)
-    g = mc.Model(model, engine=0, block=1024)
+    g = mc.Model(model, engine=0, block=block)
     t_min, argmin = g.mc_min_time()
     st = g.last_stats
     assert (t_min, argmin) == (s["t_min"], s["argmin"])
@@ -212,6 +215,11 @@ def test_matmul128_vw_full_size(mc):
     tr = g.mc_trace()
     assert len(tr) == s["trace_len"]
     oracle.check_trace(model, tr, target_clock=s["t_min"], cfgs=s["argmin"])
+    if block == 0:
+        assert g.last_stats["parts"] == 3828
+        # the benchmark's second query: check(T_min - 1) holds, with count_T exact
+        assert g.mc_check(s["t_min"] - 1) is False
+        assert g.last_stats["states"] == cf.count_le(model, s["t_min"] - 1)
     g.close()
 
 
