@@ -205,26 +205,37 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
     b.close()
     del ws
     torch.cuda.empty_cache()
-    # one at a time on a sample: a load per instance into one preallocated workspace,
-    # the library's automatic launch options
+    # one at a time on a sample: a load per instance into one preallocated workspace, with
+    # the library's automatic launch options and with the batch's autotuned ones; the faster
+    # of the two is the baseline
     idx = list(range(0, n_inst, max(1, n_inst // sample_alone)))[:sample_alone]
-    ws1 = torch.empty(max(mc.mc_workspace_bytes(models[i]) for i in idx), dtype=torch.uint8,
-                      device="cuda:0")
-    g = mc.Model(models[idx[0]], workspace=ws1)  # warm
-    g.mc_min_time()
-    g.close()
-    torch.cuda.synchronize()
-    t_alone, s_alone = 0.0, 0
-    for i in idx:
-        t1 = time.perf_counter()
-        g = mc.Model(models[i], workspace=ws1)
-        tm, _ = g.mc_min_time()
-        s_alone += g.last_stats["states"]
+    variants = {
+        "automatic": {},
+        "autotuned": {"block": int(best.block), "load_factor": float(best.load_factor),
+                      "lane_items": int(best.lane_items), "part_states": int(best.part_states)},
+    }
+    alone = {}
+    for name, opts in variants.items():
+        mo = mc.make_opts(**opts)
+        ws1 = torch.empty(max(mc.mc_workspace_bytes(models[i], mo) for i in idx),
+                          dtype=torch.uint8, device="cuda:0")
+        g = mc.Model(models[idx[0]], workspace=ws1, **opts)  # warm
+        g.mc_min_time()
         g.close()
-        t_alone += time.perf_counter() - t1
-        assert tm == t_min[i]
-    del ws1
-    torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t_alone, s_alone = 0.0, 0
+        for i in idx:
+            t1 = time.perf_counter()
+            g = mc.Model(models[i], workspace=ws1, **opts)
+            tm, _ = g.mc_min_time()
+            s_alone += g.last_stats["states"]
+            g.close()
+            t_alone += time.perf_counter() - t1
+            assert tm == t_min[i]
+        del ws1
+        torch.cuda.empty_cache()
+        alone[name] = {"value": s_alone / t_alone, "queries_per_s": len(idx) / t_alone}
+    base = max(alone, key=lambda k: alone[k]["value"])
     return {"instances": n_inst, "rejected_draws": rejected,
             "draw_filter": f"instances above {BATCH_BUDGET} states redrawn "
                            f"({rejected} of {rejected + n_inst} draws)",
@@ -232,10 +243,12 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
             "value": total / el, "unit": "states/s", "queries_per_s": n_inst / el,
             "ms_per_batch": 1e3 * el, "gpu_ms": gpu_ms,
             "autotuned": best.as_dict(), "autotune_s": tune_s,
-            "one_at_a_time": {"sample": len(idx), "value": s_alone / t_alone,
-                              "queries_per_s": len(idx) / t_alone,
-                              "how": "preallocated workspace, automatic launch options"},
-            "speedup_vs_one_at_a_time": (total / el) / (s_alone / t_alone)}
+            "one_at_a_time": {"sample": len(idx), "value": alone[base]["value"],
+                              "queries_per_s": alone[base]["queries_per_s"],
+                              "options": base, "variants": alone,
+                              "how": "preallocated workspace; the faster of the automatic "
+                                     "and the batch's autotuned launch options"},
+            "speedup_vs_one_at_a_time": (total / el) / alone[base]["value"]}
 
 
 def swarm_leg(mc, workloads, names, members: int = 16384, bits_log2: int = 16,

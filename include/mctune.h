@@ -148,6 +148,10 @@ typedef struct mc_opts {
                                 rounds and its long lock-step runs into run slices (a
                                 round's states j0..j1-1 of every run; 1024..8192 states per
                                 slice) (0 = automatic, UINT32_MAX = never cut) */
+    uint32_t test_hash_bits; /* testing only: 0 = the full key hash; k in 1..24 keeps k
+                                bits of it, so that keys crowd into 2^k probe sequences
+                                (long probe chains, and keys of several words that share
+                                word 0 meeting in one slot); results are unchanged */
 } mc_opts;
 
 /* ---- statistics of the last query ---------------------------------------------- */

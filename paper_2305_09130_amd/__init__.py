@@ -50,7 +50,8 @@ class McOpts(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_uint32), ("block", ctypes.c_uint32),
                 ("log2_slots", ctypes.c_uint32), ("load_factor", ctypes.c_float),
                 ("grid", ctypes.c_uint32), ("batch_items", ctypes.c_uint32),
-                ("lane_items", ctypes.c_uint32), ("part_states", ctypes.c_uint32)]
+                ("lane_items", ctypes.c_uint32), ("part_states", ctypes.c_uint32),
+                ("test_hash_bits", ctypes.c_uint32)]
 
 
 class McStats(ctypes.Structure):
@@ -237,11 +238,12 @@ def make_desc(model: dict) -> tuple[McDesc, tuple]:
 
 def make_opts(engine: int = MC_ENGINE_SUPERSTEP, block: int = 0, log2_slots: int = 0,
               load_factor: float = 0.0, grid: int = 0, batch_items: int = 0,
-              lane_items: int = 0, part_states: int = 0) -> McOpts:
+              lane_items: int = 0, part_states: int = 0, test_hash_bits: int = 0) -> McOpts:
     o = McOpts()
     o.engine, o.block, o.log2_slots, o.load_factor, o.grid = engine, block, log2_slots, \
         load_factor, grid
     o.batch_items, o.lane_items, o.part_states = batch_items, lane_items, part_states
+    o.test_hash_bits = test_hash_bits
     return o
 
 
@@ -316,14 +318,14 @@ class Model:
     def __init__(self, model: dict, engine: int = MC_ENGINE_SUPERSTEP, block: int = 0,
                  log2_slots: int = 0, load_factor: float = 0.0, grid: int = 0,
                  device: str = "cuda:0", stream=None, workspace=None, batch_items: int = 0,
-                 lane_items: int = 0, part_states: int = 0):
+                 lane_items: int = 0, part_states: int = 0, test_hash_bits: int = 0):
         import torch
         self.model = model
         self.m = model["m"]
         self.n_cfg = len(model["params"])
         self._desc, self._params = make_desc(model)
         self._opts = make_opts(engine, block, log2_slots, load_factor, grid, batch_items,
-                               lane_items, part_states)
+                               lane_items, part_states, test_hash_bits)
         nbytes = mc_workspace_bytes(model, self._opts)
         self.device = torch.device(device)
         if workspace is None:

@@ -42,6 +42,7 @@ struct WsPlan {
 uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
 
 int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) {
+  if (o.test_hash_bits > 24u) return MC_E_INVAL;
   uint64_t slots;
   if (o.log2_slots) {
     if (o.log2_slots < 4 || o.log2_slots > 31) return MC_E_INVAL;
@@ -192,6 +193,7 @@ QueryArgs make_args(mc_model* h, bool prune, uint32_t T) {
   q.prune = prune ? 1u : 0u;
   q.T = T;
   q.max_clock = h->mh.max_clock;
+  q.hkeep = h->opts.test_hash_bits;
   return q;
 }
 
@@ -297,6 +299,8 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     md.n_parts = h->n_parts;
     md.bb = bb ? 1u : 0u;
     md.pstate = nullptr;
+    md.hkeep = h->opts.test_hash_bits;
+    md.pad2 = 0u;
     HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
     HIPCHK(launch_reset_models(s, h->dmd, 1, h->head, 1));
     HIPCHK(ev_record(h->ev[2], s));

@@ -379,6 +379,12 @@ static_assert(Win<1>::n == 4 && Win<2>::n == 2 && Win<4>::n == 1, "window sizes"
 
 // Home window wi, odd window step, and the first slot j0 within every window (from
 // the hash's top bits, which neither wi nor step use for tables below 2^31 slots).
+// The key's hash with only its low `hkeep` bits kept (hkeep 0: all), remixed: a testing
+// aid that crowds keys into 2^hkeep probe sequences.
+__device__ __forceinline__ unsigned long long keep_hash(unsigned long long h, uint32_t hkeep) {
+  return hkeep ? fmix64((h & ((1ull << hkeep) - 1ull)) + 0x9e3779b97f4a7c15ull) : h;
+}
+
 template <int W>
 __device__ __forceinline__ void probe_start(unsigned long long h, unsigned long long mask,
                                             unsigned long long& wi, unsigned long long& step,
@@ -399,11 +405,11 @@ __device__ __forceinline__ unsigned long long win_slot(unsigned long long wi, in
 template <int W, int SCOPE>
 __device__ __forceinline__ int table_insert(unsigned char* base, unsigned long long mask,
                                             const Key<W>& k, uint32_t& slot_out,
-                                            uint32_t& probes) {
+                                            uint32_t& probes, uint32_t hkeep = 0u) {
   constexpr int KW = Win<W>::n;
   unsigned long long wi, step;
   int j0;
-  probe_start<W>(key_hash<W>(k), mask, wi, step, j0);
+  probe_start<W>(keep_hash(key_hash<W>(k), hkeep), mask, wi, step, j0);
   const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   const unsigned long long max_iters =
       (mask + 1ull) * 2ull < kMaxProbeIters ? (mask + 1ull) * 2ull : kMaxProbeIters;
@@ -464,7 +470,8 @@ template <int W, int SCOPE, int N>
 __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned long long mask,
                                                const unsigned long long (&key)[N][W],
                                                const bool (&act)[N], uint32_t (&slot)[N],
-                                               int (&res)[N], uint32_t& probes) {
+                                               int (&res)[N], uint32_t& probes,
+                                               uint32_t hkeep = 0u) {
   constexpr int KW = Win<W>::n;
   const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   const unsigned long long max_iters =
@@ -485,7 +492,7 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
       Key<W> k;
 #pragma unroll
       for (int q = 0; q < W; ++q) k.w[q] = key[n][q];
-      probe_start<W>(key_hash<W>(k), mask, wi[n], step[n], j0[n]);
+      probe_start<W>(keep_hash(key_hash<W>(k), hkeep), mask, wi[n], step[n], j0[n]);
     }
   }
   for (unsigned long long it = 0; it < max_iters; ++it) {
@@ -557,11 +564,11 @@ __device__ __forceinline__ void table_insert_n(unsigned char* base, unsigned lon
 // Lookup only (after the exploration finished; plain loads).
 template <int W>
 __device__ __forceinline__ uint32_t table_find(unsigned char* base, unsigned long long mask,
-                                               const Key<W>& k) {
+                                               const Key<W>& k, uint32_t hkeep = 0u) {
   constexpr int KW = Win<W>::n;
   unsigned long long wi, step;
   int j0;
-  probe_start<W>(key_hash<W>(k), mask, wi, step, j0);
+  probe_start<W>(keep_hash(key_hash<W>(k), hkeep), mask, wi, step, j0);
   const unsigned long long nwin_mask = (mask + 1ull) / KW - 1ull;
   for (unsigned long long it = 0; it <= nwin_mask; ++it) {
     for (int j = 0; j < KW; ++j) {

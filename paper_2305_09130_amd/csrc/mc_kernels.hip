@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_seed(QueryArgs a, Seed* seeds, Entry<W>
     r.cfg = a.n_cfg;
     const Key<W> k = encode<W>(r, a.L);
     uint32_t slot = kParentNone;
-    const int res = table_insert<W, kScopeAgent>(a.table, a.mask, k, slot, probes);
+    const int res = table_insert<W, kScopeAgent>(a.table, a.mask, k, slot, probes, a.hkeep);
     if (res != kInsNew) set_error(a.ctrl, kDevErrTableFull);
     else *slot_parent<W>(a.table, slot) = kParentRoot;
     s_root = slot;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_seed(QueryArgs a, Seed* seeds, Entry<W>
     s.pending = a.cfgs[c].n;
     const Key<W> k = encode<W>(s, a.L);
     uint32_t slot = kParentNone;
-    const int res = table_insert<W, kScopeAgent>(a.table, a.mask, k, slot, probes);
+    const int res = table_insert<W, kScopeAgent>(a.table, a.mask, k, slot, probes, a.hkeep);
     if (res != kInsNew) {
       set_error(a.ctrl, kDevErrTableFull);
       slot = kParentNone;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
   const uint32_t n_in = s_n_in;
   const int m = q.L.m;
   unsigned long long n_states = 0, n_terms = 0, n_edges = 0, n_dups = 0, depth_max = 0;
-  uint32_t probes = 0;
+  uint32_t probes = 0, max_probe = 0;
   for (uint32_t base = blockIdx.x * BLOCK; base < n_in; base += gridDim.x * BLOCK) {
     if (threadIdx.x == 0) s_cnt = 0u;
     __syncthreads();
@@ -238,7 +238,9 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
         for (int w = 0; w < W; ++w) k.w[w] = s_key[t][w];
         dep = s_dep[t];
         ++n_edges;
-        const int res = table_insert<W, kScopeAgent>(q.table, q.mask, k, slot, probes);
+        const uint32_t p0 = probes;
+        const int res = table_insert<W, kScopeAgent>(q.table, q.mask, k, slot, probes, q.hkeep);
+        max_probe = probes - p0 > max_probe ? probes - p0 : max_probe;
         if (res == kInsFail) {
           set_error(q.ctrl, kDevErrTableFull);
         } else if (res == kInsNew) {
@@ -275,6 +277,8 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
     __syncthreads();
   }
   flush_counters(q.ctrl, n_states, n_terms, n_edges, n_dups, probes, depth_max);
+  const unsigned long long mp = wave_max(max_probe);
+  if (lane_id() == 0 && mp) atomicMax(&q.ctrl->max_probe, (unsigned int)mp);
 }
 
 // ---- persistent super-step engine ------------------------------------------------------
@@ -793,7 +797,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     sh.stop_item = kNoItem;
     sh.cut = chain_slice ? pt.r1 : kNoClock;
     sh.pr = (md.prune || sh.cut != kNoClock) ? 1u : 0u;
-    sh.T = min(prune_T(md), sh.cut);
+    sh.T = md.prune ? min(prune_T(md), sh.cut) : sh.cut;
     const Seed sd = md.seeds[c];
     const uint32_t round_dep = (uint32_t)m + r.b;  // m dispatches, b advances
     if (!chain_slice && pt.r1 != kRoundsToEnd) {
@@ -846,7 +850,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           const Key<W> k = encode<W>(x, L);
 #pragma unroll
           for (int w = 0; w < W; ++w) k0[w] = k.w[w];
-          const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot0, tl.probes);
+          const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot0, tl.probes, md.hkeep);
           if (res == kInsFail) {
             set_error(md.ctrl, kDevErrTableFull);
             sh.fcount[0] = 0u;
@@ -866,7 +870,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           Key<W> k;
 #pragma unroll
           for (int w = 0; w < W; ++w) k.w[w] = k0[w];
-          const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot0, tl.probes);
+          const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot0, tl.probes, md.hkeep);
           if (res == kInsFail) {
             set_error(md.ctrl, kDevErrTableFull);
             sh.fcount[0] = 0u;
@@ -910,7 +914,9 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     for (uint32_t fi = 0; fi < nf; ++fi) {
       // ---- segments of this super-step (one thread builds them) ----
       if (tid == 0) {
-        sh.T = min(prune_T(md), sh.cut);
+        // the query's threshold (with branch and bound the incumbent), capped by a chain
+        // slice's end; md.T means nothing when the query does not prune
+        sh.T = md.prune ? min(prune_T(md), sh.cut) : sh.cut;
         Key<W> ck;
 #pragma unroll
         for (int w = 0; w < W; ++w) ck.w[w] = sh.fkey[cur][fi][w];
@@ -1065,7 +1071,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
               } else if (!(sh.pr && end_clock > sh.T)) {
                 // shared with the next block: agent-scope ordering
                 uint32_t slot = kParentNone;
-                const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, tl.probes);
+                const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, tl.probes, md.hkeep);
                 ++tl.edges;
                 if (res == kInsFail) {
                   set_error(md.ctrl, kDevErrTableFull);
@@ -1202,9 +1208,11 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         // a chain slice shares its last state with the next slice's workgroup: its
         // inserts are at device scope
         if (chain_slice)
-          table_insert_n<W, kScopeAgent, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+          table_insert_n<W, kScopeAgent, NI>(md.table, md.mask, keys, act, slot, res, tl.probes,
+                                              md.hkeep);
         else
-          table_insert_n<W, kScopeWG, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+          table_insert_n<W, kScopeWG, NI>(md.table, md.mask, keys, act, slot, res, tl.probes,
+                                           md.hkeep);
         tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
         bool fresh[NI], cutlink[NI];
         Item<W> it[NI];  // bookkeeping of the batch's states, recomputed without the keys
@@ -1413,7 +1421,8 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
     uint32_t slot[NI];
     int res[NI];
     const uint32_t p0 = tl.probes;
-    table_insert_n<W, kScopeAgent, NI>(md.table, md.mask, keys, act, slot, res, tl.probes);
+    table_insert_n<W, kScopeAgent, NI>(md.table, md.mask, keys, act, slot, res, tl.probes,
+                                              md.hkeep);
     tl.max_probe = (tl.probes - p0) > tl.max_probe ? (tl.probes - p0) : tl.max_probe;
     bool fresh[NI];
 #pragma unroll
@@ -1551,7 +1560,7 @@ __device__ void seed_model(const ModelDev& md) {
     r.cfg = md.n_cfg;
     const Key<W> k = encode<W>(r, md.L);
     uint32_t slot = kParentNone;
-    const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes);
+    const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes, md.hkeep);
     if (res != kInsNew) set_error(md.ctrl, kDevErrTableFull);
     else *slot_parent<W>(md.table, slot) = kParentRoot;
     s_root = slot;
@@ -1567,7 +1576,7 @@ __device__ void seed_model(const ModelDev& md) {
     s.pending = md.cfgs[c].n;
     const Key<W> k = encode<W>(s, md.L);
     uint32_t slot = kParentNone;
-    const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes);
+    const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes, md.hkeep);
     if (res != kInsNew) {
       set_error(md.ctrl, kDevErrTableFull);
       slot = kParentNone;
@@ -1660,7 +1669,7 @@ __global__ __launch_bounds__(256) void k_count_le(const unsigned char* __restric
 
 template <int W>
 __global__ void k_find(QueryArgs a, Key<W> k) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctrl->target_slot = table_find<W>(a.table, a.mask, k);
+  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctrl->target_slot = table_find<W>(a.table, a.mask, k, a.hkeep);
 }
 
 // Follows parent slots from the target to the root, writing keys terminal-first.  The
@@ -1702,7 +1711,7 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
           leaf.rem[u] = r.d;
         }
       leaf.clock = x.clock - (r.d - rem);
-      jmp = rem ? table_find<W>(a.table, a.mask, encode<W>(leaf, L)) : kParentNone;
+      jmp = rem ? table_find<W>(a.table, a.mask, encode<W>(leaf, L), a.hkeep) : kParentNone;
       if (jmp == kParentNone) {
         bad = true;
         break;

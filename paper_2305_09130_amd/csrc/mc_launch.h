@@ -20,6 +20,7 @@ struct QueryArgs {
   uint32_t prune;           // check(T): drop states with clock > T
   uint32_t T;
   uint32_t max_clock;       // bound of the packed clock field
+  uint32_t hkeep;           // bits of the key hash kept (0 = all; testing only)
 };
 
 // Keys each thread of the persistent kernel inserts per round trip: 1 or 2 as asked,
@@ -74,7 +75,8 @@ struct ModelDev {
   uint32_t bb;        // branch and bound: prune at min(T, ctrl->bound), every new
                       // terminal lowers ctrl->bound
   PartState* pstate;  // one per partition when partitions may yield, else null
-  unsigned long long pad2;
+  uint32_t hkeep;     // bits of the key hash kept (0 = all; testing only)
+  uint32_t pad2;
 };
 
 // One partition of a persistent launch: rounds [r0, r1) of one configuration's subgraph

@@ -190,3 +190,11 @@ def test_peak_library_exports_its_header():
 def test_abort_code(mc):
     assert mc.MC_E_ABORTED == -11
     assert "abort" in mc.mc_strerror(mc.MC_E_ABORTED)
+
+
+def test_test_hash_bits_bounded(mc):
+    m = workloads.reduction_g256()
+    assert mc.mc_workspace_bytes(m, mc.make_opts(test_hash_bits=24)) > 0
+    with pytest.raises(mc.McError) as e:
+        mc.mc_workspace_bytes(m, mc.make_opts(test_hash_bits=25))
+    assert e.value.code == mc.MC_E_INVAL
