@@ -492,6 +492,7 @@ def serve_engine(mc, torch, pool, qs, arr, no_reuse: bool) -> dict:
     lat = []
     base_ns = None
     reuse = [0, 0, 0]
+    by_kind = {0: [], 1: [], 2: []}  # latency and admission wait per way of service
     for k, t in enumerate(tickets):
         r = e.mc_engine_poll(t)
         assert r is not None and r["status"] == 0
@@ -499,14 +500,30 @@ def serve_engine(mc, torch, pool, qs, arr, no_reuse: bool) -> dict:
         if base_ns is None:
             base_ns = r["submit_ns"] - int(arr[0] * 1e9)
         lat.append((r["done_ns"] - base_ns) * 1e-9 - arr[k])
+        by_kind[r["reuse"]].append((lat[-1], (r["admit_ns"] - r["submit_ns"]) * 1e-9, k))
     e.close()
     torch.cuda.empty_cache()
+    first = [x for k, x in enumerate(lat) if k < 100]
     lat.sort()
+
+    def q(xs, p):
+        xs = sorted(xs)
+        return 1e3 * xs[min(len(xs) - 1, int(p * len(xs)))] if xs else None
+
+    names = {0: "explored_fresh", 1: "resumed", 2: "answered_from_resident"}
     return {"queries_per_s": n_queries / wall,
             "p50_ms": 1e3 * lat[min(len(lat) - 1, int(0.5 * len(lat)))],
             "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
             "explored_fresh": reuse[0], "resumed": reuse[1], "answered_from_resident": reuse[2],
-            "hit_rate": (reuse[1] + reuse[2]) / n_queries}
+            "hit_rate": (reuse[1] + reuse[2]) / n_queries,
+            "first_100_p99_ms": q(first, 0.99),
+            "by_service": {names[k]: {"n": len(v), "p50_ms": q([x[0] for x in v], 0.5),
+                                      "p99_ms": q([x[0] for x in v], 0.99),
+                                      "max_ms": q([x[0] for x in v], 1.0),
+                                      "admit_wait_p99_ms": q([x[1] for x in v], 0.99),
+                                      "mean_arrival_index":
+                                          sum(x[2] for x in v) / len(v) if v else None}
+                           for k, v in by_kind.items()}}
 
 
 def peak_leg(buf_bytes: int) -> dict:

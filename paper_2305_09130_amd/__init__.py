@@ -326,20 +326,25 @@ class Model:
         self._desc, self._params = make_desc(model)
         self._opts = make_opts(engine, block, log2_slots, load_factor, grid, batch_items,
                                lane_items, part_states, test_hash_bits)
-        nbytes = mc_workspace_bytes(model, self._opts)
         self.device = torch.device(device)
         if workspace is None:
-            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        elif workspace.numel() < nbytes or workspace.dtype != torch.uint8:
-            raise ValueError(f"workspace needs {nbytes} bytes of uint8")
+            workspace = torch.empty(mc_workspace_bytes(model, self._opts), dtype=torch.uint8,
+                                    device=self.device)
+        elif workspace.dtype != torch.uint8:
+            raise ValueError("the workspace must be a uint8 tensor")
         self.workspace = workspace
         nbytes = workspace.numel()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        _check("mc_model_load",
-               _lib.mc_model_load(ctypes.byref(self._desc), ctypes.byref(self._opts),
-                                  ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
-                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        # a given workspace is sized by the load itself (MC_E_NOMEM when too small)
+        rc = _lib.mc_model_load(ctypes.byref(self._desc), ctypes.byref(self._opts),
+                                ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc == MC_E_NOMEM:
+            need = mc_workspace_bytes(model, self._opts)
+            if nbytes < need:
+                raise ValueError(f"workspace needs {need} bytes of uint8, has {nbytes}")
+        _check("mc_model_load", rc)
         self._h = h
         self.last_stats: dict = {}
 

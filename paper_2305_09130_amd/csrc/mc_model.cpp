@@ -13,6 +13,7 @@
 #include "mc_model.h"
 
 #include <algorithm>
+#include <numeric>
 #include <atomic>
 #include <cstring>
 #include <thread>
@@ -169,14 +170,42 @@ void tail_walk(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T, uint
 
 }  // namespace
 
-ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T) {
+ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T,
+                        std::vector<ChainCut>* cuts) {
   ChainCount out;
   uint64_t t = 0, p = r.n, dep = 0;
   UnitRun ur[kMaxCU];
   uint32_t busy = 0;
+  const uint32_t all = (1u << m) - 1u;
+  uint64_t spacing = kCutSpacing, last = 0;
   out.states = 1;  // the SELECT state, clock 0
+  const auto record = [&](const ChainCut& c) {
+    if (c.states - last < spacing) return;
+    if (cuts->size() == kMaxCuts) {  // keep every other candidate, twice as far apart
+      size_t k = 0;
+      for (size_t i = 1; i < cuts->size(); i += 2) (*cuts)[k++] = (*cuts)[i];
+      cuts->resize(k);
+      spacing *= 2;
+    }
+    cuts->push_back(c);
+    last = c.states;
+  };
+  // While work is pending every unit restarts at each of its workgroup ends, so unit u
+  // runs workgroups back to back from clock 0 and all units end together at the period
+  // P = lcm(sp) * d, where every unit is idle again with Wp = sum(lcm / sp[u]) fewer
+  // workgroups pending.  Each later period that finds at least Wp pending repeats the
+  // first one shifted by P in clock, and by its states and edges: it is not walked.
+  uint64_t lcm = 1;
+  for (uint32_t u = 0; u < m && lcm <= kMaxPeriodLcm; ++u)
+    lcm = lcm / std::gcd<uint64_t>(lcm, sp[u]) * sp[u];
+  uint64_t Wp = 0;
+  for (uint32_t u = 0; u < m; ++u) Wp += lcm / sp[u];
+  const bool jump = T == ~0ull && lcm <= kMaxPeriodLcm && (uint64_t)r.n >= 2 * Wp;
+  const uint64_t P = lcm * r.d;
+  bool jumped = false;
+  std::vector<ChainCut> period;  // cut points of the first period
   for (;;) {
-    const uint32_t freem = ((1u << m) - 1u) & ~busy;
+    const uint32_t freem = all & ~busy;
     const uint32_t f = (uint32_t)__builtin_popcount(freem);
     if (p > 0 && f > 0) {
       if (p >= f) {
@@ -215,36 +244,35 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
     t = advance_units(r, sp, m, ur, &busy);
     ++dep;
     if (t <= T) ++out.states;
+    // every unit still busy after the advance (no workgroup ended at t) and work pending:
+    // the state at t lies on every run of the configuration
+    if (cuts && busy == all) {
+      if (jump && !jumped) period.push_back(ChainCut{t, dep + 1, out.states});
+      record(ChainCut{t, dep + 1, out.states});  // depth from the root
+    }
+    if (jump && !jumped && t == P) {  // the first period ends: every unit is idle
+      jumped = true;
+      const uint64_t J = p / Wp, dS = out.states - 1, dD = dep;
+      if (cuts)
+        for (uint64_t j = 1; j <= J; ++j)
+          for (const ChainCut& c : period)
+            record(ChainCut{c.t + j * P, c.depth + j * dD, c.states + j * dS});
+      out.states += J * dS;
+      dep += J * dD;
+      t += J * P;
+      p -= J * Wp;
+    }
   }
 }
 
-void chain_cuts(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t target,
+void chain_cuts(const std::vector<ChainCut>& cands, uint64_t target,
                 std::vector<ChainCut>* out) {
-  const uint32_t all = (1u << m) - 1u;
-  uint64_t t = 0, p = r.n, dep = 1, states = 1, last = 0;  // SELECT at depth 1
-  UnitRun ur[kMaxCU];
-  uint32_t busy = 0;
-  for (;;) {
-    const uint32_t freem = all & ~busy;
-    const uint32_t f = (uint32_t)__builtin_popcount(freem);
-    if (f > 0) {
-      if (p < f) return;  // the tails begin: no cut past here
-      states += (1ull << f) - 1;
-      dep += f;
-      p -= f;
-      for (uint32_t u = 0; u < m; ++u)
-        if ((freem >> u) & 1u) start_unit(r, sp, ur, u, t);
-      busy = all;
+  uint64_t last = 0;
+  for (const ChainCut& c : cands)
+    if (c.states - last >= target) {
+      out->push_back(c);
+      last = c.states;
     }
-    if (p == 0) return;
-    t = advance_units(r, sp, m, ur, &busy);
-    ++dep;
-    ++states;
-    if (busy == all && states - last >= target) {  // no workgroup ended at t
-      out->push_back(ChainCut{t, dep, states});
-      last = states;
-    }
-  }
 }
 
 int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
@@ -277,6 +305,7 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   h->cfgs.assign(d->n_cfg, CfgRec{});
   h->general = false;
   h->cfg_states.assign(d->n_cfg, 0);
+  h->cut_cands.clear();
   const uint32_t m = h->m;
   uint64_t total = 1, depth = 0, fb = d->n_cfg;
   uint64_t widest_sum = 0;
@@ -349,9 +378,10 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
     widest_sum += w;
   }
   if (h->hetero) {
+    h->cut_cands.assign(d->n_cfg, {});
     // the walks are independent: long ones share the host's cores
     const auto walk = [&](uint32_t c) {
-      const ChainCount cc = walk_unequal(h->cfgs[c], h->speed, m, ~0ull);
+      const ChainCount cc = walk_unequal(h->cfgs[c], h->speed, m, ~0ull, &h->cut_cands[c]);
       c_tc[c] = cc.max_clock;  // the latest terminal clock of this configuration
       h->cfg_states[c] = cc.states;
       c_depth[c] = 1 + cc.depth;
@@ -447,7 +477,7 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
     const CfgRec& r = h.cfgs[c];
     if (chains) {
       std::vector<ChainCut> cuts;
-      if (h.cfg_states[c] >= 2 * chain_target) chain_cuts(r, h.speed, h.m, chain_target, &cuts);
+      if (h.cfg_states[c] >= 2 * chain_target) chain_cuts(h.cut_cands[c], chain_target, &cuts);
       if (cuts.empty()) {
         out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
         continue;

@@ -74,6 +74,18 @@ struct CfgRec {
 };
 static_assert(sizeof(CfgRec) == 128, "CfgRec layout");
 
+// Cut points of a configuration's determined part on units of unequal speed: instants t
+// at which every unit is busy, work is pending and no workgroup ends (so the state at t
+// has a single predecessor chain and lies on every run), with the state's depth from the
+// root and the states counted up to it.
+struct ChainCut {
+  uint64_t t = 0, depth = 0, states = 0;
+};
+constexpr uint64_t kCutSpacing = 32;  // least distance between recorded cut points, in states
+constexpr size_t kMaxCuts = 4096;     // most cut points recorded per configuration
+constexpr uint64_t kMaxPeriodLcm = 1u << 12;  // longest period (in workgroups of speed 1)
+                                              // that the walk repeats rather than walks
+
 struct ModelHost {
   mc_desc desc{};
   std::vector<uint32_t> params;  // n_cfg * 4
@@ -89,6 +101,7 @@ struct ModelHost {
   uint32_t max_clock = 0;
   uint32_t max_n = 0, max_d = 0;
   std::vector<uint64_t> cfg_states;  // reachable states per configuration subgraph
+  std::vector<std::vector<ChainCut>> cut_cands;  // unequal units: cut points per configuration
   uint64_t frontier_bound = 0;   // widest BFS level
 };
 
@@ -159,22 +172,20 @@ uint64_t ends_le(const CfgRec& r, uint64_t x);
 
 // Sizes of one configuration's subgraph on units of unequal speed (sp[0..m-1]): states
 // with clock <= T (an upper bound: tails that meet are counted twice), the longest path
-// from the SELECT state, the latest terminal clock.
+// from the SELECT state, the latest terminal clock.  With `cuts`, also records cut
+// points of the determined part at least kCutSpacing states apart (at most kMaxCuts:
+// beyond that every other one is dropped and the spacing doubles).
 struct ChainCount {
   uint64_t states = 0, depth = 0, max_clock = 0;
 };
-ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T);
+ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t T,
+                        std::vector<ChainCut>* cuts = nullptr);
 // Time of the k-th operation end (0-based, k < r.b) of one workgroup.
 uint64_t end_at_host(const CfgRec& r, uint64_t k);
 
-// Cut points of a configuration's determined part on units of unequal speed, about
-// `target` states apart: instants t at which every unit is busy, work is pending and no
-// workgroup ends (so the state at t has a single predecessor chain and lies on every
-// run), with the state's depth from the root and the states counted before it.
-struct ChainCut {
-  uint64_t t = 0, depth = 0, states = 0;
-};
-void chain_cuts(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_t target,
+// The recorded cut points (in order) thinned to about `target` states apart: each one
+// kept is the first at least `target` states past the previous one kept.
+void chain_cuts(const std::vector<ChainCut>& cands, uint64_t target,
                 std::vector<ChainCut>* out);
 
 // An upper bound (exact for every configuration whose last round is not partial) on the

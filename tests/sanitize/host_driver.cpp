@@ -47,8 +47,13 @@ static void exercise(const mc_desc& d, bool valid) {
   if (h.hetero) {
     for (uint32_t c = 0; c < h.n_cfg; ++c) {
       std::vector<ChainCut> cuts;
-      chain_cuts(h.cfgs[c], h.speed, h.m, 16, &cuts);
-      for (size_t k = 1; k < cuts.size(); ++k) expect(cuts[k].t > cuts[k - 1].t, "cut order");
+      chain_cuts(h.cut_cands[c], 64, &cuts);
+      expect(h.cut_cands[c].size() <= kMaxCuts, "cut points bounded");
+      for (size_t k = 1; k < cuts.size(); ++k)
+        expect(cuts[k].t > cuts[k - 1].t && cuts[k].depth > cuts[k - 1].depth &&
+                   cuts[k].states >= cuts[k - 1].states + 64,
+               "cut order");
+      for (const ChainCut& k : cuts) expect(k.states < h.cfg_states[c], "cut inside");
     }
   }
   // the host key codec round trip on the SELECT states and a dispatched state
