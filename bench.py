@@ -79,15 +79,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str, kernel: str, src_hash: str):
+def read_traffic(workload: str, kernel: str, src_hash: str, slots: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source."""
+    on the current kernel source with a visited set of the same size."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != src_hash:
+    if d.get("kernel_source_hash") != src_hash or d.get("table_slots") != slots:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -104,6 +104,7 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
     t3 = time.perf_counter()
     holds = not g.mc_check(t_min - 1)
     st_chk = dict(g.last_stats)
+    slots = g.mc_model_info_get()["slots"]
     g.close()
     t4 = time.perf_counter()
     return {"t_min": t_min, "argmin": argmin, "trace_len": len(trace), "minimal": holds,
@@ -114,7 +115,7 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
             "min_stats": {k: st_min[k] for k in ("probes", "max_probe", "dups", "edges",
                                                  "supersteps", "batches", "critical_ns",
                                                  "critical_cfg", "parts")},
-            "parts": st_min["parts"],
+            "parts": st_min["parts"], "slots": slots,
             "breakdown_ms": {"load": 1e3 * (t1 - t0), "min_time": 1e3 * (t2 - t1),
                              "min_time_engine": st_min["engine_ns"] / 1e6,
                              "min_time_clear": st_min["clear_ns"] / 1e6,
@@ -473,6 +474,9 @@ def serve_engine(mc, torch, pool, qs, arr, no_reuse: bool) -> dict:
     e = mc.Engine(arena_bytes=24 << 30, max_active=128, max_cfg=512, block=512, slice=16,
                   no_reuse=no_reuse)
     tickets = []
+    # arrivals are offsets from t0; the library stamps completions on the same monotonic
+    # clock (CLOCK_MONOTONIC) as time.monotonic_ns
+    t0_ns = time.monotonic_ns()
     t0 = time.perf_counter()
     nxt = 0
     busy = True
@@ -490,16 +494,13 @@ def serve_engine(mc, torch, pool, qs, arr, no_reuse: bool) -> dict:
     e.drain()
     wall = time.perf_counter() - t0
     lat = []
-    base_ns = None
     reuse = [0, 0, 0]
     by_kind = {0: [], 1: [], 2: []}  # latency and admission wait per way of service
     for k, t in enumerate(tickets):
         r = e.mc_engine_poll(t)
         assert r is not None and r["status"] == 0
         reuse[r["reuse"]] += 1
-        if base_ns is None:
-            base_ns = r["submit_ns"] - int(arr[0] * 1e9)
-        lat.append((r["done_ns"] - base_ns) * 1e-9 - arr[k])
+        lat.append((r["done_ns"] - t0_ns) * 1e-9 - arr[k])
         by_kind[r["reuse"]].append((lat[-1], (r["admit_ns"] - r["submit_ns"]) * 1e-9, k))
     e.close()
     torch.cuda.empty_cache()
@@ -602,7 +603,7 @@ def main():
     algo_bytes = steps[-1]["min_states"] * bps
     achieved = algo_bytes / eng_s / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(args.workload, "k_superstep", src_hash)
+    traffic = read_traffic(args.workload, "k_superstep", src_hash, steps[-1]["slots"])
 
     legs = set(x for x in args.legs.split(",") if x)
     _progress(f"timed step done: {1e3 * elapsed / args.steps:.3f} ms/step")
@@ -665,7 +666,8 @@ def main():
                 "kernel": "k_superstep", "launch": "min_time exploration",
                 "algo_bytes_per_state": bps, "algo_bytes_per_launch": algo_bytes,
                 "states_per_launch": steps[-1]["min_states"],
-                "avg_launch_ms": eng_s * 1e3, "kernel_source_hash": src_hash}
+                "avg_launch_ms": eng_s * 1e3, "kernel_source_hash": src_hash,
+                "table_slots": steps[-1]["slots"]}
     if peak:
         # the measured random-access ceiling: random 64-byte line reads (the granule of
         # every visited-set touch) and random 64-bit CAS (one per claim)

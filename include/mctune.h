@@ -136,7 +136,9 @@ typedef struct mc_opts {
                                 critical chains of inserts then decide the launch time,
                                 else 256) */
     uint32_t log2_slots;     /* visited-set capacity 2^log2_slots (0 = from load_factor) */
-    float load_factor;       /* target states/slots when sizing (0 = 0.5) */
+    float load_factor;       /* target states/slots when sizing (0 = automatic: at most
+                                0.375 after rounding the slots up to a power of two, or
+                                0.5 where that passes 2^31 slots) */
     uint32_t grid;           /* persistent workgroups (0 = automatic) */
     uint32_t batch_items;    /* super-step engine: states generated from one frontier state
                                 before waiting for the visited set (0 = 2 x lanes) */

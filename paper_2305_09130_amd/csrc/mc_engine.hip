@@ -556,7 +556,7 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       if (r->explored && resumable(r->mh)) {
         q->mode = kResume;
         Start st{q, r, {}};
-        plan_resume(r->mh, r->T_done, &st.plan);
+        plan_resume(r->mh, r->T_done, r->parts, &st.plan);
         starts.push_back(std::move(st));
       } else {
         q->mode = kFresh;

@@ -590,17 +590,47 @@ bool word0_orders_rounds(const ModelHost& h) {
 
 bool resumable(const ModelHost& h) { return word0_orders_rounds(h); }
 
-void plan_resume(const ModelHost& h, uint64_t T_done, std::vector<PartPlan>* out) {
-  for (uint32_t c = 0; c < h.n_cfg; ++c) {
+void plan_resume(const ModelHost& h, uint64_t T_done, const std::vector<PartPlan>& fresh,
+                 std::vector<PartPlan>* out) {
+  // configurations that the fresh plan cuts into round blocks only keep those blocks past
+  // T_done; every other one resumes as one partition
+  std::vector<uint32_t> nparts(h.n_cfg, 0);
+  std::vector<uint8_t> blocks(h.n_cfg, 1), done(h.n_cfg, 0);
+  for (const PartPlan& p : fresh) {
+    if (p.cfg >= h.n_cfg) continue;
+    ++nparts[p.cfg];
+    if (p.r0 == kRunSlice || p.r0 == kChainSlice || p.j1 != 0) blocks[p.cfg] = 0;
+  }
+  const auto whole = [&](uint32_t c) {
     const CfgRec& r = h.cfgs[c];
     const uint64_t rounds = (r.n + h.m - 1) / h.m;
-    if (rounds * r.d <= T_done) continue;  // its terminals are in already
+    if (rounds * r.d <= T_done) return;  // its terminals are in already
     // round r0 starts at clock r0*d <= T_done: its start state was inserted, the states
     // of the round past T_done were not
     const uint64_t r0 = std::min<uint64_t>(T_done / r.d, rounds - 1);
     const uint64_t left = h.cfg_states[c] * (rounds - r0) / rounds + 1;
     out->push_back(PartPlan{c, (uint32_t)r0, kRoundsToEnd, left});
+  };
+  for (const PartPlan& p : fresh) {  // in the fresh plan's order (largest first)
+    const uint32_t c = p.cfg;
+    if (c >= h.n_cfg) continue;
+    if (!blocks[c] || nparts[c] < 2) {
+      if (!done[c]) whole(c);
+      done[c] = 1;
+      continue;
+    }
+    const CfgRec& r = h.cfgs[c];
+    const uint64_t rounds = (r.n + h.m - 1) / h.m;
+    if (rounds * r.d <= T_done) continue;
+    const uint64_t rs = std::min<uint64_t>(T_done / r.d, rounds - 1);
+    const uint64_t b = p.r1 == kRoundsToEnd ? rounds : p.r1;
+    if (b <= rs) continue;  // every state of the block has clock <= b*d <= T_done
+    const uint64_t a = std::max<uint64_t>(p.r0, rs);
+    const uint64_t left = p.states * (b - a) / std::max<uint64_t>(1, b - p.r0) + 1;
+    out->push_back(PartPlan{c, (uint32_t)a, p.r1, left});
   }
+  for (uint32_t c = 0; c < h.n_cfg; ++c)  // configurations absent from the fresh plan
+    if (!nparts[c]) whole(c);
 }
 
 uint64_t auto_part_states(uint64_t states, uint32_t m) {

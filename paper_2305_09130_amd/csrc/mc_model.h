@@ -158,10 +158,15 @@ bool word0_orders_rounds(const ModelHost& h);
 bool resumable(const ModelHost& h);
 
 // Partitions that continue a resumable model's exploration after every state with clock
-// <= T_done was inserted: for each configuration not yet at its terminals, rounds
-// r0 = floor(T_done / d) (its start state is in the set) to the end.  Re-exploring round
-// r0 finds its states up to T_done present and inserts the rest.
-void plan_resume(const ModelHost& h, uint64_t T_done, std::vector<PartPlan>* out);
+// <= T_done was inserted, from rounds r0 = floor(T_done / d) of each configuration not yet
+// at its terminals (its start state is in the set; re-exploring round r0 finds its states
+// up to T_done present and inserts the rest).  A configuration that the fresh plan `fresh`
+// cuts into round blocks keeps the blocks that end past round r0, the one holding r0
+// starting there, so the continuation is as parallel as the fresh exploration; any other
+// configuration continues as one partition.  Never more partitions than the fresh plan
+// has (or than configurations, if that is more).
+void plan_resume(const ModelHost& h, uint64_t T_done, const std::vector<PartPlan>& fresh,
+                 std::vector<PartPlan>* out);
 
 // Default target states per partition for a launch exploring `states` states in total
 // on models of m units.

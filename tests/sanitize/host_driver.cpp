@@ -5,6 +5,7 @@
 // Built with AddressSanitizer + UndefinedBehaviorSanitizer, and separately with
 // ThreadSanitizer, by tests/test_sanitizers.py; test infrastructure only.
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -39,9 +40,31 @@ static void exercise(const mc_desc& d, bool valid) {
     expect(n >= last && n <= h.states, "count_le_bound monotone and bounded");
     last = n;
     if (resumable(h)) {
-      std::vector<PartPlan> rp;
-      plan_resume(h, T, &rp);
-      expect(rp.size() <= h.n_cfg, "resume plan size");
+      for (uint64_t target : {0ull, 64ull, 4096ull}) {
+        std::vector<PartPlan> fresh, rp;
+        plan_parts(h, target, &fresh);
+        plan_resume(h, T, fresh, &rp);
+        expect(rp.size() <= std::max<size_t>(fresh.size(), h.n_cfg), "resume plan size");
+        // per configuration: the resumed rounds are [floor(T/d), rounds), disjoint, covered
+        for (uint32_t c = 0; c < h.n_cfg; ++c) {
+          const CfgRec& r = h.cfgs[c];
+          const uint64_t rounds = (r.n + h.m - 1) / h.m;
+          std::vector<std::pair<uint64_t, uint64_t>> iv;
+          for (const PartPlan& p : rp)
+            if (p.cfg == c) iv.push_back({p.r0, p.r1 == kRoundsToEnd ? rounds : p.r1});
+          if (rounds * r.d <= T) {
+            expect(iv.empty(), "finished configuration resumed");
+            continue;
+          }
+          std::sort(iv.begin(), iv.end());
+          uint64_t at = std::min<uint64_t>(T / r.d, rounds - 1);
+          for (const auto& x : iv) {
+            expect(x.first == at && x.second > x.first, "resumed rounds contiguous");
+            at = x.second;
+          }
+          expect(at == rounds, "resumed rounds reach the end");
+        }
+      }
     }
   }
   if (h.hetero) {

@@ -54,9 +54,12 @@ def test_describe_tiny_sweep(mc):
 def test_workspace_sizes(mc):
     m = workloads.matmul_128_vw()
     n = mc.mc_workspace_bytes(m)
-    # 58M states at load factor <= 0.5 in 16-byte slots (one key word): 2^27 slots = 2 GiB
-    assert 2 * 2**30 <= n < 2.5 * 2**30
-    small = mc.mc_workspace_bytes(m, mc.make_opts(load_factor=0.25))
+    # 58M states at the automatic load factor (at most 3/8 after rounding up to a power of
+    # two) in 16-byte slots (one key word): 2^28 slots = 4 GiB
+    assert 4 * 2**30 <= n < 4.5 * 2**30
+    half = mc.mc_workspace_bytes(m, mc.make_opts(load_factor=0.5))
+    assert 2 * 2**30 <= half < 2.5 * 2**30
+    small = mc.mc_workspace_bytes(m, mc.make_opts(load_factor=0.125))
     assert small > n
 
 
