@@ -116,6 +116,8 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
                                                  "supersteps", "batches", "critical_ns",
                                                  "critical_cfg", "parts")},
             "parts": st_min["parts"], "slots": slots,
+            "check_stats": {k: st_chk[k] for k in ("states", "probes", "max_probe", "supersteps",
+                                                   "critical_ns", "critical_cfg", "parts")},
             "breakdown_ms": {"load": 1e3 * (t1 - t0), "min_time": 1e3 * (t2 - t1),
                              "min_time_engine": st_min["engine_ns"] / 1e6,
                              "min_time_clear": st_min["clear_ns"] / 1e6,
@@ -707,6 +709,7 @@ def main():
                               for k in steps[0]["breakdown_ms"]},
         "partitions": steps[0]["parts"],
         "min_time_stats": steps[-1]["min_stats"],
+        "check_stats": steps[-1]["check_stats"],
         "latency_ms": {"p50": 1e3 * pct(0.5), "p99": 1e3 * pct(0.99)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -620,6 +620,9 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
   return v;
 }
 
+// Records the first error of a query (later ones keep it).
+__device__ __forceinline__ void set_error(Ctrl* ctrl, unsigned int e) { atomicCAS(&ctrl->error, 0u, e); }
+
 // splitmix64 (Steele, Lea, Flood 2014)
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
   z += 0x9E3779B97F4A7C15ull;
