@@ -177,6 +177,10 @@ typedef struct mc_stats {
     uint64_t critical_cfg;   /* the configuration of that partition */
     uint64_t parts;          /* partitions of the persistent launch (configurations, or
                                 blocks of whole rounds of them) */
+    uint64_t cas_fail;       /* probes whose compare-and-swap met a slot holding another
+                                state: every insert ends on one deciding probe (its claim,
+                                or its own key found), so this is probes - new states -
+                                dups of the query's exploration (0 if it explored nothing) */
 } mc_stats;
 
 typedef struct mc_model_info {

@@ -58,7 +58,8 @@ class McStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("states", "levels", "terminals", "edges", "dups", "probes", "launches",
                  "explore_ns", "total_ns", "clear_ns", "engine_ns", "supersteps",
-                 "batches", "max_probe", "critical_ns", "critical_cfg", "parts")]
+                 "batches", "max_probe", "critical_ns", "critical_cfg", "parts",
+                 "cas_fail")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

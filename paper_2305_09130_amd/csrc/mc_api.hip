@@ -54,6 +54,12 @@ uint64_t table_slots(uint64_t states, float load_factor) {
   return s <= (1ull << 31) ? s : next_pow2(2 * states + 1);
 }
 
+// Failed claims of an exploration: every insert ends on one deciding probe (a claim or
+// its own key found), the others met a slot holding another state.
+uint64_t cas_fails(uint64_t probes, uint64_t states, uint64_t dups) {
+  return probes > states + dups ? probes - states - dups : 0u;
+}
+
 int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) {
   if (o.test_hash_bits > 24u) return MC_E_INVAL;
   uint64_t slots;
@@ -151,7 +157,8 @@ struct mc_model {
   uint32_t* tc = nullptr;
   CfgRec* cfgs = nullptr;
   Part* parts = nullptr;
-  uint32_t n_parts = 0;
+  uint32_t n_parts = 0;  // partitions of the load's plan (the capacity of `parts`)
+  uint32_t q_parts = 0;  // partitions of the last query's launch
   ModelDev* dmd = nullptr;
   unsigned int* head = nullptr;
   unsigned char* pin = nullptr;  // pooled pinned block: hctrl, hpoll, hmd, tc_host, uploads
@@ -277,11 +284,41 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   }
   h->q_slots = q_slots;
   h->resident = false;
-  if (h->parts_resumed) {
+  // A check(T) explores only the states with clock <= T.  The load's plan cuts
+  // configurations into blocks sized for the whole exploration, so one block can hold most
+  // of what a check explores and decide its time alone; on models cut into round blocks a
+  // check gets its own plan, sized for the states up to T, without the blocks that start
+  // past T.
+  uint32_t n_parts = h->n_parts;
+  bool own_plan = false;
+  if (prune && !bb && h->opts.engine == MC_ENGINE_SUPERSTEP && h->opts.part_states == 0 &&
+      !h->mh.hetero && word0_orders_rounds(h->mh)) {
+    std::vector<PartPlan> plan, keep;
+    plan_parts(h->mh, auto_part_states(count_le_bound(h->mh, T), h->mh.m), &plan);
+    for (const PartPlan& p : plan)
+      if (p.r0 == kRunSlice || (uint64_t)p.r0 * h->mh.cfgs[p.cfg].d <= T) keep.push_back(p);
+    if (keep.size() <= h->n_parts) {
+      std::stable_sort(keep.begin(), keep.end(), [](const PartPlan& a, const PartPlan& b) {
+        return a.states > b.states;
+      });
+      std::vector<Part> parts(keep.size());
+      for (size_t i = 0; i < keep.size(); ++i)
+        parts[i] = Part{0u, keep[i].cfg, keep[i].r0, keep[i].r1, (uint32_t)i, keep[i].j0,
+                        keep[i].j1, 0u};
+      if (!parts.empty())
+        HIPCHK(hipMemcpyAsync(h->parts, parts.data(), sizeof(Part) * parts.size(),
+                              hipMemcpyHostToDevice, s));
+      n_parts = (uint32_t)parts.size();
+      own_plan = true;
+      h->parts_resumed = true;  // the load's plan goes back before the next other query
+    }
+  }
+  if (!own_plan && h->parts_resumed) {
     HIPCHK(hipMemcpyAsync(h->parts, h->parts_host.data(), sizeof(Part) * h->parts_host.size(),
                           hipMemcpyHostToDevice, s));
     h->parts_resumed = false;
   }
+  h->q_parts = n_parts;
   bool cleared = false;
   if (h->dirty) {
     HIPCHK(ev_record(h->ev[0], s));
@@ -305,7 +342,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     md.prune = prune ? 1u : 0u;
     md.T = T;
     md.max_clock = h->mh.max_clock;
-    md.n_parts = h->n_parts;
+    md.n_parts = n_parts;
     md.bb = bb ? 1u : 0u;
     md.pstate = nullptr;
     md.hkeep = h->opts.test_hash_bits;
@@ -318,8 +355,8 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     PartQueue pq;
     pq.models = h->dmd;
     pq.parts = h->parts;
-    pq.n_parts = h->n_parts;
-    const uint32_t li = h->opts.lane_items || h->n_parts < kManyParts
+    pq.n_parts = n_parts;
+    const uint32_t li = h->opts.lane_items || n_parts < kManyParts
                             ? lane_items_for(h->opts.lane_items, h->mh.W)
                             : 1u;
     pq.batch_items = h->opts.batch_items ? h->opts.batch_items : 2u * li * h->opts.block;
@@ -329,7 +366,8 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     pq.yielded = nullptr;
     pq.n_yielded = nullptr;
     pq.abort = h->habort;
-    const uint32_t grid = h->opts.grid ? h->opts.grid : std::min<uint32_t>(h->n_parts, 4096u);
+    const uint32_t grid =
+        h->opts.grid ? h->opts.grid : std::max<uint32_t>(1u, std::min<uint32_t>(n_parts, 4096u));
     HIPCHK(launch_super(s, h->mh.W, grid, h->opts.block, li, pq, h->mh.general, h->mh.hetero));
     HIPCHK(ev_record(h->ev[5], s));
     launches = 2;
@@ -382,7 +420,8 @@ int finish_query(mc_model* h, std::chrono::steady_clock::time_point t0, bool cle
     st->max_probe = h->hctrl->max_probe;
     st->critical_ns = h->hctrl->crit_ticks * 10ull;  // 100 MHz device clock
     st->critical_cfg = h->hctrl->crit_part;
-    st->parts = h->opts.engine == MC_ENGINE_SUPERSTEP ? h->n_parts : 0u;
+    st->parts = h->opts.engine == MC_ENGINE_SUPERSTEP ? h->q_parts : 0u;
+    st->cas_fail = cas_fails(st->probes, st->states, st->dups);
     st->total_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                        std::chrono::steady_clock::now() - t0)
                        .count();
@@ -420,6 +459,7 @@ int run_resume(mc_model* h, uint32_t T, mc_stats* st) {
   md.T = T;
   md.bb = 0u;
   md.n_parts = (uint32_t)parts.size();
+  h->q_parts = md.n_parts;
   HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
   HIPCHK(launch_resume_models(s, h->dmd, 1, h->head, 1));
   HIPCHK(ev_record(h->ev[2], s));

@@ -419,6 +419,7 @@ int mc_batch_min_time(mc_batch* b, uint32_t* t_min, uint64_t* states, mc_stats* 
     acc.edges += c->edges;
     acc.dups += c->dups;
     acc.probes += c->probes;
+    acc.cas_fail += c->probes > c->states + c->dups ? c->probes - c->states - c->dups : 0u;
     acc.levels = std::max<uint64_t>(acc.levels, c->max_depth + 1);
     acc.supersteps += c->supersteps;
     acc.batches += c->chunks;

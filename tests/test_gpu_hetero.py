@@ -38,6 +38,12 @@ def check_min_time(g, model, r, engine):
     assert st["terminals"] == r["terminals"]
     if engine == ENGINES["level"]:
         assert st["levels"] == r["levels"]
+    else:
+        # the super-step engine reports each state's depth at its first claim: at least its
+        # BFS depth, at most the longest path to it
+        assert r["levels"] <= st["levels"] <= g.mc_model_info_get()["max_depth"] + 1
+    assert st["probes"] >= st["states"] + st["dups"]
+    assert st["cas_fail"] == st["probes"] - st["states"] - st["dups"]
     assert g.mc_terminal_clocks() == r["tc"]
     oracle.check_trace(model, g.mc_trace(), target_clock=r["t_min"], cfgs=r["argmin"])
 

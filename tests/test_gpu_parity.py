@@ -54,9 +54,17 @@ def ref(model, T=None):
     return _oracle_cached((_freeze(model), T))
 
 
+def check_accounting(st):
+    """Every insert ends on one deciding probe (a claim, or its own key found): the other
+    probes met slots holding other states."""
+    assert st["probes"] >= st["states"] + st["dups"], st
+    assert st["cas_fail"] == st["probes"] - st["states"] - st["dups"]
+
+
 def check_min_time(mc, g, model, r):
     t_min, argmin = g.mc_min_time()
     st = g.last_stats
+    check_accounting(st)
     assert (t_min, argmin) == (r["t_min"], r["argmin"])
     assert st["states"] == r["reachable"]
     assert st["levels"] == r["levels"]
@@ -72,6 +80,7 @@ def check_threshold(mc, g, model, T):
     r = ref(model, T)
     v = g.mc_check(T)
     st = g.last_stats
+    check_accounting(st)
     assert v == r["violated"], (T, v, r["violated"])
     assert st["states"] == r["reachable"], (T, st["states"], r["reachable"])
     assert g.mc_terminal_clocks() == r["tc"]
@@ -220,6 +229,11 @@ def test_matmul128_vw_full_size(mc, block):
         # the benchmark's second query: check(T_min - 1) holds, with count_T exact
         assert g.mc_check(s["t_min"] - 1) is False
         assert g.last_stats["states"] == cf.count_le(model, s["t_min"] - 1)
+        # the check ran on its own plan (blocks sized for its states, none past T)
+        assert len(model["params"]) <= g.last_stats["parts"] < 3828
+        # and the load's plan is back for the next full query
+        assert g.mc_min_time() == (t_min, argmin)
+        assert g.last_stats["parts"] == 3828 and g.last_stats["states"] == s["reachable"]
     g.close()
 
 

@@ -52,8 +52,10 @@ def test_low_entropy_hash(mc, bits, engine):
             assert (t_min, argmin) == (r["t_min"], r["argmin"])
             assert st["states"] == r["reachable"]
             assert g.mc_terminal_clocks() == r["tc"]
+            assert st["cas_fail"] == st["probes"] - st["states"] - st["dups"] >= 0
             if bits == 3:
                 assert st["max_probe"] > 16   # the chains really are long
+                assert st["cas_fail"] > st["states"]
             oracle.check_trace(model, g.mc_trace(), target_clock=r["t_min"], cfgs=r["argmin"])
             q = oracle.explore(model, T=r["t_min"] - 1, trace=False)
             assert g.mc_check(r["t_min"] - 1) is False
