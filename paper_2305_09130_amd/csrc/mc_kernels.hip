@@ -1267,11 +1267,17 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
           const uint32_t segf = x.sgi ? sh.segfslot[x.sgi] : sg.fslot;
           uint32_t par, jmp = kParentNone;
           // the interior states of a lock-step run from a dispatch leaf store no links:
-          // the trace derives the leaf from such a state's key (busy units back at d)
-          const bool linkless = !x.is_clos && sg.lock && sg.kstar && x.j + 1u < sg.len;
+          // the trace derives the leaf from such a state's key (busy units back at d).
+          // On units alike the inner states of a dispatch closure store none either, and
+          // a leaf links to the closure's root: a counterexample passes through one chain
+          // of the closure only, which the trace regenerates (the missing units started in
+          // index order).  That is one link write per closure instead of 2^k - 1.
+          const uint32_t ns = (uint32_t)__popc(x.rmask);
+          const bool linkless = (!x.is_clos && sg.lock && sg.kstar && x.j + 1u < sg.len) ||
+                                (!HET && x.is_clos && ns < sg.kstar);
           if (x.is_clos) {
             const uint32_t pm = x.rmask & ~(1u << (31 - __clz(x.rmask)));
-            par = pm ? sh.mslot[x.sgi][pm] : segf;
+            par = (pm && (HET || ns < sg.kstar)) ? sh.mslot[x.sgi][pm] : segf;
           } else {
             const uint32_t leaf_slot = x.rmask ? sh.mslot[x.sgi][x.rmask] : segf;
             const uint32_t li = (uint32_t)n * BLOCK + tid;  // local index of the item
@@ -1723,6 +1729,48 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
         for (int w = 0; w < W; ++w) out[(unsigned long long)n * W + w] = k.w[w];
       }
       ++n;
+      if (par != kParentRoot && par != kParentNone && (unsigned long long)par <= a.mask) {
+        // a dispatch leaf linked to its closure's root (the closure's inner states store
+        // no links): the states between them start the missing units one at a time, in
+        // index order, at the root's clock
+        const unsigned long long* pp = slot_key<W>(a.table, par);
+        Key<W> pk;
+#pragma unroll
+        for (int w = 0; w < W; ++w) pk.w[w] = pp[w];
+        const St root = decode<W>(pk, L, a.cfgs);
+        const St x = decode<W>(k, L, a.cfgs);
+        if (root.cfg == x.cfg && root.clock == x.clock && root.pending > x.pending + 1u) {
+          const uint32_t gap = root.pending - x.pending - 1u;  // inner states to list
+          if (n + gap > cap) {
+            bad = true;
+            break;
+          }
+          uint32_t dmask = 0;  // units the closure started
+          for (int u = 0; u < m; ++u)
+            if (root.rem[u] == 0u && x.rem[u] != 0u) dmask |= 1u << u;
+          if ((uint32_t)__popc(dmask) != gap + 1u) {
+            bad = true;
+            break;
+          }
+          if (lane == 0) {
+            // terminal-first: the state with the first gap units started comes first
+            for (uint32_t i = gap; i >= 1u; --i) {
+              St y = root;
+              uint32_t left = i;
+              for (int u = 0; u < m && left; ++u)
+                if ((dmask >> u) & 1u) {
+                  y.rem[u] = x.rem[u];
+                  --left;
+                }
+              y.pending = root.pending - i;
+              const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+              for (int w = 0; w < W; ++w) out[(unsigned long long)(n + gap - i) * W + w] = yk.w[w];
+            }
+          }
+          n += gap;
+        }
+      }
       s = par;
       continue;
     }
