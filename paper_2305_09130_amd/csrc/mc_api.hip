@@ -39,7 +39,8 @@ struct WsPlan {
   uint64_t n_parts = 0;
 };
 
-uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
+// visited-set bytes per slot: the key words, then the parent and jump words
+uint32_t slot_bytes_for(uint32_t W) { return 8u * W + 8u; }
 
 // Slots for `states` keys at the given load factor, rounded up to a power of two.  The
 // automatic target (load_factor 0) is 3/8: a large single query is bound by the rate of
@@ -322,7 +323,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   bool cleared = false;
   if (h->dirty) {
     HIPCHK(ev_record(h->ev[0], s));
-    HIPCHK(launch_clear(s, h->table, h->q_slots * h->plan.slot_bytes));
+    // units alike clear the keys only (their links are read only where written)
+    HIPCHK(launch_clear(s, h->table,
+                        h->q_slots * (h->mh.hetero ? h->plan.slot_bytes : 8ull * h->mh.W)));
     HIPCHK(ev_record(h->ev[1], s));
     cleared = true;
   }
@@ -449,7 +452,8 @@ int run_resume(mc_model* h, uint32_t T, mc_stats* st) {
   plan_resume(h->mh, h->resident_T, fresh, &plan);
   std::vector<Part> parts(plan.size());
   for (size_t i = 0; i < plan.size(); ++i)
-    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1, (uint32_t)i, 0u, 0u, 0u};
+    parts[i] = Part{0u, plan[i].cfg, plan[i].r0, plan[i].r1, (uint32_t)i, plan[i].j0,
+                    plan[i].j1, 0u};
   h->parts_resumed = true;
   if (!parts.empty())
     HIPCHK(hipMemcpyAsync(h->parts, parts.data(), sizeof(Part) * parts.size(),

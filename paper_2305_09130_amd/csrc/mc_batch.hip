@@ -27,7 +27,8 @@ uint64_t next_pow2(uint64_t x) {
   while (p < x) p <<= 1;
   return p;
 }
-uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
+// visited-set bytes per slot: the key words, then the parent and jump words
+uint32_t slot_bytes_for(uint32_t W) { return 8u * W + 8u; }
 constexpr size_t kCtrlStride = 256;
 
 struct BatchPlan {

@@ -47,14 +47,10 @@ constexpr unsigned int kDevErrAbort = 6;  // the host asked the query to stop
 
 constexpr uint32_t kMaxProbeIters = 1u << 16;
 
+// A visited set of S slots holds the keys of all its slots first (8W bytes each), then
+// their links (a parent and a jump word, 8 bytes each): SlotBytes is the total per slot.
 template <int W>
-struct SlotBytes;
-template <>
-struct SlotBytes<1> { static constexpr uint32_t v = 16; };
-template <>
-struct SlotBytes<2> { static constexpr uint32_t v = 32; };
-template <>
-struct SlotBytes<4> { static constexpr uint32_t v = 64; };
+struct SlotBytes { static constexpr uint32_t v = 8u * W + 8u; };
 
 template <int W>
 struct Key {
@@ -328,18 +324,31 @@ __device__ __forceinline__ void advance_once(St& s, const CfgRec& r, int m,
 
 // ---- visited set ----------------------------------------------------------------
 
+// The key region starts at base; the link region of a set of mask + 1 slots follows it.
+// Every writer of a link stores both words.  On units alike only the key region is
+// cleared: a state's links are read only where they were written (the trace tells the
+// states that store none from their keys).
 template <int W>
 __device__ __forceinline__ unsigned long long* slot_key(unsigned char* base, unsigned long long s) {
-  return reinterpret_cast<unsigned long long*>(base + s * SlotBytes<W>::v);
+  return reinterpret_cast<unsigned long long*>(base + s * (8ull * W));
 }
 template <int W>
-__device__ __forceinline__ uint32_t* slot_parent(unsigned char* base, unsigned long long s) {
-  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W);
+__device__ __forceinline__ uint32_t* slot_parent(unsigned char* base, unsigned long long mask,
+                                                 unsigned long long s) {
+  return reinterpret_cast<uint32_t*>(base + (mask + 1ull) * (8ull * W) + s * 8ull);
 }
 // jump word: first predecessor of the lock-step run a state belongs to (else 0xFFFFFFFF)
 template <int W>
-__device__ __forceinline__ uint32_t* slot_jump(unsigned char* base, unsigned long long s) {
-  return reinterpret_cast<uint32_t*>(base + s * SlotBytes<W>::v + 8u * W + 4u);
+__device__ __forceinline__ uint32_t* slot_jump(unsigned char* base, unsigned long long mask,
+                                               unsigned long long s) {
+  return reinterpret_cast<uint32_t*>(base + (mask + 1ull) * (8ull * W) + s * 8ull + 4ull);
+}
+// both links of a slot in one 8-byte store
+template <int W>
+__device__ __forceinline__ void set_links(unsigned char* base, unsigned long long mask,
+                                          unsigned long long s, uint32_t parent, uint32_t jump) {
+  *reinterpret_cast<unsigned long long*>(base + (mask + 1ull) * (8ull * W) + s * 8ull) =
+      (unsigned long long)parent | ((unsigned long long)jump << 32);
 }
 
 constexpr int kScopeWG = __HIP_MEMORY_SCOPE_WORKGROUP;
@@ -348,12 +357,12 @@ constexpr int kScopeSystem = __HIP_MEMORY_SCOPE_SYSTEM;
 
 enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 
-// Open addressing in windows of consecutive slots that share one 64-byte line (4, 2 or
-// 1 slots for 1-, 2- and 4-word keys); windows are visited in a double-hashing sequence
+// Open addressing in windows of consecutive slots whose keys share one 64-byte line (8, 4
+// or 2 slots for 1-, 2- and 4-word keys); windows are visited in a double-hashing sequence
 // (odd step, so every window is reached) and the slots of a window in a circular order
 // that starts at a slot the key's hash picks (keys that share a home window then start
-// apart: 1.38 probes per new key instead of 1.90 when every key starts at the window's
-// first slot, at the load 0.43 of the largest workload).  Every
+// apart: with windows of four slots, 1.38 probes per new key instead of 1.90 when every
+// key starts at the window's first slot, at the load 0.43 of the largest workload).  Every
 // probe is a 64-bit compare-and-swap of word 0 from empty to the key's word 0, issued
 // without reading the slot first: a probe of an empty slot claims it in one round trip,
 // and a failed one returns the slot's word 0, which is all a read would have told.
@@ -373,12 +382,14 @@ enum { kInsNew = 1, kInsDup = 0, kInsFail = -1 };
 // so a lookup stops at the first empty slot.
 template <int W>
 struct Win {
-  static constexpr int n = 64 / SlotBytes<W>::v;  // slots per window (one 64-byte line)
+  static constexpr int n = 8 / W;                       // slots per window (one 64-byte line)
+  static constexpr int log2 = W == 1 ? 3 : W == 2 ? 2 : 1;
 };
-static_assert(Win<1>::n == 4 && Win<2>::n == 2 && Win<4>::n == 1, "window sizes");
+static_assert(Win<1>::n == 8 && Win<2>::n == 4 && Win<4>::n == 2, "window sizes");
 
 // Home window wi, odd window step, and the first slot j0 within every window (from
-// the hash's top bits, which neither wi nor step use for tables below 2^31 slots).
+// the hash's top log2(slots per window) bits, which neither wi nor step use for tables of
+// at most 2^31 slots: step takes bits 33 to 32 + log2(windows)).
 // The key's hash with only its low `hkeep` bits kept (hkeep 0: all), remixed: a testing
 // aid that crowds keys into 2^hkeep probe sequences.
 __device__ __forceinline__ unsigned long long keep_hash(unsigned long long h, uint32_t hkeep) {
@@ -393,7 +404,7 @@ __device__ __forceinline__ void probe_start(unsigned long long h, unsigned long 
   wi = h & nwin_mask;
   step = ((h >> 33) | 1ull) & nwin_mask;
   step |= 1ull;
-  j0 = (int)(h >> 62) & (Win<W>::n - 1);
+  j0 = (int)(h >> (64 - Win<W>::log2)) & (Win<W>::n - 1);
 }
 
 // the t-th slot of window wi in the circular order from j0

@@ -40,7 +40,8 @@ uint64_t next_pow2(uint64_t x) {
   while (p < x) p <<= 1;
   return p;
 }
-uint32_t slot_bytes_for(uint32_t W) { return W == 1 ? 16u : W == 2 ? 32u : 64u; }
+// visited-set bytes per slot: the key words, then the parent and jump words
+uint32_t slot_bytes_for(uint32_t W) { return 8u * W + 8u; }
 constexpr size_t kCtrlStride = 256;
 
 uint64_t now_ns() {
@@ -578,8 +579,9 @@ int mc_engine_step(mc_engine* e, uint32_t* n_active, uint32_t* n_waiting) {
       q->n_parts = (uint32_t)st.plan.size();
       const ModelDev md = make_dev(e, r, q, q->n_parts);
       if (q->mode == kFresh) {
+        // units alike clear the keys only (their links are read only where written)
         HIPCHK(launch_clear(s, e->base + e->arena_off + r->off + r->table_off,
-                            r->slots * slot_bytes_for(r->mh.W)));
+                            r->slots * (r->mh.hetero ? slot_bytes_for(r->mh.W) : 8ull * r->mh.W)));
         fresh_md.push_back(md);
         fresh_slot.push_back(r->slot_idx);
       } else {

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_seed(QueryArgs a, Seed* seeds, Entry<W>
     uint32_t slot = kParentNone;
     const int res = table_insert<W, kScopeAgent>(a.table, a.mask, k, slot, probes, a.hkeep);
     if (res != kInsNew) set_error(a.ctrl, kDevErrTableFull);
-    else *slot_parent<W>(a.table, slot) = kParentRoot;
+    else set_links<W>(a.table, a.mask, slot, kParentRoot, kParentNone);
     s_root = slot;
     a.ctrl->root_slot = slot;
     a.ctrl->fcount[0] = a.n_cfg;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_seed(QueryArgs a, Seed* seeds, Entry<W>
       set_error(a.ctrl, kDevErrTableFull);
       slot = kParentNone;
     } else {
-      *slot_parent<W>(a.table, slot) = s_root;
+      set_links<W>(a.table, a.mask, slot, s_root, kParentNone);
     }
     Seed sd;
 #pragma unroll
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(BLOCK) void k_level(LevelArgs a, const Entry<W>* __
           set_error(q.ctrl, kDevErrTableFull);
         } else if (res == kInsNew) {
           fresh = true;
-          *slot_parent<W>(q.table, slot) = s_par[t];
+          set_links<W>(q.table, q.mask, slot, s_par[t], kParentNone);
           ++n_states;
           depth_max = dep > depth_max ? dep : depth_max;
           const St y = decode<W>(k, q.L, q.cfgs);
@@ -1285,8 +1285,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             if (sg.lock) jmp = leaf_slot;
           }
           if (!linkless) {
-            *slot_parent<W>(md.table, slot[n]) = par;
-            if (jmp != kParentNone) *slot_jump<W>(md.table, slot[n]) = jmp;
+            set_links<W>(md.table, md.mask, slot[n], par, jmp);
           }
           if (!fresh[n]) continue;
           if (!x.is_clos && x.j + 1u == sg.len && !x.term && x.sgi + 1u == nseg &&
@@ -1314,15 +1313,13 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         const uint32_t leaf_slot = sh.mslot[nseg - 1u][(1u << sg.nfree) - 1u];
         const uint32_t par =
             sg.len > 1u ? sh.chunk_slot[(stop_item - 1u) % (NI * BLOCK)] : leaf_slot;
-        *slot_parent<W>(md.table, sh.stop_slot) = par;
-        *slot_jump<W>(md.table, sh.stop_slot) = leaf_slot;
+        set_links<W>(md.table, md.mask, sh.stop_slot, par, leaf_slot);
       } else if (sh.stop_capped && tid == 0 && sh.stop_slot != kParentNone) {
         // B_r1 after a run whose later states are in run slices: the run is regenerated
         // from its dispatch leaf, which is both links
         const SegDesc& sg = sh.seg[nseg - 1u];
         const uint32_t leaf_slot = sh.mslot[nseg - 1u][(1u << sg.nfree) - 1u];
-        *slot_parent<W>(md.table, sh.stop_slot) = leaf_slot;
-        *slot_jump<W>(md.table, sh.stop_slot) = leaf_slot;
+        set_links<W>(md.table, md.mask, sh.stop_slot, leaf_slot, leaf_slot);
       }
     }
     if (tid == 0) sh.fcount[cur] = 0u;
@@ -1461,7 +1458,7 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
     for (int q = 0; q < NI; ++q) {
       if (!fresh[q] || !term[q]) continue;
       const uint32_t li = (uint32_t)q * BLOCK + tid;  // the run's previous state: item i-1
-      *slot_parent<W>(md.table, slot[q]) = li ? sh.chunk_slot[li - 1] : sh.carry;
+      set_links<W>(md.table, md.mask, slot[q], li ? sh.chunk_slot[li - 1] : sh.carry, kParentNone);
     }
     __syncthreads();
     if (tid == BLOCK - 1) sh.carry = sh.chunk_slot[NI * BLOCK - 1];
@@ -1568,7 +1565,7 @@ __device__ void seed_model(const ModelDev& md) {
     uint32_t slot = kParentNone;
     const int res = table_insert<W, kScopeAgent>(md.table, md.mask, k, slot, probes, md.hkeep);
     if (res != kInsNew) set_error(md.ctrl, kDevErrTableFull);
-    else *slot_parent<W>(md.table, slot) = kParentRoot;
+    else set_links<W>(md.table, md.mask, slot, kParentRoot, kParentNone);
     s_root = slot;
     md.ctrl->root_slot = slot;
     md.ctrl->max_depth = 1;
@@ -1587,7 +1584,7 @@ __device__ void seed_model(const ModelDev& md) {
       set_error(md.ctrl, kDevErrTableFull);
       slot = kParentNone;
     } else {
-      *slot_parent<W>(md.table, slot) = s_root;
+      set_links<W>(md.table, md.mask, slot, s_root, kParentNone);
     }
     Seed sd;
 #pragma unroll
@@ -1656,7 +1653,7 @@ __global__ __launch_bounds__(256) void k_count_le(const unsigned char* __restric
   for (unsigned long long s = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
        s += stride) {
     const unsigned long long* w = reinterpret_cast<const unsigned long long*>(
-        table + s * SlotBytes<W>::v);
+        table + s * (8ull * W));
     Key<W> k;
     bool ready = true;
 #pragma unroll
@@ -1682,8 +1679,12 @@ __global__ void k_find(QueryArgs a, Key<W> k) {
 // end of a lock-step run carries a jump to the run's first predecessor (the leaf), and
 // an interior state of a run from a dispatch leaf carries no link at all: its leaf is
 // the same state with every busy unit back at d and the clock of the run's start, found
-// by a lookup.  The run's states are regenerated lane-parallel from the leaf (operation
-// end E[i0+j] on every busy unit) instead of being chased one parent at a time.
+// by a lookup (on units alike every state inside a run is taken this way, told from its
+// key).  The run's states are regenerated lane-parallel from the leaf (operation end
+// E[i0+j] on every busy unit) instead of being chased one parent at a time.  On units
+// alike a dispatch leaf links to its closure's root, the inner closure states storing no
+// links: the states between the two are listed by starting the leaf's extra units one at
+// a time in index order.
 template <int W>
 __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* out, uint32_t cap) {
   if (blockIdx.x != 0) return;
@@ -1702,8 +1703,17 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
     Key<W> k;
 #pragma unroll
     for (int w = 0; w < W; ++w) k.w[w] = p[w];
-    const uint32_t par = *slot_parent<W>(a.table, s);
-    uint32_t jmp = *slot_jump<W>(a.table, s);
+    // on units alike a state with busy units short of d is inside a lock-step run: its
+    // links, if it stored any, are not read (the link region is not cleared there)
+    bool inside_run = false;
+    if (L.shared_rem) {
+      const St xs = decode<W>(k, L, a.cfgs);
+      uint32_t rem = 0;
+      for (int u = 0; u < m; ++u) rem = xs.rem[u] ? xs.rem[u] : rem;
+      inside_run = rem != 0u && xs.cfg < a.n_cfg && rem < a.cfgs[xs.cfg].d;
+    }
+    const uint32_t par = inside_run ? kParentNone : *slot_parent<W>(a.table, a.mask, s);
+    uint32_t jmp = inside_run ? kParentNone : *slot_jump<W>(a.table, a.mask, s);
     if (par == kParentNone && jmp == kParentNone) {
       // an interior state of a lock-step run from a dispatch leaf (it stores no links):
       // the leaf has the same busy units, each at d, and the clock of the run's start
@@ -1942,9 +1952,11 @@ MC_INSTANTIATE(2)
 MC_INSTANTIATE(4)
 
 hipError_t launch_clear(hipStream_t st, void* p, unsigned long long bytes) {
+  // about two 16-byte stores per thread, at most 2^18 workgroups: a 4 GiB fill ran at
+  // 6.3 TB/s with 2^18 workgroups against 5.2 TB/s with 2^13
   const unsigned long long n16 = bytes / 16;
-  unsigned long long grid = (n16 + 255) / 256;
-  if (grid > 8192) grid = 8192;
+  unsigned long long grid = (n16 + 511) / 512;
+  if (grid > (1ull << 18)) grid = 1ull << 18;
   if (grid == 0) grid = 1;
   hipLaunchKernelGGL(k_clear, dim3((uint32_t)grid), dim3(256), 0, st, reinterpret_cast<uint4*>(p),
                      n16);
