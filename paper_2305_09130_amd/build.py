@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmctune.so")
 PEAK_LIB = os.path.join(HERE, "libmcpeak.so")
-SOURCES = ["mc_model.cpp", "mc_host_pool.cpp", "mc_kernels.hip", "mc_walks.hip", "mc_api.hip",
-           "mc_batch.hip", "mc_engine.hip", "mc_static.hip"]
+SOURCES = ["mc_model.cpp", "mc_host_pool.cpp", "mc_kernels.hip", "mc_walks.hip", "mc_trace.hip",
+           "mc_api.hip", "mc_batch.hip", "mc_engine.hip", "mc_static.hip"]
 PEAK_SOURCES = ["mc_peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -349,7 +349,7 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     md.bb = bb ? 1u : 0u;
     md.pstate = nullptr;
     md.hkeep = h->opts.test_hash_bits;
-    md.pad2 = 0u;
+    md.refloor = 0u;
     HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));
     HIPCHK(launch_reset_models(s, h->dmd, 1, h->head, 1));
     HIPCHK(ev_record(h->ev[2], s));
@@ -462,6 +462,7 @@ int run_resume(mc_model* h, uint32_t T, mc_stats* st) {
   md.prune = 1u;
   md.T = T;
   md.bb = 0u;
+  md.refloor = h->resident_T + 1u;  // resident_T < T <= the largest clock
   md.n_parts = (uint32_t)parts.size();
   h->q_parts = md.n_parts;
   HIPCHK(hipMemcpyAsync(h->dmd, h->hmd, sizeof(ModelDev), hipMemcpyHostToDevice, s));

@@ -227,6 +227,8 @@ ModelDev make_dev(mc_engine* e, const Resident* r, const Query* q, uint32_t n_pa
   d.max_clock = r->mh.max_clock;
   d.n_parts = n_parts;
   d.pstate = reinterpret_cast<PartState*>(g + r->pstate_off);
+  // a continued exploration expands the states it finds again below T_done
+  d.refloor = q->mode == kResume ? r->T_done + 1u : 0u;
   return d;
 }
 

@@ -76,7 +76,9 @@ struct ModelDev {
                       // terminal lowers ctrl->bound
   PartState* pstate;  // one per partition when partitions may yield, else null
   uint32_t hkeep;     // bits of the key hash kept (0 = all; testing only)
-  uint32_t pad2;
+  uint32_t refloor;   // a continued exploration: every state with clock < refloor was
+                      // inserted before, and one found again is still expanded, so the
+                      // walk reaches the new states past it (0 = a fresh exploration)
 };
 
 // One partition of a persistent launch: rounds [r0, r1) of one configuration's subgraph

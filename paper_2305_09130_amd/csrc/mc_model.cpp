@@ -588,10 +588,34 @@ bool word0_orders_rounds(const ModelHost& h) {
   return L.clock_implied ? L.word[kFRem] == 0 && L.word[kFRem + 1] == 0 : L.word[kFClock] == 0;
 }
 
-bool resumable(const ModelHost& h) { return word0_orders_rounds(h); }
+bool resumable(const ModelHost& h) { return h.hetero || word0_orders_rounds(h); }
 
 void plan_resume(const ModelHost& h, uint64_t T_done, const std::vector<PartPlan>& fresh,
                  std::vector<PartPlan>* out) {
+  if (h.hetero) {
+    // units of unequal speed: a configuration whose latest terminal clock is at most
+    // T_done is done; otherwise its chain slices that end past T_done are kept (each
+    // starts on a cut of the determined part, whose state is in the set when the cut's
+    // clock is at most T_done, and the last one runs through the tails), and a
+    // configuration the fresh plan does not cut continues from its SELECT state
+    std::vector<uint8_t> seen(h.n_cfg, 0);
+    for (const PartPlan& p : fresh) {
+      if (p.cfg >= h.n_cfg) continue;
+      const uint32_t c = p.cfg;
+      seen[c] = 1;
+      if (h.cfgs[c].tc <= T_done) continue;
+      if (p.r0 == kChainSlice) {
+        if (p.r1 != kNoClock && p.r1 <= T_done) continue;
+        out->push_back(p);
+      } else {
+        out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
+      }
+    }
+    for (uint32_t c = 0; c < h.n_cfg; ++c)
+      if (!seen[c] && h.cfgs[c].tc > T_done)
+        out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
+    return;
+  }
   // configurations that the fresh plan cuts into round blocks only keep those blocks past
   // T_done; every other one resumes as one partition
   std::vector<uint32_t> nparts(h.n_cfg, 0);

@@ -154,7 +154,8 @@ bool word0_orders_rounds(const ModelHost& h);
 // Whether an exploration pruned at some T can be continued to a larger T' on the same
 // visited set: units that all work alike (every configuration passes through the state
 // after r full rounds, (c, r d, n - r m, all idle)) and a key whose word 0 holds the
-// pending count and the clock (so a partition may start at that state).
+// pending count and the clock (so a partition may start at that state); or units of
+// unequal speed, which continue from the cuts of their chain slices (or from SELECT).
 bool resumable(const ModelHost& h);
 
 // Partitions that continue a resumable model's exploration after every state with clock
@@ -164,7 +165,8 @@ bool resumable(const ModelHost& h);
 // cuts into round blocks keeps the blocks that end past round r0, the one holding r0
 // starting there, so the continuation is as parallel as the fresh exploration; any other
 // configuration continues as one partition.  Never more partitions than the fresh plan
-// has (or than configurations, if that is more).
+// has (or than configurations, if that is more).  On units of unequal speed it keeps the
+// chain slices that end past T_done and restarts uncut configurations from SELECT.
 void plan_resume(const ModelHost& h, uint64_t T_done, const std::vector<PartPlan>& fresh,
                  std::vector<PartPlan>* out);
 

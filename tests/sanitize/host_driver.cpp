@@ -45,6 +45,25 @@ static void exercise(const mc_desc& d, bool valid) {
         plan_parts(h, target, &fresh);
         plan_resume(h, T, fresh, &rp);
         expect(rp.size() <= std::max<size_t>(fresh.size(), h.n_cfg), "resume plan size");
+        if (h.hetero) {
+          // chain slices ending past T, or whole configurations from SELECT; nothing of a
+          // configuration whose terminals all lie at or below T
+          for (const PartPlan& p : rp) {
+            expect(p.cfg < h.n_cfg && h.cfgs[p.cfg].tc > T, "unequal units: finished resumed");
+            if (p.r0 == kChainSlice)
+              expect(p.r1 == kNoClock || p.r1 > T, "unequal units: slice ends past T");
+            else
+              expect(p.r0 == 0 && p.r1 == kRoundsToEnd, "unequal units: whole from SELECT");
+          }
+          for (uint32_t c = 0; c < h.n_cfg; ++c) {
+            if (h.cfgs[c].tc <= T) continue;
+            bool last = false;  // the part that runs through the tails is always kept
+            for (const PartPlan& p : rp)
+              last |= p.cfg == c && (p.r0 != kChainSlice || p.r1 == kNoClock);
+            expect(last, "unequal units: configuration's end resumed");
+          }
+          continue;
+        }
         // per configuration: the resumed rounds are [floor(T/d), rounds), disjoint, covered
         for (uint32_t c = 0; c < h.n_cfg; ++c) {
           const CfgRec& r = h.cfgs[c];

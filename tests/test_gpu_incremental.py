@@ -75,13 +75,37 @@ def test_incremental_bisection(mc, k):
     g.close()
 
 
-def test_unequal_units_bisect_fresh_checks(mc):
-    """Units of unequal speed have no common state after whole rounds: every check is a
-    fresh exploration, and the result is the oracle's."""
-    model = workloads.with_speeds(workloads.reduction_model(64, 3, [1, 2, 4], [1, 2], 6, 2),
-                                  [1, 2, 3])
-    g = mc.Model(model)
-    t_min, n = g.mc_tune_bisect(5)
-    t_ini, _ = oracle.simulate(model, 5)
-    assert (t_min, n) == oracle.bisect_t_min(model, t_ini)
-    g.close()
+def _hetero_models():
+    return ([workloads.with_speeds(workloads.reduction_model(64, 3, [1, 2, 4], [1, 2], 6, 2),
+                                   [1, 2, 3])]
+            + list(workloads.hetero_workloads().values())
+            + workloads.tiny_hetero_models(73, 16, max_cu=4, max_speed=3))
+
+
+@pytest.mark.parametrize("k", range(19))
+def test_unequal_units_bisect_incremental(mc, k):
+    """Units of unequal speed continue a check from the cuts of their chain slices (or
+    from SELECT): the bisection equals the oracle's and explores each state up to the
+    largest threshold it checked once, also with every configuration uncut."""
+    models = _hetero_models()
+    if k >= len(models):
+        pytest.skip("fewer models")
+    model = models[k]
+    _say(f"incremental bisection, unequal units: {workloads.describe(model)}")
+    r = oracle.explore(model, trace=False)
+    for part_states in (0, 32, mc.NEVER_CUT):
+        g = mc.Model(model, part_states=part_states)
+        for seed in (5, 11):
+            t_min, n = g.mc_tune_bisect(seed)
+            t_ini, _ = oracle.simulate(model, seed)
+            checks, n_loop = _thresholds(t_ini, r["t_min"])
+            assert (t_min, n) == (r["t_min"], n_loop)
+            if r["reachable"] < 200_000:
+                assert (t_min, n) == oracle.bisect_t_min(model, t_ini)
+            top = max(checks)
+            assert g.last_stats["states"] == oracle.explore(model, T=top,
+                                                            trace=False)["reachable"]
+            oracle.check_trace(model, g.mc_trace(), max_clock=t_min)
+        assert g.mc_min_time() == (r["t_min"], r["argmin"])
+        assert g.last_stats["states"] == r["reachable"]
+        g.close()
