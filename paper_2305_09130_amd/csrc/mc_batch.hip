@@ -32,12 +32,27 @@ uint32_t slot_bytes_for(uint32_t W) { return 8u * W + 8u; }
 constexpr size_t kCtrlStride = 256;
 
 struct BatchPlan {
-  size_t ctrl = 0, tc = 0, cfgs = 0, seeds = 0, md = 0, parts = 0, head = 0, tables = 0;
-  size_t tables_bytes = 0, total = 0;
+  size_t ctrl = 0, tc = 0, cfgs = 0, seeds = 0, md = 0, parts = 0, head = 0, ranges = 0;
+  size_t tables = 0, tables_bytes = 0, total = 0;
   std::vector<size_t> tc_off, cfg_off, seed_off, table_off;
   std::vector<uint64_t> slots;
   uint64_t n_parts = 0;
 };
+
+// The part of each model's visited set a query clears, as (first, count) of 16-byte units
+// from the tables' start: the key region on units alike (their links are read only where
+// written), the whole set on units of unequal speed.  One workgroup row per model.
+__global__ void k_clear_ranges(uint4* base, const ulonglong2* ranges, uint32_t n) {
+  const uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  for (uint32_t r = blockIdx.y; r < n; r += gridDim.y) {
+    const ulonglong2 rg = ranges[r];
+    uint4* p = base + rg.x;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         i < rg.y; i += stride)
+      p[i] = v;
+  }
+}
 
 mc_batch_opts default_bopts(const mc_batch_opts* o) {
   mc_batch_opts r;
@@ -107,6 +122,8 @@ int plan_batch(const std::vector<ModelHost>& ms, const mc_batch_opts& o, uint64_
   off = align_up(off);
   p->md = off;
   off = align_up(off + sizeof(ModelDev) * n);
+  p->ranges = off;
+  off = align_up(off + sizeof(unsigned long long) * 2 * n);
   p->n_parts = n_parts;
   p->parts = off;
   off = align_up(off + sizeof(Part) * p->n_parts);
@@ -166,6 +183,7 @@ struct mc_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool ran = false;
+  uint64_t max_range16 = 0;  // the largest range of the clear, in 16-byte units
   uint32_t grid[3] = {0, 0, 0};
   uint32_t group_off[3] = {0, 0, 0}, group_n[3] = {0, 0, 0};  // partitions per key width
   Fork fork;
@@ -176,7 +194,16 @@ namespace {
 int enqueue_query(mc_batch* b) {
   hipStream_t s = b->stream;
   const uint32_t n = (uint32_t)b->ms.size();
-  HIPCHK(launch_clear(s, b->ws + b->plan.tables, b->plan.tables_bytes));
+  {
+    // about two 16-byte stores per thread of the largest range, at most 65535 model rows
+    const unsigned long long x = std::min<unsigned long long>(
+        std::max<unsigned long long>(1, (b->max_range16 + 511) / 512), 1024);
+    const uint32_t y = std::min<uint32_t>(n, 65535u);
+    hipLaunchKernelGGL(k_clear_ranges, dim3((uint32_t)x, y), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(b->ws + b->plan.tables),
+                       reinterpret_cast<const ulonglong2*>(b->ws + b->plan.ranges), n);
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(launch_reset_models(s, b->dmd, n, b->head, 3));
   HIPCHK(launch_seed_models(s, b->dmd, n));
   const uint32_t li = b->opts.lane_items;  // 0: per key width
@@ -340,7 +367,18 @@ int mc_batch_create(const mc_desc* models, uint32_t n, const mc_batch_opts* o, v
         free_batch(b);
         return MC_E_DEVICE;
       }
-    if (hipMemcpyAsync(b->dmd, md.data(), sizeof(ModelDev) * n, hipMemcpyHostToDevice, s) !=
+    // the part of each visited set a query clears (16-byte units from the tables' start)
+    std::vector<unsigned long long> ranges(2ull * n);
+    for (uint32_t i = 0; i < n; ++i) {
+      const ModelHost& m = b->ms[i];
+      const uint64_t bytes = b->plan.slots[i] * (m.hetero ? slot_bytes_for(m.W) : 8ull * m.W);
+      ranges[2 * i] = (b->plan.table_off[i] - b->plan.tables) / 16;
+      ranges[2 * i + 1] = bytes / 16;
+      b->max_range16 = std::max<uint64_t>(b->max_range16, bytes / 16);
+    }
+    if (hipMemcpyAsync(b->ws + b->plan.ranges, ranges.data(), sizeof(unsigned long long) * 2 * n,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->dmd, md.data(), sizeof(ModelDev) * n, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipMemcpyAsync(b->parts, parts.data(), sizeof(Part) * parts.size(),
                        hipMemcpyHostToDevice, s) != hipSuccess ||
