@@ -175,7 +175,11 @@ def test_resident_state_is_reused_exactly(mc):
                   workloads.matmul_model(16, 16, 16, 4, [1, 2, 4], [1, 2], [1, 2, 4], [1, 2],
                                          5, 2),
                   workloads.unit_model(workloads.KIND_MINIMUM, 64, 4, 3, [2, 4, 8], [1, 4], 4,
-                                       1)):
+                                       1),
+                  # units of unequal speed continue from the cuts of their chain slices
+                  workloads.with_speeds(workloads.reduction_model(64, 4, [1, 2, 4], [1, 2], 37,
+                                                                  3), [1, 2, 3, 4]),
+                  workloads.hetero_workloads()["reduction_g256_cu4_s1123"]):
         full = oracle.explore(model, trace=False)
         t = full["t_min"]
         seq = [("check", t // 2), ("check", t // 4), ("check", t - 1), ("check", t),
