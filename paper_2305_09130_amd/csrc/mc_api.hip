@@ -294,10 +294,8 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
   bool own_plan = false;
   if (prune && !bb && h->opts.engine == MC_ENGINE_SUPERSTEP && h->opts.part_states == 0 &&
       !h->mh.hetero && word0_orders_rounds(h->mh)) {
-    std::vector<PartPlan> plan, keep;
-    plan_parts(h->mh, auto_part_states(count_le_bound(h->mh, T), h->mh.m), &plan);
-    for (const PartPlan& p : plan)
-      if (p.r0 == kRunSlice || (uint64_t)p.r0 * h->mh.cfgs[p.cfg].d <= T) keep.push_back(p);
+    std::vector<PartPlan> keep;
+    plan_parts(h->mh, auto_part_states(count_le_bound(h->mh, T), h->mh.m), &keep, T);
     if (keep.size() <= h->n_parts) {
       std::stable_sort(keep.begin(), keep.end(), [](const PartPlan& a, const PartPlan& b) {
         return a.states > b.states;

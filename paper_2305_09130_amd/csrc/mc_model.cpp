@@ -465,7 +465,8 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   return MC_OK;
 }
 
-void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out) {
+void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out,
+                uint64_t clock_max) {
   // units of unequal speed pass through no common idle state after whole rounds
   const bool cuttable = target > 0 && word0_orders_rounds(h);
   // ... but their determined part is cut into chain slices, which share no word-0 value
@@ -547,11 +548,13 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
       // `sl1` states of its run and claims the next round's start; slices hold the rest
       const uint64_t full_blocks = p ? q : q - 1;  // rounds whose block ends at a cut
       for (uint64_t k = 0; k < full_blocks; ++k) {
+        if (k * r.d > clock_max) break;  // the round starts past every state asked for
         PartPlan b{c, (uint32_t)k, (uint32_t)(k + 1), per_round - (r.b - 1 - sl1)};
         b.j1 = (uint32_t)sl1;
         out->push_back(b);
         add_slices(k, 1, sl1, false);
       }
+      if ((p ? q : q - 1) * r.d > clock_max) continue;
       if (p) {  // the partial round, to the terminals
         const uint64_t choices = binom(h.m, (uint32_t)p), slp = slice_of(choices);
         const bool cut = r.b > slp + 1;
@@ -573,10 +576,11 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out)
       out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
       continue;
     }
-    for (uint64_t k = 0; k + 1 < K; ++k)
+    for (uint64_t k = 0; k + 1 < K && k * R * r.d <= clock_max; ++k)
       out->push_back(PartPlan{c, (uint32_t)(k * R), (uint32_t)((k + 1) * R), R * per_round});
     const uint64_t r0 = (K - 1) * R;
-    out->push_back(PartPlan{c, (uint32_t)r0, kRoundsToEnd, h.cfg_states[c] - r0 * per_round});
+    if (r0 * r.d <= clock_max)
+      out->push_back(PartPlan{c, (uint32_t)r0, kRoundsToEnd, h.cfg_states[c] - r0 * per_round});
   }
 }
 

@@ -142,7 +142,10 @@ struct PartPlan {
 // single round whose runs are longer than a slice is cut into run slices: each spans
 // every run of the configuration over about max(1024, min(8192, target) / runs) states
 // of each (every state of a slice has a clock no other partition's states have).
-void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out);
+// With clock_max, the blocks and run slices of rounds that start after clock_max are left
+// out (a query that drops every state past clock_max explores nothing there).
+void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out,
+                uint64_t clock_max = ~0ull);
 
 // Whether key word 0 alone tells apart the states of different rounds and of different
 // positions along a round's runs (configuration, pending count and either the clock or,

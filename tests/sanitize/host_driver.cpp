@@ -33,6 +33,22 @@ static void exercise(const mc_desc& d, bool valid) {
     plan_parts(h, target, &parts);
     expect(!parts.empty(), "no partitions");
     for (const PartPlan& p : parts) expect(p.cfg < h.n_cfg, "partition configuration");
+    // bounded by a clock: the same plan without the parts of rounds starting after it
+    if (!h.hetero)
+      for (uint64_t cmax : {0ull, 7ull, 300ull, 5000ull}) {
+        std::vector<PartPlan> bounded, want;
+        plan_parts(h, target, &bounded, cmax);
+        for (const PartPlan& p : parts) {
+          const uint64_t round = p.r0 == kRunSlice ? p.r1 : p.r0;
+          if (round * h.cfgs[p.cfg].d <= cmax) want.push_back(p);
+        }
+        bool same = bounded.size() == want.size();
+        for (size_t i = 0; same && i < want.size(); ++i)
+          same = bounded[i].cfg == want[i].cfg && bounded[i].r0 == want[i].r0 &&
+                 bounded[i].r1 == want[i].r1 && bounded[i].j0 == want[i].j0 &&
+                 bounded[i].j1 == want[i].j1;
+        expect(same, "bounded plan");
+      }
   }
   uint64_t last = 0;
   for (uint64_t T : {0ull, 1ull, 50ull, 500ull, 5000ull, 1ull << 31}) {
