@@ -16,6 +16,9 @@
 #include <numeric>
 #include <atomic>
 #include <cstring>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <thread>
 
 namespace mc {
@@ -275,6 +278,84 @@ void chain_cuts(const std::vector<ChainCut>& cands, uint64_t target,
     }
 }
 
+namespace {
+
+// Process-wide workers for the walks of a load: starting and joining threads per load
+// cost about 0.2 ms for seven of them.  Workers are started as first needed (at most
+// 15, detached: they wait for work until the process ends); one job runs at a time and
+// the caller takes part in it.  A worker joins a job only while the caller still admits
+// helpers, and the caller returns once every helper that joined has finished.
+class WalkPool {
+ public:
+  static WalkPool& get() {
+    static WalkPool* p = new WalkPool();  // never destroyed: its workers never stop
+    return *p;
+  }
+
+  // fn(i) for every i < n, on up to `threads` threads (the caller's included)
+  void run(uint32_t n, uint32_t threads, const std::function<void(uint32_t)>& fn) {
+    std::lock_guard<std::mutex> job(job_mu_);
+    const uint32_t helpers = threads > 1 ? start(threads - 1) : 0u;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_.store(0);
+      want_ = helpers;
+      taken_ = 0;
+      ++gen_;
+    }
+    if (helpers) cv_.notify_all();
+    for (uint32_t i; (i = next_.fetch_add(1)) < n;) fn(i);
+    std::unique_lock<std::mutex> g(mu_);
+    want_ = 0;  // no helper joins from here on
+    done_.wait(g, [&] { return active_ == 0u; });
+    fn_ = nullptr;
+  }
+
+ private:
+  // workers up to k (fewer if the system refuses threads); returns how many there are
+  uint32_t start(uint32_t k) {
+    k = std::min<uint32_t>(k, 15u);
+    while (workers_ < k) {
+      try {
+        std::thread([this] { loop(); }).detach();
+      } catch (...) {
+        break;
+      }
+      ++workers_;
+    }
+    return workers_ < k ? workers_ : k;
+  }
+
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> g(mu_);
+    for (;;) {
+      cv_.wait(g, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (taken_ >= want_) continue;  // enough helpers, or the job is over
+      ++taken_;
+      ++active_;
+      const std::function<void(uint32_t)>* fn = fn_;
+      const uint32_t n = n_;
+      g.unlock();
+      for (uint32_t i; (i = next_.fetch_add(1)) < n;) (*fn)(i);
+      g.lock();
+      if (--active_ == 0u) done_.notify_all();
+    }
+  }
+
+  std::mutex job_mu_, mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(uint32_t)>* fn_ = nullptr;
+  std::atomic<uint32_t> next_{0};
+  uint32_t n_ = 0, want_ = 0, taken_ = 0, active_ = 0, workers_ = 0;
+  uint64_t gen_ = 0;
+};
+
+}  // namespace
+
 int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   if (!d || !h) return fail(err, "null descriptor");
   if (d->n_cu < 1 || d->n_cu > (uint32_t)kMaxCU) return fail(err, "n_cu out of range 1..8");
@@ -388,17 +469,7 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
     };
     const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
     const uint32_t nt = walk_work < (1ull << 17) ? 1u : std::min<uint32_t>({hw, 16u, d->n_cfg});
-    std::atomic<uint32_t> next{0};
-    const auto worker = [&] {
-      for (uint32_t c; (c = next.fetch_add(1)) < d->n_cfg;) walk(c);
-    };
-    std::vector<std::thread> pool;
-    try {
-      for (uint32_t i = 1; i < nt; ++i) pool.emplace_back(worker);
-    } catch (...) {  // no more threads: the ones started and this one share the rest
-    }
-    worker();
-    for (auto& th : pool) th.join();
+    WalkPool::get().run(d->n_cfg, nt, walk);
   }
   for (uint32_t c = 0; c < d->n_cfg; ++c) {
     if (c_tc[c] >= 0xFFFFFFFFull) return fail(err, "terminal clock exceeds 32 bits");
