@@ -17,6 +17,7 @@
 #include <atomic>
 #include <cstring>
 #include <condition_variable>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <thread>
@@ -284,7 +285,8 @@ namespace {
 // cost about 0.2 ms for seven of them.  Workers are started as first needed (at most
 // 15, detached: they wait for work until the process ends); one job runs at a time and
 // the caller takes part in it.  A worker joins a job only while the caller still admits
-// helpers, and the caller returns once every helper that joined has finished.
+// helpers, and the caller returns once every helper that joined has finished; the first
+// exception of any item ends the job and is rethrown to the caller.
 class WalkPool {
  public:
   static WalkPool& get() {
@@ -306,11 +308,15 @@ class WalkPool {
       ++gen_;
     }
     if (helpers) cv_.notify_all();
-    for (uint32_t i; (i = next_.fetch_add(1)) < n;) fn(i);
+    work(fn, n);
     std::unique_lock<std::mutex> g(mu_);
     want_ = 0;  // no helper joins from here on
     done_.wait(g, [&] { return active_ == 0u; });
     fn_ = nullptr;
+    std::exception_ptr e = error_;
+    error_ = nullptr;
+    g.unlock();
+    if (e) std::rethrow_exception(e);  // after every helper has left the job
   }
 
  private:
@@ -340,14 +346,26 @@ class WalkPool {
       const std::function<void(uint32_t)>* fn = fn_;
       const uint32_t n = n_;
       g.unlock();
-      for (uint32_t i; (i = next_.fetch_add(1)) < n;) (*fn)(i);
+      work(*fn, n);
       g.lock();
       if (--active_ == 0u) done_.notify_all();
     }
   }
 
-  std::mutex job_mu_, mu_;
+  // the job's items until none is left; the first exception stops the job and is kept
+  void work(const std::function<void(uint32_t)>& fn, uint32_t n) {
+    try {
+      for (uint32_t i; (i = next_.fetch_add(1)) < n;) fn(i);
+    } catch (...) {
+      next_.store(n);  // no further items
+      std::lock_guard<std::mutex> g(err_mu_);
+      if (!error_) error_ = std::current_exception();
+    }
+  }
+
+  std::mutex job_mu_, mu_, err_mu_;
   std::condition_variable cv_, done_;
+  std::exception_ptr error_;  // the job's first exception (read once every helper left)
   const std::function<void(uint32_t)>* fn_ = nullptr;
   std::atomic<uint32_t> next_{0};
   uint32_t n_ = 0, want_ = 0, taken_ = 0, active_ = 0, workers_ = 0;
