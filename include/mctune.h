@@ -134,7 +134,7 @@ typedef struct mc_opts {
     uint32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = automatic:
                                 512 when the query has fewer than 256 partitions, whose
                                 critical chains of inserts then decide the launch time,
-                                else 256) */
+                                or when the units have unequal speeds; else 256) */
     uint32_t log2_slots;     /* visited-set capacity 2^log2_slots (0 = from load_factor) */
     float load_factor;       /* target states/slots when sizing (0 = automatic: at most
                                 0.375 after rounding the slots up to a power of two, or

@@ -669,7 +669,10 @@ int bind_model(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes
     // each runs nearly alone on its compute unit and its chain of insert round trips is
     // the launch time, which 512 threads shorten; with many, 256 keeps more of them
     // resident
-    if (!h->opts.block) h->opts.block = h->n_parts < kWideParts ? 512u : 256u;
+    // units of unequal speed: 512 (their chain listing is block-wide; on the 1.4M-state
+    // workload the launch took 0.77 ms against 0.94 with 256 and 0.85 with 1024)
+    if (!h->opts.block)
+      h->opts.block = (h->mh.hetero || h->n_parts < kWideParts) ? 512u : 256u;
     // one staging block: counters, poll words, descriptor, clocks and, when small, the
     // staging of the uploads below
     static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "staging block layout");
