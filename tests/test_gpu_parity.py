@@ -295,3 +295,31 @@ def test_single_unit_closed_form(mc):
     g.mc_min_time()
     assert g.last_stats["states"] == cf.single_cu_count(model)
     g.close()
+
+
+def test_workspace_reused_across_models(mc):
+    """One workspace for several models in turn, as the benchmark loads them: on units alike
+    only the key region is cleared, so the link region holds the previous model's links;
+    every count, clock and counterexample must still be the oracle's."""
+    import torch
+    models = [workloads.matmul_64(), workloads.reduction_g256(),
+              workloads.matmul_model(16, 16, 16, 4, [1, 2, 4], [1, 2], [1, 2, 4], [1, 2], 5, 2),
+              workloads.reduction_model(128, 3, [1, 2, 4, 8], [1, 2, 4], 9, 3, Lb=0),
+              workloads.matmul_64()]
+    ws = torch.empty(max(mc.mc_workspace_bytes(m) for m in models), dtype=torch.uint8,
+                     device="cuda:0")
+    for model in models:
+        _say(f"shared workspace: {workloads.describe(model)}")
+        g = mc.Model(model, workspace=ws)
+        if mc.state_count(model) and mc.state_count(model) > 1_000_000:
+            s = cf.summary(model, with_E=False)
+            assert g.mc_min_time() == (s["t_min"], s["argmin"])
+            assert g.last_stats["states"] == s["reachable"]
+            oracle.check_trace(model, g.mc_trace(), target_clock=s["t_min"], cfgs=s["argmin"])
+            assert g.mc_check(s["t_min"] - 1) is False
+            assert g.last_stats["states"] == cf.count_le(model, s["t_min"] - 1)
+        else:
+            r = ref(model)
+            check_min_time(mc, g, model, r)
+            check_threshold(mc, g, model, r["t_min"])
+        g.close()
