@@ -48,9 +48,7 @@ constexpr unsigned int kDevErrAbort = 6;  // the host asked the query to stop
 constexpr uint32_t kMaxProbeIters = 1u << 16;
 
 // A visited set of S slots holds the keys of all its slots first (8W bytes each), then
-// their links (a parent and a jump word, 8 bytes each): SlotBytes is the total per slot.
-template <int W>
-struct SlotBytes { static constexpr uint32_t v = 8u * W + 8u; };
+// their links (a parent and a jump word, 8 bytes each): 8W + 8 bytes per slot.
 
 template <int W>
 struct Key {

@@ -1285,7 +1285,9 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
             const uint32_t leaf_slot = x.rmask ? sh.mslot[x.sgi][x.rmask] : segf;
             const uint32_t li = (uint32_t)n * BLOCK + tid;  // local index of the item
             par = x.j == 0u ? leaf_slot : (li ? sh.chunk_slot[li - 1] : sh.carry);
-            if (sg.lock) jmp = leaf_slot;
+            // a lock-step run, or a chain of units of unequal speed, jumps to the state it
+            // starts from: the trace regenerates the steps in between
+            if (sg.lock || (HET && sg.pad)) jmp = leaf_slot;
           }
           if (!linkless && (fresh[n] || cutlink[n])) {
             set_links<W>(md.table, md.mask, slot[n], par, jmp);

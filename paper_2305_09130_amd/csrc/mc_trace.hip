@@ -55,12 +55,153 @@ __global__ void k_find(QueryArgs a, Key<W> k) {
 // alike a dispatch leaf links to its closure's root, the inner closure states storing no
 // links: the states between the two are listed by starting the leaf's extra units one at
 // a time in index order.
+constexpr int kChaseE = 4096;     // operation ends of a workgroup the trace keeps in LDS
+constexpr int kChaseCand = 1024;  // candidate ends of one chain the trace merges
+
+// The number of E[0..b) at or below x (E ascending).
+__device__ __forceinline__ uint32_t ends_le_lds(const uint32_t* E, uint32_t b, uint32_t x) {
+  uint32_t lo = 0, cnt = b;
+  while (cnt) {
+    const uint32_t h = cnt >> 1;
+    if (E[lo + h] <= x) {
+      lo += h + 1u;
+      cnt -= h + 1u;
+    } else {
+      cnt = h;
+    }
+  }
+  return lo;
+}
+
+// The states of a chain of units of unequal speed from f (excluded) to x (included): the
+// distinct operation ends of f's busy units up to x's clock, each a state with the same
+// pending count.  Merged wavefront-wide like the exploration lists chains: lane i takes
+// candidate end i (unit u's k-th end after f), which counts where no unit of lower index
+// ends at the same time; its rank among the distinct times is the sum over units of the
+// counted ends before it, from an exclusive prefix sum of the counted flags.  The states
+// go out terminal-first at out[n..n+cnt).  Returns cnt, or 0 when the chain exceeds the LDS
+// tables (the caller follows the parent links instead); sets bad when the merge does not
+// end on x or passes cap.  E holds the configuration's operation ends (b <= kChaseE).
+template <int W>
+__device__ uint32_t chase_chain(const St& f, const St& x, const Key<W>& xk, const CfgRec& r,
+                                const Layout& L, int m, const uint32_t* E, uint32_t* S,
+                                unsigned long long* out, uint32_t n, uint32_t cap, bool& bad) {
+  const uint32_t lane = threadIdx.x;
+  uint32_t base[kMaxCU], sp[kMaxCU], k0[kMaxCU], nu[kMaxCU], O[kMaxCU + 1];
+  uint32_t C = 0;
+#pragma unroll
+  for (int u = 0; u < kMaxCU; ++u) {
+    base[u] = 0u;
+    sp[u] = 1u;
+    k0[u] = 0u;
+    nu[u] = 0u;
+    O[u] = C;
+    if (u < m && f.rem[u]) {
+      sp[u] = L.speed[u];
+      // elapsed e < sp*d; the ends after f are sp*E[k] > e, i.e. E[k] > floor(e / sp)
+      const uint32_t e = sp[u] * r.d - f.rem[u];
+      base[u] = f.clock - e;  // the workgroup's start on unit u
+      k0[u] = ends_le_lds(E, r.b, e / sp[u]);
+      const uint32_t hi = ends_le_lds(E, r.b, (x.clock - base[u]) / sp[u]);
+      nu[u] = hi > k0[u] ? hi - k0[u] : 0u;
+    }
+    C += nu[u];
+  }
+  O[kMaxCU] = C;
+  if (C == 0u || C > (uint32_t)kChaseCand) return 0u;
+  const auto cand = [&](uint32_t i, int& u, uint32_t& tau) {
+    u = 0;
+#pragma unroll
+    for (int j = 1; j < kMaxCU; ++j)
+      if (i >= O[j]) u = j;
+    tau = base[u] + sp[u] * E[k0[u] + (i - O[u])];
+  };
+  // counted flags: a time counts on the lowest unit that ends at it
+  for (uint32_t i = lane; i < C; i += 64u) {
+    int u;
+    uint32_t tau;
+    cand(i, u, tau);
+    bool first = true;
+    for (int j = 0; j < u; ++j) {
+      if (!nu[j] || tau < base[j] || (tau - base[j]) % sp[j]) continue;
+      const uint32_t xj = (tau - base[j]) / sp[j];
+      const uint32_t idx = ends_le_lds(E, r.b, xj);
+      if (idx > k0[j] && E[idx - 1u] == xj) first = false;
+    }
+    S[i] = first ? 1u : 0u;
+  }
+  __syncthreads();
+  {  // exclusive prefix sum of the flags in place; S[C] = their total
+    const uint32_t per = (C + 63u) / 64u, lo = lane * per;
+    const uint32_t hi = lo + per < C ? lo + per : C;
+    uint32_t sum = 0;
+    for (uint32_t i = lo; i < hi; ++i) sum += S[i];
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if ((int)lane >= off) incl += y;
+    }
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (uint32_t i = lo; i < hi; ++i) {
+      const uint32_t v = S[i];
+      S[i] = run;
+      run += v;
+    }
+    if (lane == 63u) S[C] = incl;
+  }
+  __syncthreads();
+  const uint32_t cnt = S[C];
+  if (cnt == 0u || n + cnt > cap) {
+    bad = true;
+    return 0u;
+  }
+  bool ends_on_x = false;
+  for (uint32_t i = lane; i < C; i += 64u) {
+    if (S[i + 1u] == S[i]) continue;  // not counted
+    int u;
+    uint32_t tau;
+    cand(i, u, tau);
+    uint32_t rank = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxCU; ++j) {
+      if (!nu[j]) continue;
+      // unit j's ends before tau: E[k] <= floor((tau - 1 - base_j) / sp_j)
+      const uint32_t lt = ends_le_lds(E, r.b, (tau - 1u - base[j]) / sp[j]);
+      uint32_t c = lt > k0[j] ? lt - k0[j] : 0u;
+      c = c < nu[j] ? c : nu[j];
+      rank += S[O[j] + c] - S[O[j]];
+    }
+    St y = f;
+    y.clock = tau;
+    for (int v = 0; v < m; ++v) {
+      const uint32_t wend = f.rem[v] ? base[v] + sp[v] * r.d : 0u;
+      y.rem[v] = wend > tau ? wend - tau : 0u;
+    }
+    const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+    for (int w = 0; w < W; ++w) out[(unsigned long long)(n + cnt - 1u - rank) * W + w] = yk.w[w];
+    if (rank + 1u == cnt) {
+      bool same = true;
+#pragma unroll
+      for (int w = 0; w < W; ++w) same = same && yk.w[w] == xk.w[w];
+      ends_on_x = same;
+    }
+  }
+  if (!__any(ends_on_x ? 1 : 0)) bad = true;
+  __syncthreads();
+  return cnt;
+}
+
 template <int W>
 __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* out, uint32_t cap) {
   if (blockIdx.x != 0) return;
   const uint32_t lane = threadIdx.x;
   const Layout& L = a.L;
   const int m = L.m;
+  __shared__ uint32_t sE[kChaseE];        // operation ends of the configuration being traced
+  __shared__ uint32_t sS[kChaseCand + 1];  // a chain's counted flags and their prefix sums
+  uint32_t e_cfg = 0xFFFFFFFFu;
   uint32_t s = a.ctrl->target_slot;
   uint32_t n = 0;
   bool bad = false;
@@ -157,6 +298,43 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
         }
       }
       s = par;
+      continue;
+    }
+    if (!L.shared_rem) {
+      // a chain of units of unequal speed: regenerated from the state it starts from
+      const unsigned long long* fp = slot_key<W>(a.table, jmp);
+      Key<W> fk;
+#pragma unroll
+      for (int w = 0; w < W; ++w) fk.w[w] = fp[w];
+      const St f = decode<W>(fk, L, a.cfgs);
+      const St x = decode<W>(k, L, a.cfgs);
+      if (f.cfg != x.cfg || f.cfg >= a.n_cfg || f.pending != x.pending || f.clock >= x.clock) {
+        bad = true;
+        break;
+      }
+      const CfgRec r = a.cfgs[f.cfg];
+      uint32_t cnt = 0;
+      if (r.b <= (uint32_t)kChaseE) {
+        if (f.cfg != e_cfg) {  // the configuration's operation ends, E[0..b)
+          __syncthreads();
+          for (uint32_t i = lane; i < r.b; i += 64u) sE[i] = end_at(r, i);
+          e_cfg = f.cfg;
+          __syncthreads();
+        }
+        cnt = chase_chain<W>(f, x, k, r, L, m, sE, sS, out, n, cap, bad);
+        if (bad) break;
+      }
+      if (cnt == 0u) {  // too long for the tables: the parent link instead
+        if (lane == 0) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) out[(unsigned long long)n * W + w] = k.w[w];
+        }
+        ++n;
+        s = par;
+        continue;
+      }
+      n += cnt;
+      s = jmp;
       continue;
     }
     // regenerate the run leaf -> s
