@@ -338,7 +338,7 @@ struct SegDesc {
   uint32_t fslot, nfree, aux, pad;  // pad: 1 for a chain (states listed in gkey)
 };
 
-template <int BLOCK, int NI, int SEGS = kSegMax>
+template <int BLOCK, int NI, int SEGS, int KW>  // KW: words of a key
 struct SuperShared {
   uint32_t E[kEMax];
   uint32_t mslot[SEGS][256];
@@ -346,7 +346,7 @@ struct SuperShared {
   uint32_t chunk_slot[NI * BLOCK];
   SegDesc seg[SEGS];
   uint32_t segfslot[SEGS];
-  unsigned long long fkey[2][kFCap][4];
+  unsigned long long fkey[2][kFCap][KW];
   uint32_t fslot[2][kFCap];
   uint32_t fdep[2][kFCap];
   uint32_t fcount[2];
@@ -358,14 +358,14 @@ struct SuperShared {
   uint32_t chain_more;  // another chain joined the batch: list it
   // end of a block of rounds: the state B_r1, its clock and depth, the batch item that
   // generates it, and whether it was reached
-  unsigned long long stopkey[4];
+  unsigned long long stopkey[KW];
   uint32_t has_stop, stop_clock, stop_dep, stop_item, stop_slot, handed;
   uint32_t stop_capped;  // B_r1 ends a run cut short by run slices: no item generates it
   uint32_t T;   // prune threshold of this super-step (check(T), or the incumbent)
   ModelDev md;  // descriptor of the model being explored
   // successors of the leaves of a segment whose run is not in lock step (one ADVANCE
   // each), computed once per super-step outside the batch loop
-  unsigned long long gkey[kMaxLeaves][4];
+  unsigned long long gkey[kMaxLeaves][KW];
   uint32_t gclk[kMaxLeaves];
   uint32_t gterm[kMaxLeaves];
 };
@@ -399,7 +399,7 @@ struct Item {
 // j-th state of a run from a leaf, built directly from the segment's templates.
 template <int W, int BLOCK, int NI, bool KEY, bool GEN, bool HET, int SEGS>
 __device__ __forceinline__ void gen_item(uint32_t i, uint32_t total, uint32_t nseg,
-                                         const SuperShared<BLOCK, NI, SEGS>& sh, const CfgRec& r,
+                                         const SuperShared<BLOCK, NI, SEGS, W>& sh, const CfgRec& r,
                                          bool e_lds, const ModelDev& md, int m, Item<W>& it) {
   const Layout& L = md.L;
   it.active = i < total;
@@ -544,7 +544,7 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
 // order, as the chain's states, from E[kChainTimes + idx0] (the batch's chains are
 // listed one after another).  Their number is the segment's length.
 template <int W, int BLOCK, int NI, int SEGS>
-__device__ __noinline__ void build_chain(SuperShared<BLOCK, NI, SEGS>& sh, const CfgRec& r,
+__device__ __noinline__ void build_chain(SuperShared<BLOCK, NI, SEGS, W>& sh, const CfgRec& r,
                                          const Layout& L, int m) {
   const uint32_t tid = threadIdx.x;
   SegDesc& sg = sh.seg[sh.nseg - 1];
@@ -673,7 +673,7 @@ __device__ __noinline__ void build_chain(SuperShared<BLOCK, NI, SEGS>& sh, const
 // continues it.  sh.chain_more tells the workgroup to list the new chain.  Only a
 // choice among units, a terminal, the prune threshold or the batch's room ends a batch.
 template <int W, int BLOCK, int NI, int SEGS, bool GEN>
-__device__ __noinline__ void extend_chain(SuperShared<BLOCK, NI, SEGS>& sh, const CfgRec& r,
+__device__ __noinline__ void extend_chain(SuperShared<BLOCK, NI, SEGS, W>& sh, const CfgRec& r,
                                           const ModelDev& md, int m, uint32_t batch_items) {
   const Layout& L = md.L;
   sh.chain_more = 0u;
@@ -778,7 +778,7 @@ __device__ __forceinline__ uint32_t prune_T(const ModelDev& md) {
 template <int W, int BLOCK, int NI, bool GEN, bool HET, int SEGS>
 __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t batch_items,
                                   uint32_t slice, const PartQueue& pq,
-                                  SuperShared<BLOCK, NI, SEGS>& sh) {
+                                  SuperShared<BLOCK, NI, SEGS, W>& sh) {
   Tally tl;
   const Layout& L = md.L;
   const int m = L.m;
@@ -806,7 +806,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
       field_add<W>(k1, L, kFClock, (unsigned long long)pt.r1 * r.d);
       field_add<W>(k1, L, kFPending, (unsigned long long)(-(long long)pt.r1 * m));
 #pragma unroll
-      for (int w = 0; w < 4; ++w) sh.stopkey[w] = w < W ? k1[w] : 0ull;
+      for (int w = 0; w < W; ++w) sh.stopkey[w] = k1[w];
       sh.stop_clock = pt.r1 * r.d;
       sh.stop_dep = sd.depth + pt.r1 * round_dep;
       sh.has_stop = 1u;
@@ -814,7 +814,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
     if (md.pstate && md.pstate[pt.pidx].status == 1u) {  // resume a partition that yielded
       const PartState ps = md.pstate[pt.pidx];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = ps.k[w];
+      for (int w = 0; w < W; ++w) sh.fkey[0][0][w] = ps.k[w];
       sh.fslot[0][0] = ps.slot;
       sh.fdep[0][0] = ps.depth;
       sh.fcount[0] = 1u;
@@ -880,7 +880,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
         }
       }
 #pragma unroll
-      for (int w = 0; w < 4; ++w) sh.fkey[0][0][w] = w < W ? k0[w] : 0ull;
+      for (int w = 0; w < W; ++w) sh.fkey[0][0][w] = k0[w];
       sh.fslot[0][0] = slot0;
       sh.fdep[0][0] = dep0;
     }
@@ -896,7 +896,7 @@ __device__ void explore_partition(const ModelDev& md, const Part pt, uint32_t ba
       if (tid == 0) {
         PartState ps;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) ps.k[w] = sh.fkey[cur][0][w];
+        for (int w = 0; w < 4; ++w) ps.k[w] = w < W ? sh.fkey[cur][0][w] : 0ull;
         ps.slot = sh.fslot[cur][0];
         ps.depth = sh.fdep[cur][0];
         ps.status = 1u;
@@ -1365,7 +1365,7 @@ __device__ __forceinline__ void flush_tally(const ModelDev& md, const Tally& tl)
 // block's boundary states; no state of a slice has a (pending, clock) pair that another
 // partition's states have.
 template <int W, int BLOCK, int NI, bool GEN, int SEGS>
-__device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLOCK, NI, SEGS>& sh) {
+__device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLOCK, NI, SEGS, W>& sh) {
   Tally tl;
   const Layout& L = md.L;
   const int m = L.m;
@@ -1476,9 +1476,12 @@ __device__ void explore_slice(const ModelDev& md, const Part pt, SuperShared<BLO
   flush_tally(md, tl);
 }
 
+// The unequal-speed build at 512 threads asks for four waves per SIMD (at most 128 VGPRs):
+// with its LDS under half a CU's, two workgroups then share a CU, and a partition's
+// serial sections (listing a chain, the super-step's barriers) overlap another's.
 template <int W, int BLOCK, int NI, bool GEN, bool HET>
-__global__ __launch_bounds__(BLOCK) void k_superstep(PartQueue a) {
-  __shared__ SuperShared<BLOCK, NI, HET ? kSegMaxChain : kSegMax> sh;
+__global__ __launch_bounds__(BLOCK, (HET && BLOCK == 512) ? 4 : 1) void k_superstep(PartQueue a) {
+  __shared__ SuperShared<BLOCK, NI, HET ? kSegMaxChain : kSegMax, W> sh;
   const uint32_t tid = threadIdx.x;
   for (;;) {
     if (tid == 0) {
