@@ -258,7 +258,9 @@ def swarm_leg(mc, workloads, names, members: int = 16384, bits_log2: int = 16,
               budget: int = 20000):
     """The swarm search of Sec. 5 on each named workload: one swarm against G(!FIN)
     (time to its first trail, that trail's optimality T_min / T_first), then the search
-    loop with the over-time property; against the exact min_time on the same GPU."""
+    loop with the over-time property; against the exact min_time on the same GPU (best
+    of three launches).  The first trail is the first on the device clock, so which
+    member's trail it is, and its optimality, can change from run to run."""
     out = {}
     # the swarm's bit arrays and member records live in the visited-set region
     need = members * ((1 << bits_log2) // 8 + 128)
@@ -270,6 +272,9 @@ def swarm_leg(mc, workloads, names, members: int = 16384, bits_log2: int = 16,
             g = mc.Model(model, log2_slots=max(10, (need // 16 - 1).bit_length()))
         t_min, _ = g.mc_min_time()
         exact_ms = g.last_stats["engine_ns"] / 1e6
+        for _ in range(2):  # the first call also pays the first launch of its instance
+            g.mc_min_time()
+            exact_ms = min(exact_ms, g.last_stats["engine_ns"] / 1e6)
         r = g.mc_swarm(members, bits_log2, budget, 1)
         t0 = time.perf_counter()
         t_found, rounds, best = g.mc_swarm_tune(members, bits_log2, budget, 1)

@@ -237,3 +237,30 @@ def test_hetero_workloads_sliced_full_size(mc):
         assert g.mc_terminal_clocks() == r["tc"]
         oracle.check_trace(model, g.mc_trace(), target_clock=r["t_min"], cfgs=r["argmin"])
         g.close()
+
+
+def _long_chain_models():
+    """One 16-item workgroup per dispatch with K / 16 * 80 operation ends (b): chains
+    between dispatches and the tails after the last one run from a few hundred to many
+    thousand states."""
+    w = workloads
+    return [(w.with_speeds(w.matmul_model(16, 16, K, m, [16], [1], [1], [1], 23, 3), sp), b)
+            for K, m, sp, b in ((64, 2, [1, 2], 320), (128, 2, [1, 2], 640),
+                                (256, 3, [1, 2, 3], 1280), (1024, 2, [2, 1], 5120))]
+
+
+def test_hetero_long_chain_traces(mc):
+    """Counterexamples through long chains of units of unequal speed, replayed through the
+    oracle: the trace rebuilds a chain wavefront-wide from the state it starts from (several
+    candidate ends per lane at b = 320), and follows parent links one state at a time where
+    a chain has more than 1,024 candidate ends (the tails at b = 640 and 1280) or a
+    workgroup more than 4,096 operation ends (b = 5120)."""
+    for model, b in _long_chain_models():
+        _say(f"long chains b={b}: {workloads.describe(model)}")
+        assert len(mc.mc_config_ends(model, 0)["E"]) == b
+        r = oracle.explore(model)
+        g = mc.Model(model)
+        check_min_time(g, model, r, ENGINES["superstep"])
+        for T in (r["t_min"] - 1, r["t_min"]):
+            check_threshold(mc, g, model, T)
+        g.close()
