@@ -258,9 +258,22 @@ ChainCount walk_unequal(const CfgRec& r, const uint32_t* sp, uint32_t m, uint64_
       jumped = true;
       const uint64_t J = p / Wp, dS = out.states - 1, dD = dep;
       if (cuts)
-        for (uint64_t j = 1; j <= J; ++j)
-          for (const ChainCut& c : period)
-            record(ChainCut{c.t + j * P, c.depth + j * dD, c.states + j * dS});
+        for (uint64_t j = 1; j <= J; ++j) {
+          // record() takes a candidate at least `spacing` states past the last one
+          // taken, and the period's states ascend: search for the next such candidate
+          // instead of offering it every one
+          auto it = period.begin();
+          for (;;) {
+            const uint64_t want = last + spacing;  // in states, after the shift by j periods
+            const uint64_t lo = want > j * dS ? want - j * dS : 0;
+            it = std::lower_bound(it, period.end(), lo, [](const ChainCut& c, uint64_t v) {
+              return c.states < v;
+            });
+            if (it == period.end()) break;
+            record(ChainCut{it->t + j * P, it->depth + j * dD, it->states + j * dS});
+            ++it;
+          }
+        }
       out.states += J * dS;
       dep += J * dD;
       t += J * P;
