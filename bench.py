@@ -92,10 +92,17 @@ def read_traffic(workload: str, kernel: str, src_hash: str, slots: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_step(mc, model, engine, workspace, block, load_factor=0.0):
+def run_step(mc, model, engine, workspace, block, load_factor=0.0, handle=None):
+    """One tuning query: load the model (into `handle`, the query's handle kept across
+    steps, when given; else into a new one, freed at the end), min_time, its trace and
+    check(T_min - 1)."""
     t0 = time.perf_counter()
-    g = mc.Model(model, engine=engine, block=block, workspace=workspace,
-                 load_factor=load_factor)
+    if handle is not None:
+        handle.mc_model_reload(model)
+        g = handle
+    else:
+        g = mc.Model(model, engine=engine, block=block, workspace=workspace,
+                     load_factor=load_factor)
     t1 = time.perf_counter()
     t_min, argmin = g.mc_min_time()
     st_min = dict(g.last_stats)
@@ -105,7 +112,8 @@ def run_step(mc, model, engine, workspace, block, load_factor=0.0):
     holds = not g.mc_check(t_min - 1)
     st_chk = dict(g.last_stats)
     slots = g.mc_model_info_get()["slots"]
-    g.close()
+    if handle is None:
+        g.close()
     t4 = time.perf_counter()
     return {"t_min": t_min, "argmin": argmin, "trace_len": len(trace), "minimal": holds,
             "states": st_min["states"] + st_chk["states"], "min_states": st_min["states"],
@@ -311,12 +319,15 @@ def model_leg(mc, torch, models: dict, reps: int, cpu: bool):
     for name, model in models.items():
         nbytes = mc.mc_workspace_bytes(model)
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
-        run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0)
+        g = mc.Model(model, workspace=ws)
+        run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0, handle=g)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        steps = [run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0) for _ in range(reps)]
+        steps = [run_step(mc, model, mc.MC_ENGINE_SUPERSTEP, ws, 0, handle=g)
+                 for _ in range(reps)]
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        g.close()
         del ws
         states = sum(s["states"] for s in steps)
         eng_s = sum(s["engine_ns_min"] for s in steps) * 1e-9 / reps
@@ -590,16 +601,21 @@ def main():
     # validates, builds, plans and uploads the model)
     import numpy as np
     model_in = dict(model, params=np.ascontiguousarray(model["params"], dtype=np.uint32))
+    # the query handle over the workspace, kept across steps: each step reloads its model
+    handle = mc.Model(model_in, engine=mc.MC_ENGINE_SUPERSTEP, block=args.block,
+                      workspace=workspace, load_factor=args.load_factor)
     for _ in range(args.warmup):
-        run_step(mc, model_in, mc.MC_ENGINE_SUPERSTEP, workspace, args.block, args.load_factor)
+        run_step(mc, model_in, mc.MC_ENGINE_SUPERSTEP, workspace, args.block, args.load_factor,
+                 handle=handle)
     torch.cuda.synchronize()
     steps = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         steps.append(run_step(mc, model_in, mc.MC_ENGINE_SUPERSTEP, workspace, args.block,
-                              args.load_factor))
+                              args.load_factor, handle=handle))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    handle.close()  # before the workspace serves other handles
     states = sum(s["states"] for s in steps)
     assert all(s["minimal"] for s in steps)
     lat = sorted(s["seconds"] for s in steps)

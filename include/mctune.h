@@ -216,12 +216,29 @@ int mc_config_ends(const mc_desc *d, uint32_t cfg, uint32_t *n, uint32_t *b, uin
 
 /* Load a model: validates, derives per-configuration tables, uploads them into
  * the caller's workspace and binds the stream.  dev_ws: device memory of ws_bytes
- * bytes owned by the caller, kept alive until mc_model_free.  stream: hipStream_t
- * (NULL = default stream).  The library owns *out.
+ * bytes owned by the caller, kept alive and left alone until mc_model_free.  stream:
+ * hipStream_t (NULL = default stream).  The library owns *out.
+ * Every call on the handle is ordered on that stream.  Besides it the handle holds a side
+ * stream of its own: a query that needs less of the visited set than earlier queries
+ * wrote clears the bytes past its own there, while it runs, so that a later larger
+ * query finds them cleared; the handle's stream waits for that clear before it next
+ * touches the workspace, and mc_model_free waits for it too.
  * MC_E_NOMEM if ws_bytes < mc_workspace_bytes(); MC_E_DEVICE wraps a HIP error. */
 int mc_model_load(const mc_desc *d, const mc_opts *o, void *dev_ws, size_t ws_bytes,
                   void *stream, mc_model **out);
 
+/* Replace the handle's model with d (the next tuning query, Sec. 4 step 1), with the
+ * options, workspace and stream given at load: validates, derives the tables, uploads
+ * them and starts the handle's query state over (no trace, nothing resident).  The bytes
+ * of the visited set known to be cleared stay known, so a query after the reload clears only
+ * what earlier queries wrote of what it needs.
+ * MC_E_INVAL (bad descriptor) and MC_E_NOMEM (the workspace is too small for d): the
+ * handle keeps its model.  MC_E_DEVICE wraps a HIP error; the handle can then only be
+ * freed. */
+int mc_model_reload(mc_model *h, const mc_desc *d);
+
+/* Frees the handle after waiting for its side stream; the workspace is the caller's
+ * again. */
 int mc_model_free(mc_model *h);
 int mc_model_info_get(const mc_model *h, mc_model_info *info);
 

@@ -147,6 +147,7 @@ _SIGS = {
     "mc_workspace_bytes": ([_P(McDesc), _P(McOpts), _P(ctypes.c_size_t)], ctypes.c_int),
     "mc_model_load": ([_P(McDesc), _P(McOpts), _vp, ctypes.c_size_t, _vp, _P(_vp)], ctypes.c_int),
     "mc_model_free": ([_vp], ctypes.c_int),
+    "mc_model_reload": ([_vp, _P(McDesc)], ctypes.c_int),
     "mc_model_info_get": ([_vp, _P(McModelInfo)], ctypes.c_int),
     "mc_set_engine": ([_vp, ctypes.c_uint32], ctypes.c_int),
     "mc_abort": ([_vp], ctypes.c_int),
@@ -348,6 +349,17 @@ class Model:
         _check("mc_model_load", rc)
         self._h = h
         self.last_stats: dict = {}
+
+    def mc_model_reload(self, model: dict) -> None:
+        """The next model on this handle, its workspace and its stream (the options given
+        at construction)."""
+        desc, params = make_desc(model)
+        _check("mc_model_reload", _lib.mc_model_reload(self._h, ctypes.byref(desc)))
+        self.model = model
+        self.m = model["m"]
+        self.n_cfg = len(model["params"])
+        self._desc, self._params = desc, params
+        self.last_stats = {}
 
     def close(self) -> None:
         if getattr(self, "_h", None):

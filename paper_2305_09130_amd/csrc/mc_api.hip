@@ -73,7 +73,13 @@ int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) 
   }
   const uint32_t W = mh.W;
   const size_t entry = 8ull * W + 8ull;
-  size_t off = 0;
+  // the visited set first: it starts at the same place for every model, so a handle that
+  // loads another model knows which of its bytes are still cleared
+  p->slots = slots;
+  p->slot_bytes = slot_bytes_for(W);
+  p->table = 0;
+  p->table_bytes = (size_t)slots * p->slot_bytes;
+  size_t off = align_up(p->table_bytes);
   p->ctrl = off;   off = align_up(off + sizeof(Ctrl));
   p->tc = off;     off = align_up(off + 4ull * mh.n_cfg);
   p->cfgs = off;   off = align_up(off + sizeof(CfgRec) * mh.n_cfg);
@@ -87,11 +93,6 @@ int plan_ws(const ModelHost& mh, const mc_opts& o, uint64_t n_parts, WsPlan* p) 
   p->front1 = off; off = align_up(off + entry * p->fcap);
   p->trace_cap = mh.max_depth + 2;
   p->trace = off;  off = align_up(off + 8ull * W * p->trace_cap);
-  p->slots = slots;
-  p->slot_bytes = slot_bytes_for(W);
-  p->table = off;
-  p->table_bytes = (size_t)slots * p->slot_bytes;
-  off = align_up(off + p->table_bytes);
   p->total = off;
   return MC_OK;
 }
@@ -175,7 +176,21 @@ struct mc_model {
   // query that returns MC_E_ABORTED clears it
   unsigned int* habort = nullptr;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  bool dirty = true;
+  // Clearing the visited set.  Bytes [0, dirty_in) of the table may hold an earlier
+  // query's data; the rest of [0, max_need) is cleared (empty slots) once the side
+  // stream's clear, if one is pending, has ended.  max_need: the most a query of this model
+  // needs cleared (every key; with units of unequal speed every slot).  A query clears what
+  // it needs of the dirty prefix on the handle's stream, and once its results are on their
+  // way hands the dirty bytes past those it touched to the side stream (pooled handles),
+  // which clears them while the host reads the results and loads the next query.
+  uint64_t dirty_in = 0, max_need = 0;
+  uint64_t behind_lo = 0, behind_hi = 0;  // the current query's bytes to clear behind it
+  uint64_t side_hi = 0;                    // end of the side stream's pending clear
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_side = nullptr;
+  bool side_pending = false;
+  mc_opts opts_in{};  // the options given at load: a reload derives its own from them
+  size_t ws_bytes = 0;
   int last = kQueryNone;
   uint32_t last_T = 0;
   int last_violated = 0;
@@ -214,6 +229,74 @@ QueryArgs make_args(mc_model* h, bool prune, uint32_t T) {
   q.max_clock = h->mh.max_clock;
   q.hkeep = h->opts.test_hash_bits;
   return q;
+}
+
+// Bytes of the table a query with q slots needs cleared (its keys; with units of unequal
+// speed its links too), and the bytes it may write (keys and links), within max_need.
+uint64_t need_bytes(const mc_model* h, uint64_t q) {
+  return q * (h->mh.hetero ? (uint64_t)h->plan.slot_bytes : 8ull * h->mh.W);
+}
+uint64_t touched_bytes(const mc_model* h, uint64_t q) {
+  return std::min<uint64_t>(q * h->plan.slot_bytes, h->max_need);
+}
+
+// Orders the handle's stream after the side stream's clear, if one is in flight: every
+// use that may touch the table or the regions after it (a query, a swarm, a reload's
+// uploads) calls this first.
+hipError_t join_side(mc_model* h) {
+  if (!h->side_pending) return hipSuccess;
+  h->side_pending = false;
+  return hipStreamWaitEvent(h->stream, h->ev_side, 0);
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // unknown: keep to the one stream
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Before a query whose visited set has q slots: clears the dirty part of what it needs on
+// the handle's stream (between events ev[0] and ev[1]; *cleared says whether it did), and
+// notes the dirty bytes past what it touches, which finish_query hands to the side stream.
+int prepare_table(mc_model* h, uint64_t q, bool* cleared) {
+  hipStream_t s = h->stream;
+  HIPCHK(join_side(h));
+  const uint64_t need = need_bytes(h, q), touched = touched_bytes(h, q);
+  const uint64_t now = std::min<uint64_t>(need, h->dirty_in);
+  h->behind_lo = h->behind_hi = 0;
+  if (h->dirty_in > touched && h->side && !capturing(s)) {
+    h->behind_lo = touched;
+    h->behind_hi = h->dirty_in;
+  }
+  *cleared = now > 0;
+  if (now) {
+    HIPCHK(ev_record(h->ev[0], s));
+    HIPCHK(launch_clear(s, h->table, now));
+    HIPCHK(ev_record(h->ev[1], s));
+  }
+  h->dirty_in = std::max<uint64_t>(h->dirty_in, touched);  // what the query will write
+  return MC_OK;
+}
+
+// After a query's launches and the copies of its results: clears the dirty bytes past the
+// ones it touched on the side stream.  Started there rather than beside the query, the
+// clear's workgroups do not hold back the query's own (a latency-bound launch) or its
+// result copies; it runs while the host reads the results and prepares the next query.
+int clear_behind(mc_model* h) {
+  if (h->behind_hi <= h->behind_lo) return MC_OK;
+  const uint64_t lo = h->behind_lo, hi = h->behind_hi;
+  h->behind_lo = h->behind_hi = 0;
+  HIPCHK(hipEventRecord(h->ev_fork, h->stream));
+  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  HIPCHK(launch_clear(h->side, h->table + lo, hi - lo));
+  HIPCHK(hipEventRecord(h->ev_side, h->side));
+  h->side_pending = true;
+  h->side_hi = hi;
+  h->dirty_in = lo;  // [lo, hi) is the side stream's; past hi it was cleared already
+  return MC_OK;
 }
 
 template <int W>
@@ -318,15 +401,9 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
     h->parts_resumed = false;
   }
   h->q_parts = n_parts;
+  // units alike need their keys cleared only (their links are read only where written)
   bool cleared = false;
-  if (h->dirty) {
-    HIPCHK(ev_record(h->ev[0], s));
-    // units alike clear the keys only (their links are read only where written)
-    HIPCHK(launch_clear(s, h->table,
-                        h->q_slots * (h->mh.hetero ? h->plan.slot_bytes : 8ull * h->mh.W)));
-    HIPCHK(ev_record(h->ev[1], s));
-    cleared = true;
-  }
+  if (const int prc = prepare_table(h, h->q_slots, &cleared)) return prc;
   const QueryArgs q = make_args(h, prune, T);
   uint64_t launches = 0;
   int rc = MC_OK;
@@ -381,7 +458,6 @@ int run_query(mc_model* h, bool prune, uint32_t T, mc_stats* st, bool bb = false
       default: rc = explore_w<4>(h, q, &launches); break;
     }
   }
-  h->dirty = true;
   if (rc != MC_OK) {
     (void)hipStreamSynchronize(s);
     return rc;
@@ -396,6 +472,7 @@ int finish_query(mc_model* h, std::chrono::steady_clock::time_point t0, bool cle
   HIPCHK(ev_record(h->ev[3], s));
   HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(h->tc_host, h->tc, 4ull * h->mh.n_cfg, hipMemcpyDeviceToHost, s));
+  if (const int crc = clear_behind(h)) return crc;
   HIPCHK(hipStreamSynchronize(s));
   const int derr = dev_error_code(h->hctrl->error);
   if (derr == MC_E_ABORTED && h->habort) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
@@ -440,6 +517,9 @@ int run_resume(mc_model* h, uint32_t T, mc_stats* st) {
   hipStream_t s = h->stream;
   h->trace_ready = false;
   h->last = kQueryNone;
+  HIPCHK(join_side(h));
+  h->behind_lo = h->behind_hi = 0;  // a continued exploration clears nothing behind it
+  h->dirty_in = std::max<uint64_t>(h->dirty_in, touched_bytes(h, h->q_slots));
   std::vector<PartPlan> fresh(h->parts_host.size()), plan;
   for (size_t i = 0; i < fresh.size(); ++i) {
     const Part& p = h->parts_host[i];
@@ -608,8 +688,13 @@ int mc_workspace_bytes(const mc_desc* d, const mc_opts* o, size_t* bytes) {
 int mc_model_free(mc_model* h) {
   if (!h) return MC_E_INVAL;
   if (h->pooled) {
+    // the side stream may still be clearing bytes of the caller's workspace
+    if (h->side) (void)hipStreamSynchronize(h->side);
     for (auto& e : h->ev)
       if (e) event_put(e);
+    if (h->ev_fork) event_put(h->ev_fork);
+    if (h->ev_side) event_put(h->ev_side);
+    if (h->side) stream_put(h->side);
     if (h->pin) pinned_put(h->pin, h->pin_bytes);
   }
   delete h;
@@ -620,108 +705,161 @@ int mc_model_free(mc_model* h) {
 
 namespace {
 
+// The host side of a load: the model, its options, its partitions and its workspace plan.
+struct Loaded {
+  ModelHost mh;
+  mc_opts opts{};
+  WsPlan plan;
+  std::vector<Part> parts;
+};
+
+int prepare_load(const mc_desc* d, const mc_opts& opts_in, size_t ws_bytes, Loaded* L) {
+  std::string err;
+  int rc = build_model(d, &L->mh, &err);
+  if (rc) return rc;
+  L->opts = opts_in;
+  L->parts = model_parts(L->mh, L->opts);
+  rc = plan_ws(L->mh, L->opts, L->parts.size(), &L->plan);
+  if (rc) return rc;
+  if (ws_bytes < L->plan.total) return MC_E_NOMEM;
+  // automatic workgroup size: with fewer partitions than a wide launch has workgroups,
+  // each runs nearly alone on its compute unit and its chain of insert round trips is
+  // the launch time, which 512 threads shorten; with many, 256 keeps more of them
+  // resident
+  // units of unequal speed: 512 (their chain listing is block-wide; on the 1.4M-state
+  // workload the launch took 0.70 ms against 0.95 with 256 and 0.83 with 1024)
+  if (!L->opts.block)
+    L->opts.block = (L->mh.hetero || L->parts.size() < kWideParts) ? 512u : 256u;
+  return MC_OK;
+}
+
+// Bytes of the table that a query of the model may need cleared (see mc_model::max_need).
+uint64_t max_need_of(const Loaded& L) {
+  return L.plan.slots * (L.mh.hetero ? (uint64_t)L.plan.slot_bytes : 8ull * L.mh.W);
+}
+
+// Puts a prepared model into a handle whose stream, workspace and pooled objects are set:
+// its regions, its staging and the upload of its tables.  The per-query state starts over.
+int install(mc_model* h, Loaded& L) {
+  h->mh = std::move(L.mh);
+  h->opts = L.opts;
+  h->plan = L.plan;
+  h->parts_host = std::move(L.parts);
+  h->ctrl = reinterpret_cast<Ctrl*>(h->ws + h->plan.ctrl);
+  h->tc = reinterpret_cast<uint32_t*>(h->ws + h->plan.tc);
+  h->cfgs = reinterpret_cast<CfgRec*>(h->ws + h->plan.cfgs);
+  h->parts = reinterpret_cast<Part*>(h->ws + h->plan.order);
+  h->dmd = reinterpret_cast<ModelDev*>(h->ws + h->plan.md);
+  h->head = reinterpret_cast<unsigned int*>(h->ws + h->plan.head);
+  h->seeds = reinterpret_cast<Seed*>(h->ws + h->plan.seeds);
+  h->front[0] = h->ws + h->plan.front0;
+  h->front[1] = h->ws + h->plan.front1;
+  h->trace_buf = reinterpret_cast<unsigned long long*>(h->ws + h->plan.trace);
+  h->table = h->ws + h->plan.table;
+  h->q_slots = h->plan.slots;
+  h->q_parts = 0;
+  const std::vector<Part>& parts = h->parts_host;
+  h->n_parts = (uint32_t)parts.size();
+  h->trace_ready = false;
+  h->trace_rows.clear();
+  h->last = kQueryNone;
+  h->last_T = 0;
+  h->last_violated = 0;
+  h->swarm_members = 0;
+  h->swarm_best = false;
+  h->resident = false;
+  h->resident_T = 0;
+  h->parts_resumed = false;
+  // one staging block: counters, poll words, descriptor, clocks and, when small, the
+  // staging of the uploads below
+  static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "staging block layout");
+  const size_t tc_off = 768, up_off = align_up(tc_off + 4ull * h->mh.n_cfg);
+  const size_t cfg_bytes = sizeof(CfgRec) * h->mh.n_cfg, part_bytes = sizeof(Part) * parts.size();
+  const bool stage = cfg_bytes + part_bytes <= (4u << 20);
+  const size_t pin_bytes = stage ? up_off + cfg_bytes + part_bytes : up_off;
+  unsigned char* blk = nullptr;
+  if (h->pooled) {
+    if (!h->pin || pin_bytes > h->pin_bytes) {
+      unsigned char* nb = static_cast<unsigned char*>(pinned_get(pin_bytes));
+      if (!nb) return MC_E_DEVICE;
+      if (h->pin) pinned_put(h->pin, h->pin_bytes);
+      h->pin = nb;
+      h->pin_bytes = pin_bytes;
+    }
+    blk = h->pin;
+  } else {
+    h->host_stage.assign(pin_bytes, 0);
+    blk = h->host_stage.data();
+  }
+  h->hctrl = reinterpret_cast<Ctrl*>(blk);
+  h->hpoll = reinterpret_cast<uint32_t*>(blk + 256);
+  // the stop request is a word the kernels read at system scope: pinned memory only
+  h->habort = h->pooled ? reinterpret_cast<unsigned int*>(blk + 256 + 128) : nullptr;
+  if (h->habort) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
+  h->hmd = reinterpret_cast<ModelDev*>(blk + 512);
+  h->tc_host = reinterpret_cast<uint32_t*>(blk + tc_off);
+  for (uint32_t c = 0; c < h->mh.n_cfg; ++c) h->tc_host[c] = kNoClock;
+  const void* up_cfg = h->mh.cfgs.data();
+  const void* up_part = parts.data();
+  if (stage) {
+    std::memcpy(blk + up_off, up_cfg, cfg_bytes);
+    std::memcpy(blk + up_off + cfg_bytes, up_part, part_bytes);
+    up_cfg = blk + up_off;
+    up_part = blk + up_off + cfg_bytes;
+  }
+  hipStream_t s = h->stream;
+  if (hipMemcpyAsync(h->cfgs, up_cfg, cfg_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->parts, up_part, part_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return MC_E_DEVICE;
+  }
+  return MC_OK;
+}
+
 // Builds a handle over a caller's workspace.  pooled: counters, descriptor and clocks
-// are staged in a pooled pinned block and the query is timed with pooled events (the
-// ordinary handle); otherwise they are staged in ordinary host memory and no runtime
-// object is created (the handle over the static scratch).
+// are staged in a pooled pinned block, the query is timed with pooled events and dead
+// bytes of the visited set are cleared on a pooled side stream (the ordinary handle);
+// otherwise they are staged in ordinary host memory and no runtime object is created
+// (the handle over the static scratch).
 int bind_model(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_bytes, void* stream,
                bool pooled, mc_model** out) {
   if (!out || !dev_ws) return MC_E_INVAL;
   *out = nullptr;
   mc_model* h = nullptr;
   try {
+    Loaded L;
+    const mc_opts opts_in = default_opts(o);
+    int rc = prepare_load(d, opts_in, ws_bytes, &L);
+    if (rc) return rc;
     h = new mc_model();
     h->pooled = pooled;
-    std::string err;
-    int rc = build_model(d, &h->mh, &err);
-    if (rc) {
-      delete h;
-      return rc;
-    }
-    h->opts = default_opts(o);
-    rc = plan_ws(h->mh, h->opts, model_parts(h->mh, h->opts).size(), &h->plan);
-    if (rc) {
-      delete h;
-      return rc;
-    }
-    if (ws_bytes < h->plan.total) {
-      delete h;
-      return MC_E_NOMEM;
-    }
+    h->opts_in = opts_in;
     h->stream = reinterpret_cast<hipStream_t>(stream);
     h->ws = reinterpret_cast<unsigned char*>(dev_ws);
-    h->ctrl = reinterpret_cast<Ctrl*>(h->ws + h->plan.ctrl);
-    h->tc = reinterpret_cast<uint32_t*>(h->ws + h->plan.tc);
-    h->cfgs = reinterpret_cast<CfgRec*>(h->ws + h->plan.cfgs);
-    h->parts = reinterpret_cast<Part*>(h->ws + h->plan.order);
-    h->dmd = reinterpret_cast<ModelDev*>(h->ws + h->plan.md);
-    h->head = reinterpret_cast<unsigned int*>(h->ws + h->plan.head);
-    h->seeds = reinterpret_cast<Seed*>(h->ws + h->plan.seeds);
-    h->front[0] = h->ws + h->plan.front0;
-    h->front[1] = h->ws + h->plan.front1;
-    h->trace_buf = reinterpret_cast<unsigned long long*>(h->ws + h->plan.trace);
-    h->table = h->ws + h->plan.table;
-    h->q_slots = h->plan.slots;
-    h->parts_host = model_parts(h->mh, h->opts);
-    const std::vector<Part>& parts = h->parts_host;
-    h->n_parts = (uint32_t)parts.size();
-    // automatic workgroup size: with fewer partitions than a wide launch has workgroups,
-    // each runs nearly alone on its compute unit and its chain of insert round trips is
-    // the launch time, which 512 threads shorten; with many, 256 keeps more of them
-    // resident
-    // units of unequal speed: 512 (their chain listing is block-wide; on the 1.4M-state
-    // workload the launch took 0.77 ms against 0.94 with 256 and 0.85 with 1024)
-    if (!h->opts.block)
-      h->opts.block = (h->mh.hetero || h->n_parts < kWideParts) ? 512u : 256u;
-    // one staging block: counters, poll words, descriptor, clocks and, when small, the
-    // staging of the uploads below
-    static_assert(sizeof(Ctrl) <= 256 && sizeof(ModelDev) <= 256, "staging block layout");
-    const size_t tc_off = 768, up_off = align_up(tc_off + 4ull * h->mh.n_cfg);
-    const size_t cfg_bytes = sizeof(CfgRec) * h->mh.n_cfg, part_bytes = sizeof(Part) * parts.size();
-    const bool stage = cfg_bytes + part_bytes <= (4u << 20);
-    h->pin_bytes = stage ? up_off + cfg_bytes + part_bytes : up_off;
-    unsigned char* blk = nullptr;
+    h->ws_bytes = ws_bytes;
+    h->max_need = max_need_of(L);
+    h->dirty_in = h->max_need;  // a workspace of unknown content
     if (pooled) {
-      h->pin = static_cast<unsigned char*>(pinned_get(h->pin_bytes));
-      bool ok = h->pin != nullptr;
+      bool ok = true;
       for (auto& e : h->ev) {
         e = event_get();
         ok = ok && e != nullptr;
       }
+      h->ev_fork = event_get();
+      h->ev_side = event_get();
+      h->side = stream_get();
+      ok = ok && h->ev_fork && h->ev_side && h->side;
       if (!ok) {
         mc_model_free(h);
         return MC_E_DEVICE;
       }
-      blk = h->pin;
-    } else {
-      h->host_stage.assign(h->pin_bytes, 0);
-      blk = h->host_stage.data();
     }
-    h->hctrl = reinterpret_cast<Ctrl*>(blk);
-    h->hpoll = reinterpret_cast<uint32_t*>(blk + 256);
-    // the stop request is a word the kernels read at system scope: pinned memory only
-    h->habort = pooled ? reinterpret_cast<unsigned int*>(blk + 256 + 128) : nullptr;
-    if (h->habort) __atomic_store_n(h->habort, 0u, __ATOMIC_RELEASE);
-    h->hmd = reinterpret_cast<ModelDev*>(blk + 512);
-    h->tc_host = reinterpret_cast<uint32_t*>(blk + tc_off);
-    for (uint32_t c = 0; c < h->mh.n_cfg; ++c) h->tc_host[c] = kNoClock;
-    const void* up_cfg = h->mh.cfgs.data();
-    const void* up_part = parts.data();
-    if (stage) {
-      std::memcpy(blk + up_off, up_cfg, cfg_bytes);
-      std::memcpy(blk + up_off + cfg_bytes, up_part, part_bytes);
-      up_cfg = blk + up_off;
-      up_part = blk + up_off + cfg_bytes;
-    }
-    hipStream_t s = h->stream;
-    if (hipMemcpyAsync(h->cfgs, up_cfg, cfg_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(h->parts, up_part, part_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      (void)hipGetLastError();
+    rc = install(h, L);
+    if (rc) {
       mc_model_free(h);
-      return MC_E_DEVICE;
+      return rc;
     }
-    h->dirty = true;
     *out = h;
     return MC_OK;
   } catch (const std::bad_alloc&) {
@@ -757,6 +895,33 @@ int mc_model_load(const mc_desc* d, const mc_opts* o, void* dev_ws, size_t ws_by
                   mc_model** out) {
   return bind_model(d, o, dev_ws, ws_bytes, stream, true, out);
 }
+
+int mc_model_reload(mc_model* h, const mc_desc* d) {
+  if (!h || !d) return MC_E_INVAL;
+  try {
+    Loaded L;
+    const int rc = prepare_load(d, h->opts_in, h->ws_bytes, &L);
+    if (rc) return rc;  // the handle keeps its model
+    // the new model's tables go past its visited set: where the side stream is still
+    // clearing bytes there, the uploads wait for it (its own queries wait anyway)
+    if (h->side_pending && h->side_hi > L.plan.table + L.plan.table_bytes &&
+        join_side(h) != hipSuccess) {
+      (void)hipGetLastError();
+      return MC_E_DEVICE;
+    }
+    // the table's cleared bytes carry over as far as the new model's need reaches into the
+    // old one's; past that lay the old model's links and tables: dirty
+    const uint64_t need = max_need_of(L);
+    h->dirty_in = need <= h->max_need ? std::min<uint64_t>(h->dirty_in, need) : need;
+    h->max_need = need;
+    return install(h, L);
+  } catch (const std::bad_alloc&) {
+    return MC_E_NOMEM;
+  } catch (...) {
+    return MC_E_INVAL;
+  }
+}
+
 
 int mc_model_info_get(const mc_model* h, mc_model_info* info) {
   if (!h || !info) return MC_E_INVAL;
@@ -966,7 +1131,8 @@ int mc_swarm(mc_model* h, const mc_swarm_opts* o, mc_swarm_result* r) {
   if (p.total > h->plan.table_bytes) return MC_E_NOMEM;
   hipStream_t s = h->stream;
   // the region is no longer a visited set
-  h->dirty = true;
+  HIPCHK(join_side(h));
+  h->dirty_in = std::max<uint64_t>(h->dirty_in, std::min<uint64_t>(p.total, h->max_need));
   h->trace_ready = false;
   h->last = kQueryNone;
   h->swarm_members = 0;
@@ -1070,7 +1236,9 @@ int mc_swarm_trace(mc_model* h, uint32_t* rows, size_t cap, size_t* len) {
   const SwarmPlan p = swarm_plan(h, o.members, o.bits_log2);
   const SwarmArgs a = swarm_args(h, o, p);
   uint32_t* drows = reinterpret_cast<uint32_t*>(h->table + p.rows);
-  h->dirty = true;  // the rows overwrite the visited-set region
+  HIPCHK(join_side(h));  // the rows overwrite the visited-set region
+  const uint64_t rows_end = p.rows + 4ull * (3 + h->mh.m) * h->plan.trace_cap;
+  h->dirty_in = std::max<uint64_t>(h->dirty_in, std::min<uint64_t>(rows_end, h->max_need));
   h->trace_ready = false;
   h->last = kQueryNone;
   HIPCHK(hipMemsetAsync(&h->ctrl->error, 0, 4, s));

@@ -12,6 +12,7 @@ namespace {
 std::mutex g_mu;
 std::map<std::pair<int, size_t>, std::vector<void*>> g_blocks;  // (device, class) -> free
 std::map<int, std::vector<hipEvent_t>> g_events;                 // device -> free
+std::map<int, std::vector<hipStream_t>> g_streams;               // device -> free
 
 size_t size_class(size_t bytes) {
   size_t c = 4096;
@@ -79,6 +80,31 @@ void event_put(hipEvent_t e) {
   if (!e) return;
   std::lock_guard<std::mutex> lk(g_mu);
   g_events[device()].push_back(e);
+}
+
+hipStream_t stream_get() {
+  const int d = device();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto& v = g_streams[d];
+    if (!v.empty()) {
+      hipStream_t s = v.back();
+      v.pop_back();
+      return s;
+    }
+  }
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return s;
+}
+
+void stream_put(hipStream_t s) {
+  if (!s) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_streams[device()].push_back(s);
 }
 
 }  // namespace mc
