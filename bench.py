@@ -216,9 +216,9 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
     b.close()
     del ws
     torch.cuda.empty_cache()
-    # one at a time on a sample: a load per instance into one preallocated workspace, with
-    # the library's automatic launch options and with the batch's autotuned ones; the faster
-    # of the two is the baseline
+    # one at a time on a sample: each instance loaded into one handle over a preallocated
+    # workspace (mc_model_reload), with the library's automatic launch options and with the
+    # batch's autotuned ones; the faster of the two is the baseline
     idx = list(range(0, n_inst, max(1, n_inst // sample_alone)))[:sample_alone]
     variants = {
         "automatic": {},
@@ -230,19 +230,18 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
         mo = mc.make_opts(**opts)
         ws1 = torch.empty(max(mc.mc_workspace_bytes(models[i], mo) for i in idx),
                           dtype=torch.uint8, device="cuda:0")
-        g = mc.Model(models[idx[0]], workspace=ws1, **opts)  # warm
+        g = mc.Model(models[idx[0]], workspace=ws1, **opts)  # warm; kept for every instance
         g.mc_min_time()
-        g.close()
         torch.cuda.synchronize()
         t_alone, s_alone = 0.0, 0
         for i in idx:
             t1 = time.perf_counter()
-            g = mc.Model(models[i], workspace=ws1, **opts)
+            g.mc_model_reload(models[i])
             tm, _ = g.mc_min_time()
             s_alone += g.last_stats["states"]
-            g.close()
             t_alone += time.perf_counter() - t1
             assert tm == t_min[i]
+        g.close()
         del ws1
         torch.cuda.empty_cache()
         alone[name] = {"value": s_alone / t_alone, "queries_per_s": len(idx) / t_alone}
@@ -257,7 +256,8 @@ def batched_leg(mc, torch, workloads, n_inst: int, reps: int, sample_alone: int)
             "one_at_a_time": {"sample": len(idx), "value": alone[base]["value"],
                               "queries_per_s": alone[base]["queries_per_s"],
                               "options": base, "variants": alone,
-                              "how": "preallocated workspace; the faster of the automatic "
+                              "how": "one handle over a preallocated workspace, each "
+                                     "instance reloaded into it; the faster of the automatic "
                                      "and the batch's autotuned launch options"},
             "speedup_vs_one_at_a_time": (total / el) / alone[base]["value"]}
 
@@ -412,8 +412,9 @@ def bb_leg(mc, torch, workloads, names, reps: int = 5):
 def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int = 32):
     """Poisson arrivals of check(T)/min_time queries over a pool of models: the
     continuous-batching engine against FIFO one-query-at-a-time service, both run in
-    real time under the same arrival stream.  FIFO service loads each query's model
-    into one preallocated workspace with the library's automatic launch options."""
+    real time under the same arrival stream.  FIFO service loads each query's model into
+    one handle over a preallocated workspace (mc_model_reload) with the library's
+    automatic launch options."""
     pool, rejected = workloads.draw_batch(
         4, pool_size, lambda x: (mc.state_count(x) or BATCH_BUDGET + 1) <= BATCH_BUDGET)
     mix = workloads.query_mix(4, n_queries, pool_size)
@@ -426,13 +427,14 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
         g.close()
     qs = [(i, kind, int(u * tmins[i])) for i, kind, u in mix]
 
+    fifo = mc.Model(pool[0], workspace=ws)  # the FIFO server's one handle
+
     def serve_one(i, kind, T):
-        g = mc.Model(pool[i], workspace=ws)
+        fifo.mc_model_reload(pool[i])
         if kind == "min_time":
-            g.mc_min_time()
+            fifo.mc_min_time()
         else:
-            g.mc_check(T)
-        g.close()
+            fifo.mc_check(T)
 
     # FIFO capacity: every query of the stream served back to back
     torch.cuda.synchronize()
@@ -480,6 +482,7 @@ def served_leg(mc, torch, workloads, n_queries: int, qps_factors, pool_size: int
             else:
                 run.update(r_)
         out["runs"].append(run)
+    fifo.close()
     del ws
     torch.cuda.empty_cache()
     return out
