@@ -13,6 +13,8 @@
 #include "mc_model.h"
 
 #include <algorithm>
+#include <map>
+#include <array>
 #include <numeric>
 #include <atomic>
 #include <cstring>
@@ -418,6 +420,7 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   h->general = false;
   h->cfg_states.assign(d->n_cfg, 0);
   h->cut_cands.clear();
+  h->cut_of.clear();
   const uint32_t m = h->m;
   uint64_t total = 1, depth = 0, fb = d->n_cfg;
   uint64_t widest_sum = 0;
@@ -491,16 +494,41 @@ int build_model(const mc_desc* d, ModelHost* h, std::string* err) {
   }
   if (h->hetero) {
     h->cut_cands.assign(d->n_cfg, {});
+    h->cut_of.assign(d->n_cfg, 0u);
+    // configurations whose workgroups have the same count and operation ends (the same
+    // record but for its terminal clock) walk alike: each distinct one is walked once, and
+    // the others take its sizes and share its cut points
+    std::vector<uint32_t> walked;
+    {
+      std::map<std::array<uint32_t, sizeof(CfgRec) / 4>, uint32_t> first;
+      for (uint32_t c = 0; c < d->n_cfg; ++c) {
+        CfgRec k = h->cfgs[c];
+        k.tc = 0;
+        std::array<uint32_t, sizeof(CfgRec) / 4> key;
+        std::memcpy(key.data(), &k, sizeof(CfgRec));
+        const auto ins = first.emplace(key, c);
+        h->cut_of[c] = ins.first->second;
+        if (ins.second) walked.push_back(c);
+      }
+    }
     // the walks are independent: long ones share the host's cores
-    const auto walk = [&](uint32_t c) {
+    const auto walk = [&](uint32_t i) {
+      const uint32_t c = walked[i];
       const ChainCount cc = walk_unequal(h->cfgs[c], h->speed, m, ~0ull, &h->cut_cands[c]);
       c_tc[c] = cc.max_clock;  // the latest terminal clock of this configuration
       h->cfg_states[c] = cc.states;
       c_depth[c] = 1 + cc.depth;
     };
+    const uint32_t nw = (uint32_t)walked.size();
     const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const uint32_t nt = walk_work < (1ull << 17) ? 1u : std::min<uint32_t>({hw, 16u, d->n_cfg});
-    WalkPool::get().run(d->n_cfg, nt, walk);
+    const uint32_t nt = walk_work < (1ull << 17) ? 1u : std::min<uint32_t>({hw, 16u, nw});
+    WalkPool::get().run(nw, nt, walk);
+    for (uint32_t c = 0; c < d->n_cfg; ++c) {
+      const uint32_t w = h->cut_of[c];
+      c_tc[c] = c_tc[w];
+      h->cfg_states[c] = h->cfg_states[w];
+      c_depth[c] = c_depth[w];
+    }
   }
   for (uint32_t c = 0; c < d->n_cfg; ++c) {
     if (c_tc[c] >= 0xFFFFFFFFull) return fail(err, "terminal clock exceeds 32 bits");
@@ -580,7 +608,8 @@ void plan_parts(const ModelHost& h, uint64_t target, std::vector<PartPlan>* out,
     const CfgRec& r = h.cfgs[c];
     if (chains) {
       std::vector<ChainCut> cuts;
-      if (h.cfg_states[c] >= 2 * chain_target) chain_cuts(h.cut_cands[c], chain_target, &cuts);
+      if (h.cfg_states[c] >= 2 * chain_target)
+        chain_cuts(h.cut_cands[h.cut_of[c]], chain_target, &cuts);
       if (cuts.empty()) {
         out->push_back(PartPlan{c, 0u, kRoundsToEnd, h.cfg_states[c]});
         continue;

@@ -101,7 +101,11 @@ struct ModelHost {
   uint32_t max_clock = 0;
   uint32_t max_n = 0, max_d = 0;
   std::vector<uint64_t> cfg_states;  // reachable states per configuration subgraph
-  std::vector<std::vector<ChainCut>> cut_cands;  // unequal units: cut points per configuration
+  // unequal units: cut points per configuration walked; configuration c uses those of
+  // cut_of[c] (the first configuration whose record, but for its terminal clock, equals its
+  // own: their walks are the same)
+  std::vector<std::vector<ChainCut>> cut_cands;
+  std::vector<uint32_t> cut_of;
   uint64_t frontier_bound = 0;   // widest BFS level
 };
 

@@ -105,8 +105,9 @@ static void exercise(const mc_desc& d, bool valid) {
   if (h.hetero) {
     for (uint32_t c = 0; c < h.n_cfg; ++c) {
       std::vector<ChainCut> cuts;
-      chain_cuts(h.cut_cands[c], 64, &cuts);
-      expect(h.cut_cands[c].size() <= kMaxCuts, "cut points bounded");
+      chain_cuts(h.cut_cands[h.cut_of[c]], 64, &cuts);
+      expect(h.cut_cands[h.cut_of[c]].size() <= kMaxCuts, "cut points bounded");
+      expect(h.cut_of[c] <= c && h.cut_of[h.cut_of[c]] == h.cut_of[c], "cut points shared");
       for (size_t k = 1; k < cuts.size(); ++k)
         expect(cuts[k].t > cuts[k - 1].t && cuts[k].depth > cuts[k - 1].depth &&
                    cuts[k].states >= cuts[k - 1].states + 64,
