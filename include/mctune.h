@@ -220,9 +220,10 @@ int mc_config_ends(const mc_desc *d, uint32_t cfg, uint32_t *n, uint32_t *b, uin
  * hipStream_t (NULL = default stream).  The library owns *out.
  * Every call on the handle is ordered on that stream.  Besides it the handle holds a side
  * stream of its own: a query that needs less of the visited set than earlier queries
- * wrote clears the bytes past its own there, while it runs, so that a later larger
- * query finds them cleared; the handle's stream waits for that clear before it next
- * touches the workspace, and mc_model_free waits for it too.
+ * wrote clears the bytes past its own there, once its results are queued (while the host
+ * reads them and loads the next query), so that a later larger query finds them cleared;
+ * the handle's stream waits for that clear before it next touches the bytes, and
+ * mc_model_free waits for it too.
  * MC_E_NOMEM if ws_bytes < mc_workspace_bytes(); MC_E_DEVICE wraps a HIP error. */
 int mc_model_load(const mc_desc *d, const mc_opts *o, void *dev_ws, size_t ws_bytes,
                   void *stream, mc_model **out);
