@@ -55,37 +55,23 @@ __global__ void k_find(QueryArgs a, Key<W> k) {
 // alike a dispatch leaf links to its closure's root, the inner closure states storing no
 // links: the states between the two are listed by starting the leaf's extra units one at
 // a time in index order.
-constexpr int kChaseE = 4096;     // operation ends of a workgroup the trace keeps in LDS
 constexpr int kChaseCand = 1024;  // candidate ends of one chain the trace merges
-
-// The number of E[0..b) at or below x (E ascending).
-__device__ __forceinline__ uint32_t ends_le_lds(const uint32_t* E, uint32_t b, uint32_t x) {
-  uint32_t lo = 0, cnt = b;
-  while (cnt) {
-    const uint32_t h = cnt >> 1;
-    if (E[lo + h] <= x) {
-      lo += h + 1u;
-      cnt -= h + 1u;
-    } else {
-      cnt = h;
-    }
-  }
-  return lo;
-}
 
 // The states of a chain of units of unequal speed from f (excluded) to x (included): the
 // distinct operation ends of f's busy units up to x's clock, each a state with the same
 // pending count.  Merged wavefront-wide like the exploration lists chains: lane i takes
 // candidate end i (unit u's k-th end after f), which counts where no unit of lower index
 // ends at the same time; its rank among the distinct times is the sum over units of the
-// counted ends before it, from an exclusive prefix sum of the counted flags.  The states
-// go out terminal-first at out[n..n+cnt).  Returns cnt, or 0 when the chain exceeds the LDS
-// tables (the caller follows the parent links instead); sets bad when the merge does not
-// end on x or passes cap.  E holds the configuration's operation ends (b <= kChaseE).
+// counted ends before it, from an exclusive prefix sum of the counted flags.  Operation
+// ends come from the configuration record (end_at, ends_upto), as in the exploration.  The
+// states go out terminal-first at out[n..n+cnt).  Returns cnt, or 0 when the chain has
+// more candidate ends than S holds flags for (the caller follows the parent links
+// instead); sets bad when the merge does not end on x or passes cap.
 template <int W>
-__device__ uint32_t chase_chain(const St& f, const St& x, const Key<W>& xk, const CfgRec& r,
-                                const Layout& L, int m, const uint32_t* E, uint32_t* S,
-                                unsigned long long* out, uint32_t n, uint32_t cap, bool& bad) {
+__device__ __forceinline__ uint32_t chase_chain(const St& f, const St& x, const Key<W>& xk,
+                                                const CfgRec& r, const Layout& L, int m,
+                                                uint32_t* S, unsigned long long* out, uint32_t n,
+                                                uint32_t cap, bool& bad) {
   const uint32_t lane = threadIdx.x;
   uint32_t base[kMaxCU], sp[kMaxCU], k0[kMaxCU], nu[kMaxCU], O[kMaxCU + 1];
   uint32_t C = 0;
@@ -99,34 +85,46 @@ __device__ uint32_t chase_chain(const St& f, const St& x, const Key<W>& xk, cons
     if (u < m && f.rem[u]) {
       sp[u] = L.speed[u];
       // elapsed e < sp*d; the ends after f are sp*E[k] > e, i.e. E[k] > floor(e / sp)
+      // (E: the configuration's operation ends)
       const uint32_t e = sp[u] * r.d - f.rem[u];
       base[u] = f.clock - e;  // the workgroup's start on unit u
-      k0[u] = ends_le_lds(E, r.b, e / sp[u]);
-      const uint32_t hi = ends_le_lds(E, r.b, (x.clock - base[u]) / sp[u]);
+      k0[u] = ends_upto(r, e / sp[u]);
+      const uint32_t hi = ends_upto(r, (x.clock - base[u]) / sp[u]);
       nu[u] = hi > k0[u] ? hi - k0[u] : 0u;
     }
     C += nu[u];
   }
   O[kMaxCU] = C;
   if (C == 0u || C > (uint32_t)kChaseCand) return 0u;
-  const auto cand = [&](uint32_t i, int& u, uint32_t& tau) {
-    u = 0;
-#pragma unroll
-    for (int j = 1; j < kMaxCU; ++j)
-      if (i >= O[j]) u = j;
-    tau = base[u] + sp[u] * E[k0[u] + (i - O[u])];
-  };
+  // candidate i: its unit u (the last whose first candidate index is at most i) and its
+  // time; every per-unit array is read at compile-time indices, so it stays in registers
+#define MC_CHASE_CAND(i, u, tau)                                  \
+  do {                                                            \
+    u = 0;                                                        \
+    uint32_t bu_ = base[0], su_ = sp[0], ku_ = k0[0], ou_ = O[0]; \
+    _Pragma("unroll") for (int j_ = 1; j_ < kMaxCU; ++j_) {       \
+      if ((i) >= O[j_]) {                                         \
+        u = j_;                                                   \
+        bu_ = base[j_];                                           \
+        su_ = sp[j_];                                             \
+        ku_ = k0[j_];                                             \
+        ou_ = O[j_];                                              \
+      }                                                           \
+    }                                                             \
+    tau = bu_ + su_ * end_at(r, ku_ + ((i) - ou_));               \
+  } while (0)
   // counted flags: a time counts on the lowest unit that ends at it
   for (uint32_t i = lane; i < C; i += 64u) {
     int u;
     uint32_t tau;
-    cand(i, u, tau);
+    MC_CHASE_CAND(i, u, tau);
     bool first = true;
-    for (int j = 0; j < u; ++j) {
-      if (!nu[j] || tau < base[j] || (tau - base[j]) % sp[j]) continue;
+#pragma unroll
+    for (int j = 0; j < kMaxCU; ++j) {
+      if (j >= u || !nu[j] || tau < base[j] || (tau - base[j]) % sp[j]) continue;
       const uint32_t xj = (tau - base[j]) / sp[j];
-      const uint32_t idx = ends_le_lds(E, r.b, xj);
-      if (idx > k0[j] && E[idx - 1u] == xj) first = false;
+      const uint32_t idx = ends_upto(r, xj);
+      if (idx > k0[j] && end_at(r, idx - 1u) == xj) first = false;
     }
     S[i] = first ? 1u : 0u;
   }
@@ -161,20 +159,22 @@ __device__ uint32_t chase_chain(const St& f, const St& x, const Key<W>& xk, cons
     if (S[i + 1u] == S[i]) continue;  // not counted
     int u;
     uint32_t tau;
-    cand(i, u, tau);
+    MC_CHASE_CAND(i, u, tau);
     uint32_t rank = 0;
 #pragma unroll
     for (int j = 0; j < kMaxCU; ++j) {
       if (!nu[j]) continue;
       // unit j's ends before tau: E[k] <= floor((tau - 1 - base_j) / sp_j)
-      const uint32_t lt = ends_le_lds(E, r.b, (tau - 1u - base[j]) / sp[j]);
+      const uint32_t lt = ends_upto(r, (tau - 1u - base[j]) / sp[j]);
       uint32_t c = lt > k0[j] ? lt - k0[j] : 0u;
       c = c < nu[j] ? c : nu[j];
       rank += S[O[j] + c] - S[O[j]];
     }
     St y = f;
     y.clock = tau;
-    for (int v = 0; v < m; ++v) {
+#pragma unroll
+    for (int v = 0; v < kMaxCU; ++v) {
+      if (v >= m) continue;
       const uint32_t wend = f.rem[v] ? base[v] + sp[v] * r.d : 0u;
       y.rem[v] = wend > tau ? wend - tau : 0u;
     }
@@ -191,6 +191,7 @@ __device__ uint32_t chase_chain(const St& f, const St& x, const Key<W>& xk, cons
   if (!__any(ends_on_x ? 1 : 0)) bad = true;
   __syncthreads();
   return cnt;
+#undef MC_CHASE_CAND
 }
 
 template <int W>
@@ -199,9 +200,7 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
   const uint32_t lane = threadIdx.x;
   const Layout& L = a.L;
   const int m = L.m;
-  __shared__ uint32_t sE[kChaseE];        // operation ends of the configuration being traced
   __shared__ uint32_t sS[kChaseCand + 1];  // a chain's counted flags and their prefix sums
-  uint32_t e_cfg = 0xFFFFFFFFu;
   uint32_t s = a.ctrl->target_slot;
   uint32_t n = 0;
   bool bad = false;
@@ -222,7 +221,8 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
     if (L.shared_rem) {
       const St xs = decode<W>(k, L, a.cfgs);
       uint32_t rem = 0;
-      for (int u = 0; u < m; ++u) rem = xs.rem[u] ? xs.rem[u] : rem;
+#pragma unroll
+      for (int u = 0; u < kMaxCU; ++u) rem = (u < m && xs.rem[u]) ? xs.rem[u] : rem;
       const uint32_t d = (rem != 0u && xs.cfg < a.n_cfg) ? a.cfgs[xs.cfg].d : 0u;
       inside_run = rem != 0u && rem < d;
       leaf_like = rem != 0u && rem == d;
@@ -236,8 +236,9 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
       const CfgRec r = a.cfgs[x.cfg];
       St leaf = x;
       uint32_t rem = 0;
-      for (int u = 0; u < m; ++u)
-        if (x.rem[u]) {
+#pragma unroll
+      for (int u = 0; u < kMaxCU; ++u)
+        if (u < m && x.rem[u]) {
           rem = x.rem[u];
           leaf.rem[u] = r.d;
         }
@@ -272,27 +273,29 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
             break;
           }
           uint32_t dmask = 0;  // units the closure started
-          for (int u = 0; u < m; ++u)
-            if (root.rem[u] == 0u && x.rem[u] != 0u) dmask |= 1u << u;
+#pragma unroll
+          for (int u = 0; u < kMaxCU; ++u)
+            if (u < m && root.rem[u] == 0u && x.rem[u] != 0u) dmask |= 1u << u;
           if ((uint32_t)__popc(dmask) != gap + 1u) {
             bad = true;
             break;
           }
-          if (lane == 0) {
-            // terminal-first: the state with the first gap units started comes first
-            for (uint32_t i = gap; i >= 1u; --i) {
-              St y = root;
-              uint32_t left = i;
-              for (int u = 0; u < m && left; ++u)
-                if ((dmask >> u) & 1u) {
-                  y.rem[u] = x.rem[u];
-                  --left;
-                }
-              y.pending = root.pending - i;
-              const Key<W> yk = encode<W>(y, L);
+          // terminal-first: lane l lists the state with the first gap - l units started
+          // (gap < m <= 8 states, one per lane)
+          if (lane < gap) {
+            const uint32_t i = gap - lane;
+            St y = root;
+            uint32_t left = i;
 #pragma unroll
-              for (int w = 0; w < W; ++w) out[(unsigned long long)(n + gap - i) * W + w] = yk.w[w];
-            }
+            for (int u = 0; u < kMaxCU; ++u)
+              if (u < m && left && ((dmask >> u) & 1u)) {
+                y.rem[u] = x.rem[u];
+                --left;
+              }
+            y.pending = root.pending - i;
+            const Key<W> yk = encode<W>(y, L);
+#pragma unroll
+            for (int w = 0; w < W; ++w) out[(unsigned long long)(n + lane) * W + w] = yk.w[w];
           }
           n += gap;
         }
@@ -313,18 +316,9 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
         break;
       }
       const CfgRec r = a.cfgs[f.cfg];
-      uint32_t cnt = 0;
-      if (r.b <= (uint32_t)kChaseE) {
-        if (f.cfg != e_cfg) {  // the configuration's operation ends, E[0..b)
-          __syncthreads();
-          for (uint32_t i = lane; i < r.b; i += 64u) sE[i] = end_at(r, i);
-          e_cfg = f.cfg;
-          __syncthreads();
-        }
-        cnt = chase_chain<W>(f, x, k, r, L, m, sE, sS, out, n, cap, bad);
-        if (bad) break;
-      }
-      if (cnt == 0u) {  // too long for the tables: the parent link instead
+      const uint32_t cnt = chase_chain<W>(f, x, k, r, L, m, sS, out, n, cap, bad);
+      if (bad) break;
+      if (cnt == 0u) {  // more candidates than flags: the parent link instead
         if (lane == 0) {
 #pragma unroll
           for (int w = 0; w < W; ++w) out[(unsigned long long)n * W + w] = k.w[w];
@@ -346,13 +340,15 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
     const St x = decode<W>(k, L, a.cfgs);
     const CfgRec r = a.cfgs[leaf.cfg];
     uint32_t busy = 0, lrem = 0;
-    for (int u = 0; u < m; ++u)
-      if (leaf.rem[u]) {
+#pragma unroll
+    for (int u = 0; u < kMaxCU; ++u)
+      if (u < m && leaf.rem[u]) {
         busy |= 1u << u;
         lrem = leaf.rem[u];
       }
     uint32_t xrem = 0;
-    for (int u = 0; u < m; ++u)
+#pragma unroll
+    for (int u = 0; u < kMaxCU; ++u)
       if ((busy >> u) & 1u) xrem = x.rem[u];
     const uint32_t e0 = r.d - lrem, ex = r.d - xrem;
     const uint32_t idx0 = ends_upto(r, e0);
@@ -368,7 +364,8 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
         const uint32_t e = end_at(r, idx0 + pos);
         St y = leaf;
         y.clock = leaf.clock + (e - e0);
-        for (int u = 0; u < m; ++u)
+#pragma unroll
+        for (int u = 0; u < kMaxCU; ++u)
           if ((busy >> u) & 1u) y.rem[u] = r.d - e;
         const Key<W> yk = encode<W>(y, L);
 #pragma unroll

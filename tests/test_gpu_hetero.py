@@ -253,8 +253,8 @@ def test_hetero_long_chain_traces(mc):
     """Counterexamples through long chains of units of unequal speed, replayed through the
     oracle: the trace rebuilds a chain wavefront-wide from the state it starts from (several
     candidate ends per lane at b = 320), and follows parent links one state at a time where
-    a chain has more than 1,024 candidate ends (the tails at b = 640 and 1280) or a
-    workgroup more than 4,096 operation ends (b = 5120)."""
+    a chain has more than 1,024 candidate ends (the tails at b = 640 and 1280, the chains of
+    b = 5120)."""
     for model, b in _long_chain_models():
         _say(f"long chains b={b}: {workloads.describe(model)}")
         assert len(mc.mc_config_ends(model, 0)["E"]) == b
