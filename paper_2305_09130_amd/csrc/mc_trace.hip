@@ -56,10 +56,11 @@ __global__ void k_find(QueryArgs a, Key<W> k) {
 // links: the states between the two are listed by starting the leaf's extra units one at
 // a time in index order.
 constexpr int kChaseCand = 1024;  // candidate ends of one chain the trace merges
+constexpr uint32_t kChaseBlock = 256;  // threads of the trace kernel (four wavefronts)
 
 // The states of a chain of units of unequal speed from f (excluded) to x (included): the
 // distinct operation ends of f's busy units up to x's clock, each a state with the same
-// pending count.  Merged wavefront-wide like the exploration lists chains: lane i takes
+// pending count.  Merged block-wide like the exploration lists chains: thread i takes
 // candidate end i (unit u's k-th end after f), which counts where no unit of lower index
 // ends at the same time; its rank among the distinct times is the sum over units of the
 // counted ends before it, from an exclusive prefix sum of the counted flags.  Operation
@@ -114,7 +115,7 @@ __device__ __forceinline__ uint32_t chase_chain(const St& f, const St& x, const 
     tau = bu_ + su_ * end_at(r, ku_ + ((i) - ou_));               \
   } while (0)
   // counted flags: a time counts on the lowest unit that ends at it
-  for (uint32_t i = lane; i < C; i += 64u) {
+  for (uint32_t i = lane; i < C; i += kChaseBlock) {
     int u;
     uint32_t tau;
     MC_CHASE_CAND(i, u, tau);
@@ -129,15 +130,19 @@ __device__ __forceinline__ uint32_t chase_chain(const St& f, const St& x, const 
     S[i] = first ? 1u : 0u;
   }
   __syncthreads();
-  {  // exclusive prefix sum of the flags in place; S[C] = their total
-    const uint32_t per = (C + 63u) / 64u, lo = lane * per;
-    const uint32_t hi = lo + per < C ? lo + per : C;
+  __shared__ uint32_t on_x;  // some thread listed x as the chain's last state
+  {  // exclusive prefix sum of the flags in place, by the first wavefront; S[C] = their total
+    const bool scan = lane < 64u;
+    const uint32_t per = (C + 63u) / 64u, lo = scan ? lane * per : 0u;
+    const uint32_t hi = scan ? (lo + per < C ? lo + per : C) : 0u;
     uint32_t sum = 0;
     for (uint32_t i = lo; i < hi; ++i) sum += S[i];
     uint32_t incl = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off);
-      if ((int)lane >= off) incl += y;
+    if (scan) {
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if ((int)lane >= off) incl += y;
+      }
     }
     __syncthreads();
     uint32_t run = incl - sum;
@@ -147,6 +152,7 @@ __device__ __forceinline__ uint32_t chase_chain(const St& f, const St& x, const 
       run += v;
     }
     if (lane == 63u) S[C] = incl;
+    if (lane == 0u) on_x = 0u;
   }
   __syncthreads();
   const uint32_t cnt = S[C];
@@ -154,8 +160,7 @@ __device__ __forceinline__ uint32_t chase_chain(const St& f, const St& x, const 
     bad = true;
     return 0u;
   }
-  bool ends_on_x = false;
-  for (uint32_t i = lane; i < C; i += 64u) {
+  for (uint32_t i = lane; i < C; i += kChaseBlock) {
     if (S[i + 1u] == S[i]) continue;  // not counted
     int u;
     uint32_t tau;
@@ -185,17 +190,19 @@ __device__ __forceinline__ uint32_t chase_chain(const St& f, const St& x, const 
       bool same = true;
 #pragma unroll
       for (int w = 0; w < W; ++w) same = same && yk.w[w] == xk.w[w];
-      ends_on_x = same;
+      if (same) on_x = 1u;
     }
   }
-  if (!__any(ends_on_x ? 1 : 0)) bad = true;
   __syncthreads();
+  if (!on_x) bad = true;
+  __syncthreads();  // S and on_x are the next chain's
   return cnt;
 #undef MC_CHASE_CAND
 }
 
 template <int W>
-__global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* out, uint32_t cap) {
+__global__ __launch_bounds__(kChaseBlock) void k_chase(QueryArgs a, unsigned long long* out,
+                                                     uint32_t cap) {
   if (blockIdx.x != 0) return;
   const uint32_t lane = threadIdx.x;
   const Layout& L = a.L;
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(64) void k_chase(QueryArgs a, unsigned long long* o
       bad = true;
       break;
     }
-    for (uint32_t t0 = 0; t0 < cnt; t0 += 64) {
+    for (uint32_t t0 = 0; t0 < cnt; t0 += kChaseBlock) {
       const uint32_t t = t0 + lane;
       if (t < cnt) {
         const uint32_t pos = cnt - 1u - t;  // terminal-first order
@@ -393,7 +400,7 @@ hipError_t launch_find(hipStream_t st, const QueryArgs& q, const unsigned long l
 
 template <int W>
 hipError_t launch_chase(hipStream_t st, const QueryArgs& q, unsigned long long* out, uint32_t cap) {
-  hipLaunchKernelGGL((k_chase<W>), dim3(1), dim3(64), 0, st, q, out, cap);
+  hipLaunchKernelGGL((k_chase<W>), dim3(1), dim3(kChaseBlock), 0, st, q, out, cap);
   return hipGetLastError();
 }
 
